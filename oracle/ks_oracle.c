@@ -1,0 +1,365 @@
+/*
+ * ks_oracle.c -- plain, slow FP64 CPU oracle for the lattice Boltzmann (LB)
+ * scheme for the Kuramoto-Sivashinsky (KS) equation of Otomo, Boghosian and
+ * Dubois, "Efficient lattice Boltzmann models for the Kuramoto-Sivashinsky
+ * equation" (arXiv:1711.03540).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file exists to check the GPU library.  Only
+ * the test suite, the package smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no source, header, table or helper with
+ * the GPU library, and the GPU library never calls it.
+ *
+ * Style: every quantity is computed the way the paper writes it, in double
+ * precision, with plain loops and no blocking, fusion or reordering.  The
+ * build uses -O2 -ffp-contract=off so no multiply-add is fused.
+ *
+ * Conventions (readings of the paper, each listed in the design notes):
+ *   - velocity order i = 0..Q-1 is c = (0, +1, -1, +2, -2[, +3, -3]);
+ *   - in the appendix's "{a, +-b, -+c}" notation the upper sign belongs to the
+ *     positive velocity;
+ *   - the D1Q7 scheme uses the D1Q5 weights w(0), w(1), w(2), w(4) padded with
+ *     zeros at c = +-3, plus the D1Q7 weight w(6) (section 2.3 names both
+ *     appendix equations for D1Q7);
+ *   - populations start at equilibrium, f_i(x,0) = feq_i(rho0(x));
+ *   - the state handed between steps is the pre-collision f of Eq. (2), and the
+ *     step is collide-then-push exactly in the order Eq. (2) is written.
+ *
+ * Parity pins live in tests/test_oracle_pins.py.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Lattice (appendix A: D1Q5 has c = 0, +-1, +-2; D1Q7 adds +-3).           */
+/* ------------------------------------------------------------------------ */
+
+static const int KO_C[7] = {0, +1, -1, +2, -2, +3, -3};
+
+int ko_velocities(int q, int *c)
+{
+    if (q != 5 && q != 7) return -1;
+    for (int i = 0; i < q; i++) c[i] = KO_C[i];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Weights, appendix A, Eqs. (weight_D1Q5) and (weight_D1Q7), typed in as   */
+/* the rationals the paper prints.  Row l holds w(l)_i in velocity order.   */
+/* Rows 0..4 come from the D1Q5 table (zero at c = +-3); rows 5 and 6 from  */
+/* the D1Q7 table.                                                          */
+/* ------------------------------------------------------------------------ */
+
+int ko_weights(double w[7][7])
+{
+    memset(w, 0, sizeof(double) * 49);
+    /* w(0) = {1, 0, 0} */
+    w[0][0] = 1.0;
+    /* w(1) = {0, +-2/3, -+1/12} */
+    w[1][1] = 2.0 / 3.0;   w[1][2] = -2.0 / 3.0;
+    w[1][3] = -1.0 / 12.0; w[1][4] = 1.0 / 12.0;
+    /* w(2) = {-5/4, 2/3, -1/24} */
+    w[2][0] = -5.0 / 4.0;
+    w[2][1] = 2.0 / 3.0;   w[2][2] = 2.0 / 3.0;
+    w[2][3] = -1.0 / 24.0; w[2][4] = -1.0 / 24.0;
+    /* w(3) = {0, -+1/6, +-1/12} */
+    w[3][1] = -1.0 / 6.0;  w[3][2] = 1.0 / 6.0;
+    w[3][3] = 1.0 / 12.0;  w[3][4] = -1.0 / 12.0;
+    /* w(4) = {1/4, -1/6, 1/24} */
+    w[4][0] = 1.0 / 4.0;
+    w[4][1] = -1.0 / 6.0;  w[4][2] = -1.0 / 6.0;
+    w[4][3] = 1.0 / 24.0;  w[4][4] = 1.0 / 24.0;
+    /* w(5) = {0, +-1/48, -+1/60, +-1/240}   (D1Q7) */
+    w[5][1] = 1.0 / 48.0;  w[5][2] = -1.0 / 48.0;
+    w[5][3] = -1.0 / 60.0; w[5][4] = 1.0 / 60.0;
+    w[5][5] = 1.0 / 240.0; w[5][6] = -1.0 / 240.0;
+    /* w(6) = {-1/36, 1/48, -1/120, 1/720}   (D1Q7) */
+    w[6][0] = -1.0 / 36.0;
+    w[6][1] = 1.0 / 48.0;   w[6][2] = 1.0 / 48.0;
+    w[6][3] = -1.0 / 120.0; w[6][4] = -1.0 / 120.0;
+    w[6][5] = 1.0 / 720.0;  w[6][6] = 1.0 / 720.0;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* T_i, section 2, Eq. (T_form): closed forms valid for tau > 1/2.          */
+/* ------------------------------------------------------------------------ */
+
+double ko_T(int i, double tau)
+{
+    switch (i) {
+    case 1: return tau - 1.0;
+    case 2: return 2.0 * tau * tau - tau - 1.0;
+    case 3: return 6.0 * tau * tau * tau - 6.0 * tau * tau + tau - 1.0;
+    case 4: return (tau - 1.0) * (24.0 * tau * tau * tau - 12.0 * tau * tau + 2.0 * tau + 1.0);
+    default: return NAN;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coefficients.  alpha = dX, beta = dT (Eq. (scaling)).                    */
+/*   J, K, M             : Table 2.                                         */
+/*   C6 (delta f_eq)     : section 2.2, the w(6) correction (D1Q7 only).    */
+/*   dM                  : Eq. (delta_M) (D1Q7 only).  dm_variant = 0 uses  */
+/*     (T3+1)/(T2+1) in the bracket, the ratio in the fourth-derivative     */
+/*     term of Eq. (KS_trunc2) that dM is introduced to cancel; dm_variant  */
+/*     = 1 uses (T3+1)/(T4+1) exactly as Eq. (delta_M) is printed.  The two */
+/*     agree at tau = 1.                                                    */
+/* out[0..4] = J, K, M, dM, C6.                                             */
+/* ------------------------------------------------------------------------ */
+
+int ko_coefficients(int q, double dX, double dT, double tau, int dm_variant, double *out)
+{
+    if (q != 5 && q != 7) return -1;
+    double alpha = dX, beta = dT;
+    double T1 = ko_T(1, tau), T2 = ko_T(2, tau), T3 = ko_T(3, tau), T4 = ko_T(4, tau);
+    double J = beta / (2.0 * alpha);
+    double K = -2.0 * beta * (T1 + 1.0) / (alpha * alpha * (T2 + 1.0));
+    double M = -24.0 * beta * (T1 + 1.0) / (alpha * alpha * alpha * alpha * (T4 + 1.0));
+    double dM = 0.0, C6 = 0.0;
+    if (q == 7) {
+        double ratio = (dm_variant == 1) ? (T3 + 1.0) / (T4 + 1.0) : (T3 + 1.0) / (T2 + 1.0);
+        dM = -24.0 * beta * beta * (T1 + 1.0) / (alpha * alpha * alpha * alpha * (T4 + 1.0))
+             * ((T2 + 1.0) / (2.0 * (T1 + 1.0)) - ratio);
+        C6 = 120.0 * (T1 + 1.0) * beta / ((T4 + 1.0) * alpha * alpha * alpha * alpha);
+    }
+    out[0] = J; out[1] = K; out[2] = M; out[3] = dM; out[4] = C6;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Minimum stable tau, Eq. (general_tau_formula) with the fits of           */
+/* Eqs. (A_B_fit_D1Q5) and (A_B_fit_D1Q7).                                  */
+/* ------------------------------------------------------------------------ */
+
+double ko_tau_fit(int q, double dX, double dT)
+{
+    double A, B;
+    if (q == 5) { A = 0.103 * pow(dX, -0.381);  B = -13.2 * dX + 6.56; }
+    else if (q == 7) { A = 0.0886 * pow(dX, -0.472); B = -12.5 * dX + 6.64; }
+    else return NAN;
+    double l = log10(dT);
+    if (l >= -B) return A * (l + B) * (l + B) + 1.0;
+    return 1.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Equilibrium, section 2.3: D1Q5 uses Eq. (feq); D1Q7 adds dM to M and    */
+/* the C6 w(6) term.  coef = {J, K, M, dM, C6}.                             */
+/* ------------------------------------------------------------------------ */
+
+static double KO_W[7][7];
+static int KO_W_READY = 0;
+
+void ko_feq(int q, const double *coef, double rho, double *feq)
+{
+    if (!KO_W_READY) { ko_weights(KO_W); KO_W_READY = 1; }
+    double (*w)[7] = KO_W;
+    double J = coef[0], K = coef[1], M = coef[2], dM = coef[3], C6 = coef[4];
+    for (int i = 0; i < q; i++) {
+        double lin;
+        if (q == 5)
+            lin = w[0][i] + K * w[2][i] + M * w[4][i];
+        else
+            lin = w[0][i] + K * w[2][i] + (M + dM) * w[4][i] + C6 * w[6][i];
+        feq[i] = rho * lin + rho * rho * J * w[1][i];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One LB step on a periodic lattice, Eq. (2): at every site take           */
+/* rho = sum_i f_i, collide f_i - (f_i - feq_i)/tau, and move the result    */
+/* to site x + c_i (index wrapped modulo n).  f and fnew are Q x n,         */
+/* population-major.                                                        */
+/* ------------------------------------------------------------------------ */
+
+static long ko_wrap(long j, long n)
+{
+    long r = j % n;
+    return r < 0 ? r + n : r;
+}
+
+static void ko_step_periodic(int q, long n, const double *coef, double tau,
+                             const double *f, double *fnew)
+{
+    double feq[7], fi[7];
+    for (long x = 0; x < n; x++) {
+        double rho = 0.0;
+        for (int i = 0; i < q; i++) { fi[i] = f[(long)i * n + x]; rho += fi[i]; }
+        ko_feq(q, coef, rho, feq);
+        for (int i = 0; i < q; i++) {
+            double post = fi[i] - (fi[i] - feq[i]) / tau;
+            fnew[(long)i * n + ko_wrap(x + KO_C[i], n)] = post;
+        }
+    }
+}
+
+/* Collision only (no streaming): the post-collision populations of f. */
+int ko_collide(int q, long n, const double *coef, double tau, const double *f, double *post)
+{
+    double feq[7];
+    for (long x = 0; x < n; x++) {
+        double rho = 0.0;
+        for (int i = 0; i < q; i++) rho += f[(long)i * n + x];
+        ko_feq(q, coef, rho, feq);
+        for (int i = 0; i < q; i++) {
+            double fi = f[(long)i * n + x];
+            post[(long)i * n + x] = fi - (fi - feq[i]) / tau;
+        }
+    }
+    return 0;
+}
+
+/* Density of each site, rho = sum_i f_i (section 2, under Eq. (feq)). */
+int ko_density(int q, long n, const double *f, double *rho)
+{
+    for (long x = 0; x < n; x++) {
+        double s = 0.0;
+        for (int i = 0; i < q; i++) s += f[(long)i * n + x];
+        rho[x] = s;
+    }
+    return 0;
+}
+
+/* Populations at equilibrium with rho0 (the initial state). */
+int ko_init(int q, long n, const double *coef, const double *rho0, double *f)
+{
+    double feq[7];
+    for (long x = 0; x < n; x++) {
+        ko_feq(q, coef, rho0[x], feq);
+        for (int i = 0; i < q; i++) f[(long)i * n + x] = feq[i];
+    }
+    return 0;
+}
+
+/*
+ * Periodic run.  f (Q x n) holds the pre-collision populations at entry and
+ * is advanced in place by nsteps steps.  coef = {J, K, M, dM, C6}.
+ * Returns 0, or -1 on bad arguments / -2 when out of memory.
+ */
+int ko_advance_periodic(int q, long n, const double *coef, double tau, double *f, long nsteps)
+{
+    if ((q != 5 && q != 7) || n <= 0 || nsteps < 0) return -1;
+    double *g = (double *)malloc(sizeof(double) * (size_t)q * (size_t)n);
+    if (!g) return -2;
+    for (long s = 0; s < nsteps; s++) {
+        ko_step_periodic(q, n, coef, tau, f, g);
+        memcpy(f, g, sizeof(double) * (size_t)q * (size_t)n);
+    }
+    free(g);
+    return 0;
+}
+
+/*
+ * Whole periodic solve from rho0: coefficients of the scheme, equilibrium
+ * start, nsteps steps.  Outputs (either may be NULL): rho_out (n) and the
+ * pre-collision populations f_out (Q x n) after the last step.
+ */
+int ko_solve_periodic(int q, long n, double dX, double dT, double tau, int dm_variant,
+                      const double *rho0, long nsteps, double *rho_out, double *f_out)
+{
+    double coef[5];
+    if (ko_coefficients(q, dX, dT, tau, dm_variant, coef)) return -1;
+    double *f = (double *)malloc(sizeof(double) * (size_t)q * (size_t)n);
+    if (!f) return -2;
+    ko_init(q, n, coef, rho0, f);
+    int rc = ko_advance_periodic(q, n, coef, tau, f, nsteps);
+    if (rc == 0) {
+        if (rho_out) ko_density(q, n, f, rho_out);
+        if (f_out) memcpy(f_out, f, sizeof(double) * (size_t)q * (size_t)n);
+    }
+    free(f);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Table 3: the travelling-wave solution and its fixed end values.          */
+/* b = 3, X_m = 0, X_M = 60, X0 = (X_M - X_m)/3, k = sqrt(11/19)/2.        */
+/* ------------------------------------------------------------------------ */
+
+static const double KO_B = 3.0;
+static const double KO_XM = 60.0;
+static const double KO_Xm = 0.0;
+
+double ko_tanh_solution(double X, double t)
+{
+    double k = 0.5 * sqrt(11.0 / 19.0);
+    double X0 = (KO_XM - KO_Xm) / 3.0;
+    double th = tanh(k * (X - KO_B * t - X0));
+    return KO_B + (15.0 / 19.0) * sqrt(11.0 / 19.0) * (-9.0 * th + 11.0 * th * th * th);
+}
+
+double ko_tanh_left(void) { return KO_B - (30.0 / 19.0) * sqrt(11.0 / 19.0); }
+double ko_tanh_right(void) { return 2.0 * KO_B - ko_tanh_left(); }
+
+/*
+ * Fixed-end solve of the Table 3 problem on X in [0, 60]: n = 60/dX + 1
+ * sites X_j = j dX.  The two boundary sites and h = max|c| ghost sites
+ * beyond each end are held at equilibrium with the Table 3 end values
+ * after every streaming (the paper gives only the values; this is the
+ * reading of the boundary condition used here).  Returns rho at all n sites
+ * after nsteps steps, in rho_out.
+ */
+int ko_solve_tanh_fixed(int q, double dX, double dT, double tau, int dm_variant,
+                        long nsteps, double *rho_out, long *n_out)
+{
+    double coef[5];
+    if (ko_coefficients(q, dX, dT, tau, dm_variant, coef)) return -1;
+    long n = lround((KO_XM - KO_Xm) / dX) + 1;
+    int h = (q == 5) ? 2 : 3;
+    long m = n + 2L * h;                      /* extended lattice: ghosts first */
+    double *f = (double *)calloc((size_t)q * (size_t)m, sizeof(double));
+    double *g = (double *)calloc((size_t)q * (size_t)m, sizeof(double));
+    if (!f || !g) { free(f); free(g); return -2; }
+    double feq_l[7], feq_r[7], feq[7];
+    ko_feq(q, coef, ko_tanh_left(), feq_l);
+    ko_feq(q, coef, ko_tanh_right(), feq_r);
+    for (long e = 0; e < m; e++) {
+        long j = e - h;                       /* physical site index */
+        double X = KO_Xm + (double)j * dX;
+        ko_feq(q, coef, ko_tanh_solution(X, 0.0), feq);
+        for (int i = 0; i < q; i++) f[(long)i * m + e] = feq[i];
+    }
+    for (long s = 0; s <= nsteps; s++) {
+        /* hold boundary + ghost sites at the end-value equilibrium */
+        for (int e = 0; e <= h; e++)
+            for (int i = 0; i < q; i++) {
+                f[(long)i * m + e] = feq_l[i];
+                f[(long)i * m + (m - 1 - e)] = feq_r[i];
+            }
+        if (s == nsteps) break;
+        /* collide everywhere, push; values leaving the extended lattice drop */
+        memset(g, 0, sizeof(double) * (size_t)q * (size_t)m);
+        for (long e = 0; e < m; e++) {
+            double rho = 0.0;
+            for (int i = 0; i < q; i++) rho += f[(long)i * m + e];
+            ko_feq(q, coef, rho, feq);
+            for (int i = 0; i < q; i++) {
+                double fi = f[(long)i * m + e];
+                double post = fi - (fi - feq[i]) / tau;
+                long d = e + KO_C[i];
+                if (d >= 0 && d < m) g[(long)i * m + d] = post;
+            }
+        }
+        memcpy(f, g, sizeof(double) * (size_t)q * (size_t)m);
+    }
+    for (long j = 0; j < n; j++) {
+        double r = 0.0;
+        for (int i = 0; i < q; i++) r += f[(long)i * m + (j + h)];
+        rho_out[j] = r;
+    }
+    if (n_out) *n_out = n;
+    free(f); free(g);
+    return 0;
+}
+
+/* Global relative error G of section 3. */
+double ko_global_error(long n, const double *rho_num, const double *rho_ana)
+{
+    double num = 0.0, den = 0.0;
+    for (long j = 0; j < n; j++) {
+        num += fabs(rho_num[j] - rho_ana[j]);
+        den += fabs(rho_ana[j]);
+    }
+    return num / den;
+}

@@ -1,0 +1,248 @@
+/*
+ * kslb.h -- C ABI of the MI355X (gfx950) lattice Boltzmann solver for the
+ * Kuramoto-Sivashinsky equation, after Otomo, Boghosian and Dubois,
+ * "Efficient lattice Boltzmann models for the Kuramoto-Sivashinsky equation"
+ * (arXiv:1711.03540).
+ *
+ * The method (paper section 2): populations f_i on a periodic 1D lattice with
+ * velocities c_i in {0, +-1, +-2} (D1Q5, "basic scheme") or {0, +-1, +-2, +-3}
+ * (D1Q7, "improved scheme") follow the BGK lattice Boltzmann equation, Eq. (2),
+ *     f_i(x + c_i, t + 1) - f_i(x, t) = -(f_i - feq_i) / tau,
+ * with rho = sum_i f_i and the equilibrium of Eq. (3) / section 2.3,
+ *     feq_i = rho (w0_i + K w2_i + M' w4_i + C6 w6_i) + rho^2 J w1_i,
+ * where J, K, M come from Table 2, M' = M + dM (Eq. (delta_M)) and C6 (the
+ * delta f_eq correction of section 2.2) are used by D1Q7 only, and the
+ * weights are those of appendix A.  Physical space and time are X = dX x and
+ * T = dT t (Eq. (scaling)).  All of this folds into two per-velocity vectors,
+ *     feq_i(rho) = E_i rho + G_i rho^2,
+ * with G_i = J w1_i nonzero only for c_i = +-1, +-2.
+ *
+ * Conventions that hold for every entry point:
+ *   - Velocity order i = 0..Q-1 is c = (0, +1, -1, +2, -2[, +3, -3]).
+ *   - Site j sits at X_j = j dX; the lattice is periodic with n_sites sites.
+ *   - Population arrays exchanged with the caller are Q x n_sites doubles,
+ *     population-major (element (i, j) at index i * n_sites + j).
+ *   - The stored state is the post-collision one; the density after n steps
+ *     is rho_j = sum_i f_i(j) of the paper's f at time n.
+ *   - Device memory and HIP streams belong to the caller.  The library never
+ *     frees a caller buffer.  It allocates only small descriptor tables and,
+ *     when a host pointer is passed to a transfer call, one device staging
+ *     buffer of Q * n_sites doubles that lives until destroy.
+ *   - Every function returns a kslb_status (0 = OK, < 0 = error) and never
+ *     aborts or throws; kslb_last_error() describes the last failure of the
+ *     calling thread.  Work enqueued on the stream is asynchronous; a device
+ *     fault surfaces at the next synchronising call.
+ *   - An object is not thread-safe; distinct objects are independent.
+ */
+#ifndef KSLB_H
+#define KSLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kslb_lattice kslb_lattice;
+typedef struct kslb_ensemble kslb_ensemble;
+
+typedef enum {
+    KSLB_OK = 0,
+    KSLB_EINVAL = -1,      /* bad argument or shape */
+    KSLB_ENOMEM = -2,      /* buffer too small or allocation failed */
+    KSLB_EDEVICE = -3,     /* HIP runtime error */
+    KSLB_ESTATE = -4,      /* call out of order (e.g. advance before init) */
+    KSLB_EUNSTABLE = -5,   /* the linear stability guard refused the parameters */
+    KSLB_ENONFINITE = -6   /* a non-finite value was found in the state */
+} kslb_status;
+
+enum { KSLB_D1Q5 = 5, KSLB_D1Q7 = 7 };
+
+/* Storage precision of the populations.
+ *   FP64  : f_i stored and updated in double precision.
+ *   FP32  : f_i stored in single precision; the density sum and the rho^2
+ *           term of the equilibrium in double, the relaxation in single.
+ *   SPLIT : rho stored in double and the non-equilibrium part
+ *           f_i - feq_i(rho) in single; arithmetic in double.  Exact change
+ *           of variables of the FP64 scheme (rounding aside).             */
+enum { KSLB_FP64 = 0, KSLB_FP32 = 1, KSLB_SPLIT = 2 };
+
+/* Reading of the bracket of Eq. (delta_M).  DERIVED uses (T3+1)/(T2+1), the
+ * ratio in the fourth-derivative term of Eq. (KS_trunc2) that dM cancels;
+ * LITERAL uses (T3+1)/(T4+1) as printed.  They coincide at tau = 1.        */
+enum { KSLB_DM_DERIVED = 0, KSLB_DM_LITERAL = 1 };
+
+/* Linear stability guard (see kslb_stability_check). */
+enum { KSLB_GUARD_REFUSE = 0, KSLB_GUARD_RAISE_TAU = 1, KSLB_GUARD_OFF = 2 };
+
+/* Kernel class used by kslb_advance.
+ *   AUTO     : the library's choice (resident ring when the lattice fits one
+ *              workgroup's registers, otherwise temporally blocked tiles).
+ *   PLAIN    : one fused stream+collide step per launch (HBM ping-pong).
+ *   RESIDENT : one workgroup holds the whole lattice in registers for all
+ *              steps; needs n_sites = B * L with B in {4, 8}, L <= 512.
+ *   TILED    : halo-widened tiles, several steps per launch in registers.
+ * All classes give bitwise identical results.                              */
+enum { KSLB_KERNEL_AUTO = 0, KSLB_KERNEL_PLAIN = 1, KSLB_KERNEL_RESIDENT = 2,
+       KSLB_KERNEL_TILED = 3 };
+
+/* ---------------------------------------------------------------------- */
+/* Host-only parameter functions (no device work).                         */
+/* ---------------------------------------------------------------------- */
+
+/* Coefficients of the scheme for q in {5, 7}, alpha = dX > 0, beta = dT > 0,
+ * tau >= 0.92 (M has a pole where T4 + 1 = 0, near tau = 0.908).
+ * jkm[5] receives {J, K, M, dM, C6} (Table 2; Eq. (delta_M); section 2.2;
+ * dM = C6 = 0 for D1Q5).  E[q], G[q] (either may be NULL) receive the folded
+ * equilibrium vectors, feq_i = E_i rho + G_i rho^2.                         */
+kslb_status kslb_scheme_coefficients(int q, double dX, double dT, double tau, int dm_variant,
+                                     double* jkm, double* E, double* G);
+
+/* The paper's fitted minimum stable tau, Eq. (general_tau_formula) with
+ * Eqs. (A_B_fit_D1Q5)/(A_B_fit_D1Q7).  Returns NaN for a bad q or dX <= 0. */
+double kslb_tau_fit(int q, double dX, double dT);
+
+/* Spectral radius of the linearised one-step operator about a uniform
+ * density rho_bar, at lattice wavenumber k (radians per site):
+ *     A(k) = diag(exp(-i k c)) [(1 - omega) I + omega (E + 2 rho_bar G) 1^T].
+ * Host-only.                                                               */
+kslb_status kslb_spectral_radius(int q, const double* E, const double* G, double omega,
+                                 double rho_bar, double k, double* radius);
+
+/* Linear stability guard.  For rho_bar in {0, +rho_max, -rho_max} and 801
+ * wavenumbers k in [0, pi]: radius <= 1 + 1e-13 where k > 1.5 dX (kappa =
+ * k/dX > 1.5, where the KS equation damps), radius <= exp(0.3 dT) elsewhere
+ * (the KS growth rate kappa^2 - kappa^4 never exceeds 1/4).  *stable = 1 if
+ * every check passes.  The paper gives no criterion for its minimum stable
+ * tau (section 3); this is the library's own.                              */
+kslb_status kslb_stability_check(int q, const double* E, const double* G, double omega,
+                                 double dX, double dT, double rho_max, int* stable);
+
+/* ---------------------------------------------------------------------- */
+/* One lattice.                                                            */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of the caller-owned device buffer a lattice needs: two copies of the
+ * state (ping-pong), each rounded up to 256 bytes, plus 4096 bytes of
+ * diagnostics.  0 for bad arguments.                                        */
+size_t kslb_state_bytes(int64_t n_sites, int q, int precision);
+
+/* Create a lattice over the caller's device buffer dev_buf (>= the bytes
+ * above, 256-byte aligned) on the caller's stream (a hipStream_t; NULL =
+ * the null stream).  The device current at this call is the lattice's.   */
+kslb_status kslb_create(kslb_lattice** out, int64_t n_sites, int q, int precision,
+                        void* dev_buf, size_t buf_bytes, void* hip_stream);
+
+/* Set alpha = dX, beta = dT and tau (tau <= 0: the paper's fitted tau),
+ * computing the coefficients and omega = 1/tau, then apply the stability
+ * guard at rho_max (>= 0) under guard_policy.  RAISE_TAU raises tau in steps
+ * of 0.02 (at most 200 steps) until the guard passes.                      */
+kslb_status kslb_set_physical(kslb_lattice* lat, double dX, double dT, double tau,
+                              int dm_variant, int guard_policy, double rho_max);
+
+/* Raw override: E[q], G[q] and omega in (0, 2).  G_i must be 0 for c_i in
+ * {0, +-3} (EINVAL otherwise).  No guard.                                  */
+kslb_status kslb_set_coefficients(kslb_lattice* lat, const double* E, const double* G,
+                                  double omega);
+
+/* Current coefficients; any output may be NULL.  jkm as in
+ * kslb_scheme_coefficients (zeros after a raw override).                   */
+kslb_status kslb_get_coefficients(const kslb_lattice* lat, double* E, double* G, double* omega,
+                                  double* tau, double* jkm);
+
+/* Choose the kernel class and, for TILED, the steps per launch (0 = the
+ * library's default).  RESIDENT/TILED requests that the shape cannot use
+ * return EINVAL.                                                           */
+kslb_status kslb_set_kernel(kslb_lattice* lat, int kernel, int steps_per_launch);
+
+/* f := feq(rho) at every site, step counter := 0.  rho: n_sites doubles on
+ * the device (rho_on_device = 1) or the host.  Host input synchronises.    */
+kslb_status kslb_init_rho(kslb_lattice* lat, const double* rho, int rho_on_device);
+
+/* Enqueue n_steps >= 0 steps of Eq. (2) on the stream (asynchronous).      */
+kslb_status kslb_advance(kslb_lattice* lat, int64_t n_steps);
+
+/* rho_j = sum_i f_i(j) into n_sites doubles (device or host).  Host output
+ * synchronises the stream; device output is enqueued.                      */
+kslb_status kslb_read_rho(kslb_lattice* lat, double* out, int out_on_device);
+
+/* Populations as Q x n_sites doubles.  pre_collision = 0: the stored state
+ * after step n, i.e. the collided populations of Eq. (2)'s right-hand side
+ * at time n.  pre_collision = 1: those populations streamed one lattice
+ * link, S_i(j - c_i), which are the paper's not-yet-collided f_i(x_j) at
+ * time n + 1 (the left-hand side of Eq. (2)).  The pre-collision f at time
+ * n itself is not kept (at tau = 1 it cannot be recovered from the state). */
+kslb_status kslb_read_f(kslb_lattice* lat, double* out, int out_on_device, int pre_collision);
+
+/* Replace the state by Q x n_sites post-collision doubles and set the step
+ * counter.  In FP32/SPLIT the values are rounded to the storage format.     */
+kslb_status kslb_write_f(kslb_lattice* lat, const double* in, int in_on_device, int64_t step);
+
+/* Raw state copy for bitwise checkpoints: state_size bytes (see
+ * kslb_state_size) copied device-to-device on the stream.                  */
+size_t kslb_state_size(const kslb_lattice* lat);
+kslb_status kslb_save_state(kslb_lattice* lat, void* dev_dst);
+kslb_status kslb_load_state(kslb_lattice* lat, const void* dev_src, int64_t step);
+
+kslb_status kslb_step_count(const kslb_lattice* lat, int64_t* step);
+
+/* Diagnostics (synchronises): mass = sum_j rho_j in double, accumulated in a
+ * fixed order; *nonfinite = 1 if any stored value is NaN or infinite.      */
+kslb_status kslb_diagnostics(kslb_lattice* lat, double* mass, int* nonfinite);
+
+kslb_status kslb_destroy(kslb_lattice* lat);
+
+/* ---------------------------------------------------------------------- */
+/* Ensembles: many independent periodic lattices of one scheme, precision  */
+/* and coefficient set, of any sizes, advanced together by one launch per  */
+/* chunk of steps.  Each instance has its own step budget.                 */
+/* ---------------------------------------------------------------------- */
+
+/* Device bytes for instances of the given sizes (ping-pong state of each,
+ * 256-byte aligned, plus diagnostics).                                     */
+size_t kslb_ensemble_bytes(int count, const int64_t* n_sites, int q, int precision);
+
+kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* n_sites, int q,
+                                 int precision, void* dev_buf, size_t buf_bytes, void* hip_stream);
+
+/* Coefficients shared by every instance (as kslb_set_physical). */
+kslb_status kslb_ensemble_set_physical(kslb_ensemble* ens, double dX, double dT, double tau,
+                                       int dm_variant, int guard_policy, double rho_max);
+
+/* Tiling knobs: sites per lane (4 or 8), lanes per workgroup (64..1024,
+ * multiple of 64) and steps per chunk (>= 1); 0 keeps the current value.   */
+kslb_status kslb_ensemble_set_tiling(kslb_ensemble* ens, int sites_per_lane, int lanes,
+                                     int steps_per_chunk);
+
+/* The tau in use (after the fit and the guard). */
+kslb_status kslb_ensemble_get_tau(const kslb_ensemble* ens, double* tau);
+
+/* Reuse instance idx's memory for a lattice of n_sites <= its capacity (the
+ * size given at create).  Its state is dropped; init it again.             */
+kslb_status kslb_ensemble_resize(kslb_ensemble* ens, int idx, int64_t n_sites);
+
+/* Initialise instance idx from its current number of densities (device or
+ * host).                                                                    */
+kslb_status kslb_ensemble_init_rho(kslb_ensemble* ens, int idx, const double* rho, int on_device);
+
+/* Advance instance i by steps[i] >= 0 steps (asynchronous).  Launches one
+ * kernel per chunk; instances with fewer steps left drop out of later
+ * chunks.                                                                  */
+kslb_status kslb_ensemble_advance(kslb_ensemble* ens, const int64_t* steps);
+
+kslb_status kslb_ensemble_read_rho(kslb_ensemble* ens, int idx, double* out, int on_device);
+
+/* Step counter and non-finite flag of instance idx (synchronises). */
+kslb_status kslb_ensemble_status(kslb_ensemble* ens, int idx, int64_t* step, int* nonfinite);
+
+kslb_status kslb_ensemble_destroy(kslb_ensemble* ens);
+
+/* Thread-local description of the last failing call ("" if none). */
+const char* kslb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KSLB_H */

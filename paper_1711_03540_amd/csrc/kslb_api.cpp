@@ -1,0 +1,851 @@
+// kslb_api.cpp -- C ABI of libkslb (see include/kslb.h).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/kslb.h"
+#include "kslb_internal.h"
+
+using namespace kslb;
+
+namespace {
+
+thread_local std::string g_err;
+
+kslb_status fail(kslb_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+kslb_status hip_fail(int e, const char* what)
+{
+    return fail(KSLB_EDEVICE, "%s: %s", what, hipGetErrorString((hipError_t)e));
+}
+
+// Make the object's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+constexpr size_t kDiagBytes = 4096;   // 256 partial sums + mass + flag
+
+bool valid_shape(int64_t n, int q, int prec)
+{
+    return n > 0 && n < (int64_t(1) << 40) && (q == 5 || q == 7) && prec >= 0 && prec <= 2;
+}
+
+int halo(int q) { return q == 5 ? 2 : 3; }
+
+void fold(Coef& cf, const double* E, const double* G, double omega, int q)
+{
+    std::memset(&cf, 0, sizeof cf);
+    for (int i = 0; i < q; i++) {
+        cf.E[i] = E[i];
+        cf.G[i] = G[i];
+        cf.A[i] = omega * E[i];
+        cf.B[i] = omega * G[i];
+    }
+    cf.a1mw = 1.0 - omega;
+    cf.a1mw_f = (float)cf.a1mw;
+}
+
+// Coefficients + tau policy shared by lattices and ensembles.
+struct Physics {
+    bool set = false;
+    double E[7] = {}, G[7] = {}, jkm[5] = {};
+    double tau = 0.0, omega = 0.0;
+    Coef cf{};
+};
+
+kslb_status set_physics(Physics& ph, int q, double dX, double dT, double tau, int dm_variant,
+                        int guard_policy, double rho_max)
+{
+    if (!(dX > 0.0) || !(dT > 0.0) || !std::isfinite(dX) || !std::isfinite(dT))
+        return fail(KSLB_EINVAL, "dX and dT must be positive and finite");
+    if (dm_variant != KSLB_DM_DERIVED && dm_variant != KSLB_DM_LITERAL)
+        return fail(KSLB_EINVAL, "bad dm_variant %d", dm_variant);
+    if (guard_policy < KSLB_GUARD_REFUSE || guard_policy > KSLB_GUARD_OFF)
+        return fail(KSLB_EINVAL, "bad guard_policy %d", guard_policy);
+    if (!(rho_max >= 0.0) || !std::isfinite(rho_max)) return fail(KSLB_EINVAL, "rho_max must be >= 0");
+    if (tau <= 0.0) tau = tau_fit(q, dX, dT);
+    if (!(tau >= kTauMin) || !std::isfinite(tau))
+        return fail(KSLB_EINVAL, "tau = %g is below %g (M has a pole near 0.908)", tau, kTauMin);
+    double E[7], G[7], jkm[5];
+    for (int tries = 0;; tries++) {
+        if (scheme_coefficients(q, dX, dT, tau, dm_variant, jkm, E, G))
+            return fail(KSLB_EINVAL, "coefficients undefined for these parameters");
+        if (guard_policy == KSLB_GUARD_OFF) break;
+        if (stability_check(q, E, G, 1.0 / tau, dX, dT, rho_max)) break;
+        if (guard_policy == KSLB_GUARD_REFUSE)
+            return fail(KSLB_EUNSTABLE, "linearly unstable at dX=%g dT=%g tau=%.6f (q=%d)", dX, dT, tau, q);
+        if (tries >= 200)
+            return fail(KSLB_EUNSTABLE, "no stable tau found up to %.3f", tau);
+        tau += 0.02;
+    }
+    ph.set = true;
+    std::memcpy(ph.E, E, sizeof E);
+    std::memcpy(ph.G, G, sizeof G);
+    std::memcpy(ph.jkm, jkm, sizeof jkm);
+    ph.tau = tau;
+    ph.omega = 1.0 / tau;
+    fold(ph.cf, E, G, ph.omega, q);
+    return KSLB_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// lattice
+// ============================================================================
+
+struct kslb_lattice {
+    int64_t n = 0;
+    int q = 0, prec = 0, device = 0;
+    char* buf = nullptr;
+    size_t bytes = 0, copy = 0;
+    hipStream_t stream = nullptr;
+    int cur = 0;                       // which ping-pong copy holds the state
+    bool have_state = false;
+    Physics ph;
+    int kernel = KSLB_KERNEL_AUTO;
+    int tile_steps = 0;
+    int64_t step = 0;
+    double* staging = nullptr;         // Q x n doubles, only for host transfers
+
+    char* state() { return buf + (size_t)cur * copy; }
+    char* other() { return buf + (size_t)(1 - cur) * copy; }
+    double* diag() { return reinterpret_cast<double*>(buf + 2 * copy); }
+};
+
+namespace {
+
+kslb_status ensure_staging(kslb_lattice* L)
+{
+    if (L->staging) return KSLB_OK;
+    void* p = nullptr;
+    int e = hipMalloc(&p, sizeof(double) * (size_t)L->q * (size_t)L->n);
+    if (e) return fail(KSLB_ENOMEM, "staging allocation of %zu bytes failed",
+                       sizeof(double) * (size_t)L->q * (size_t)L->n);
+    L->staging = (double*)p;
+    return KSLB_OK;
+}
+
+// ring kernel: B in {8, 4} dividing n, lanes <= 512 and exchange area in LDS
+int ring_sites_per_lane(int64_t n, int q)
+{
+    const int Bs[2] = {8, 4};
+    for (int B : Bs) {
+        if (n % B) continue;
+        const int64_t L = n / B;
+        if (L < 1 || L > 512) continue;
+        const int lanes = (int)((L + 63) / 64) * 64;
+        if (ring_lds_bytes(q, lanes) > max_lds_bytes()) continue;
+        return B;
+    }
+    return 0;
+}
+
+constexpr int kTileLanes = 256;
+constexpr int kTileB = 8;
+
+int default_tile_steps(int64_t n, int q)
+{
+    // keep halo overhead modest: 2 H s <= W / 8
+    const int W = kTileLanes * kTileB;
+    int s = W / (16 * halo(q));
+    (void)n;
+    return std::max(1, s);
+}
+
+kslb_status check_lat(const kslb_lattice* L)
+{
+    if (!L) return fail(KSLB_EINVAL, "null lattice");
+    return KSLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kslb_status kslb_scheme_coefficients(int q, double dX, double dT, double tau, int dm_variant,
+                                     double* jkm, double* E, double* G)
+{
+    if (!jkm) return fail(KSLB_EINVAL, "jkm must not be NULL");
+    if (scheme_coefficients(q, dX, dT, tau, dm_variant, jkm, E, G))
+        return fail(KSLB_EINVAL, "bad scheme parameters (q=%d dX=%g dT=%g tau=%g)", q, dX, dT, tau);
+    return KSLB_OK;
+}
+
+double kslb_tau_fit(int q, double dX, double dT) { return tau_fit(q, dX, dT); }
+
+kslb_status kslb_spectral_radius(int q, const double* E, const double* G, double omega, double rho_bar,
+                                 double k, double* radius)
+{
+    if ((q != 5 && q != 7) || !E || !G || !radius) return fail(KSLB_EINVAL, "bad arguments");
+    *radius = spectral_radius(q, E, G, omega, rho_bar, k);
+    return KSLB_OK;
+}
+
+kslb_status kslb_stability_check(int q, const double* E, const double* G, double omega, double dX,
+                                 double dT, double rho_max, int* stable)
+{
+    if ((q != 5 && q != 7) || !E || !G || !stable || !(dX > 0) || !(dT > 0))
+        return fail(KSLB_EINVAL, "bad arguments");
+    *stable = stability_check(q, E, G, omega, dX, dT, rho_max);
+    return KSLB_OK;
+}
+
+size_t kslb_state_bytes(int64_t n_sites, int q, int precision)
+{
+    if (!valid_shape(n_sites, q, precision)) return 0;
+    return 2 * state_copy_bytes(n_sites, q, precision) + kDiagBytes;
+}
+
+kslb_status kslb_create(kslb_lattice** out, int64_t n_sites, int q, int precision, void* dev_buf,
+                        size_t buf_bytes, void* hip_stream)
+{
+    if (!out) return fail(KSLB_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!valid_shape(n_sites, q, precision))
+        return fail(KSLB_EINVAL, "bad shape n=%lld q=%d precision=%d", (long long)n_sites, q, precision);
+    if (!dev_buf) return fail(KSLB_EINVAL, "null device buffer");
+    if (reinterpret_cast<uintptr_t>(dev_buf) % 256) return fail(KSLB_EINVAL, "buffer not 256-byte aligned");
+    const size_t need = kslb_state_bytes(n_sites, q, precision);
+    if (buf_bytes < need) return fail(KSLB_ENOMEM, "buffer has %zu bytes, needs %zu", buf_bytes, need);
+    int dev = 0;
+    int e = hipGetDevice(&dev);
+    if (e) return hip_fail(e, "hipGetDevice");
+    kslb_lattice* L = new (std::nothrow) kslb_lattice;
+    if (!L) return fail(KSLB_ENOMEM, "host allocation failed");
+    L->n = n_sites;
+    L->q = q;
+    L->prec = precision;
+    L->device = dev;
+    L->buf = (char*)dev_buf;
+    L->bytes = buf_bytes;
+    L->copy = state_copy_bytes(n_sites, q, precision);
+    L->stream = (hipStream_t)hip_stream;
+    *out = L;
+    return KSLB_OK;
+}
+
+kslb_status kslb_set_physical(kslb_lattice* L, double dX, double dT, double tau, int dm_variant,
+                              int guard_policy, double rho_max)
+{
+    if (auto s = check_lat(L)) return s;
+    Physics ph;
+    kslb_status st = set_physics(ph, L->q, dX, dT, tau, dm_variant, guard_policy, rho_max);
+    if (st) return st;
+    L->ph = ph;
+    return KSLB_OK;
+}
+
+kslb_status kslb_set_coefficients(kslb_lattice* L, const double* E, const double* G, double omega)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!E || !G) return fail(KSLB_EINVAL, "E and G must not be NULL");
+    if (!(omega > 0.0 && omega < 2.0)) return fail(KSLB_EINVAL, "omega must lie in (0, 2)");
+    for (int i = 0; i < L->q; i++) {
+        if (!std::isfinite(E[i]) || !std::isfinite(G[i])) return fail(KSLB_EINVAL, "non-finite coefficient");
+        const bool g_allowed = (i >= 1 && i <= 4);
+        if (!g_allowed && G[i] != 0.0) return fail(KSLB_EINVAL, "G_%d must be 0 (c = 0 or +-3)", i);
+    }
+    Physics ph;
+    ph.set = true;
+    for (int i = 0; i < L->q; i++) { ph.E[i] = E[i]; ph.G[i] = G[i]; }
+    ph.omega = omega;
+    ph.tau = 1.0 / omega;
+    fold(ph.cf, ph.E, ph.G, omega, L->q);
+    L->ph = ph;
+    return KSLB_OK;
+}
+
+kslb_status kslb_get_coefficients(const kslb_lattice* L, double* E, double* G, double* omega, double* tau,
+                                  double* jkm)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!L->ph.set) return fail(KSLB_ESTATE, "coefficients not set");
+    for (int i = 0; i < L->q; i++) {
+        if (E) E[i] = L->ph.E[i];
+        if (G) G[i] = L->ph.G[i];
+    }
+    if (omega) *omega = L->ph.omega;
+    if (tau) *tau = L->ph.tau;
+    if (jkm) std::memcpy(jkm, L->ph.jkm, sizeof L->ph.jkm);
+    return KSLB_OK;
+}
+
+kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
+{
+    if (auto s = check_lat(L)) return s;
+    if (kernel < KSLB_KERNEL_AUTO || kernel > KSLB_KERNEL_TILED) return fail(KSLB_EINVAL, "bad kernel %d", kernel);
+    if (steps_per_launch < 0) return fail(KSLB_EINVAL, "steps_per_launch must be >= 0");
+    if (kernel == KSLB_KERNEL_RESIDENT) {
+        DeviceGuard g(L->device);
+        if (!ring_sites_per_lane(L->n, L->q))
+            return fail(KSLB_EINVAL, "n=%lld cannot use the resident kernel (needs n = B*L, B in {4,8}, L <= 512)",
+                        (long long)L->n);
+    }
+    if (kernel == KSLB_KERNEL_TILED && steps_per_launch > 0) {
+        if (kTileLanes * kTileB - 2 * halo(L->q) * steps_per_launch <= 0)
+            return fail(KSLB_EINVAL, "steps_per_launch %d leaves no valid sites in a tile", steps_per_launch);
+    }
+    L->kernel = kernel;
+    L->tile_steps = steps_per_launch;
+    return KSLB_OK;
+}
+
+kslb_status kslb_init_rho(kslb_lattice* L, const double* rho, int rho_on_device)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!rho) return fail(KSLB_EINVAL, "rho must not be NULL");
+    if (!L->ph.set) return fail(KSLB_ESTATE, "set the coefficients before init_rho");
+    DeviceGuard g(L->device);
+    const double* src = rho;
+    if (!rho_on_device) {
+        if (auto s = ensure_staging(L)) return s;
+        int e = hipMemcpyAsync(L->staging, rho, sizeof(double) * (size_t)L->n, hipMemcpyHostToDevice, L->stream);
+        if (e) return hip_fail(e, "hipMemcpyAsync(rho)");
+        src = L->staging;
+    }
+    L->cur = 0;
+    int e = launch_init(L->q, L->prec, L->state(), L->n, src, L->ph.cf, L->stream);
+    if (e) return hip_fail(e, "init kernel");
+    if (!rho_on_device) {
+        e = hipStreamSynchronize(L->stream);
+        if (e) return hip_fail(e, "hipStreamSynchronize");
+    }
+    L->have_state = true;
+    L->step = 0;
+    return KSLB_OK;
+}
+
+kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
+{
+    if (auto s = check_lat(L)) return s;
+    if (n_steps < 0) return fail(KSLB_EINVAL, "n_steps must be >= 0");
+    if (!L->have_state) return fail(KSLB_ESTATE, "advance before init_rho/write_f");
+    if (n_steps == 0) return KSLB_OK;
+    DeviceGuard g(L->device);
+    int kernel = L->kernel;
+    const int ringB = ring_sites_per_lane(L->n, L->q);
+    if (kernel == KSLB_KERNEL_AUTO) kernel = ringB ? KSLB_KERNEL_RESIDENT : KSLB_KERNEL_TILED;
+    int e = 0;
+    if (kernel == KSLB_KERNEL_PLAIN) {
+        for (int64_t s = 0; s < n_steps; s++) {
+            e = launch_plain(L->q, L->prec, L->state(), L->other(), L->n, L->ph.cf, L->stream);
+            if (e) return hip_fail(e, "plain kernel");
+            L->cur ^= 1;
+        }
+    } else if (kernel == KSLB_KERNEL_RESIDENT) {
+        if (!ringB) return fail(KSLB_EINVAL, "shape cannot use the resident kernel");
+        const int64_t chunk = int64_t(1) << 20;   // bound a single launch
+        for (int64_t done = 0; done < n_steps; done += chunk) {
+            const int64_t s = std::min(chunk, n_steps - done);
+            e = launch_ring(L->q, L->prec, ringB, L->state(), L->other(), L->n, s, L->ph.cf, L->stream);
+            if (e) return hip_fail(e, "resident kernel");
+            L->cur ^= 1;
+        }
+    } else {
+        int s_max = L->tile_steps > 0 ? L->tile_steps : default_tile_steps(L->n, L->q);
+        for (int64_t done = 0; done < n_steps;) {
+            const int s = (int)std::min<int64_t>(s_max, n_steps - done);
+            e = launch_tile(L->q, L->prec, kTileB, kTileLanes, L->state(), L->other(), L->n, s, L->ph.cf,
+                            L->stream);
+            if (e) return hip_fail(e, "tiled kernel");
+            L->cur ^= 1;
+            done += s;
+        }
+    }
+    L->step += n_steps;
+    return KSLB_OK;
+}
+
+kslb_status kslb_read_rho(kslb_lattice* L, double* out, int out_on_device)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!out) return fail(KSLB_EINVAL, "out must not be NULL");
+    if (!L->have_state) return fail(KSLB_ESTATE, "no state");
+    DeviceGuard g(L->device);
+    double* dst = out;
+    if (!out_on_device) {
+        if (auto s = ensure_staging(L)) return s;
+        dst = L->staging;
+    }
+    int e = launch_read_rho(L->q, L->prec, L->state(), L->n, dst, L->stream);
+    if (e) return hip_fail(e, "readout kernel");
+    if (!out_on_device) {
+        e = hipMemcpyAsync(out, dst, sizeof(double) * (size_t)L->n, hipMemcpyDeviceToHost, L->stream);
+        if (e) return hip_fail(e, "hipMemcpyAsync(rho)");
+        e = hipStreamSynchronize(L->stream);
+        if (e) return hip_fail(e, "hipStreamSynchronize");
+    }
+    return KSLB_OK;
+}
+
+kslb_status kslb_read_f(kslb_lattice* L, double* out, int out_on_device, int pre_collision)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!out) return fail(KSLB_EINVAL, "out must not be NULL");
+    if (!L->have_state) return fail(KSLB_ESTATE, "no state");
+    if (!L->ph.set) return fail(KSLB_ESTATE, "coefficients not set");
+    DeviceGuard g(L->device);
+    double* dst = out;
+    if (!out_on_device) {
+        if (auto s = ensure_staging(L)) return s;
+        dst = L->staging;
+    }
+    int e = launch_read_f(L->q, L->prec, L->state(), L->n, dst, pre_collision ? 1 : 0, L->ph.cf, L->stream);
+    if (e) return hip_fail(e, "read_f kernel");
+    if (!out_on_device) {
+        e = hipMemcpyAsync(out, dst, sizeof(double) * (size_t)L->q * (size_t)L->n, hipMemcpyDeviceToHost,
+                           L->stream);
+        if (e) return hip_fail(e, "hipMemcpyAsync(f)");
+        e = hipStreamSynchronize(L->stream);
+        if (e) return hip_fail(e, "hipStreamSynchronize");
+    }
+    return KSLB_OK;
+}
+
+kslb_status kslb_write_f(kslb_lattice* L, const double* in, int in_on_device, int64_t step)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!in) return fail(KSLB_EINVAL, "in must not be NULL");
+    if (!L->ph.set) return fail(KSLB_ESTATE, "coefficients not set");
+    if (step < 0) return fail(KSLB_EINVAL, "step must be >= 0");
+    DeviceGuard g(L->device);
+    const double* src = in;
+    if (!in_on_device) {
+        if (auto s = ensure_staging(L)) return s;
+        int e = hipMemcpyAsync(L->staging, in, sizeof(double) * (size_t)L->q * (size_t)L->n,
+                               hipMemcpyHostToDevice, L->stream);
+        if (e) return hip_fail(e, "hipMemcpyAsync(f)");
+        src = L->staging;
+    }
+    L->cur = 0;
+    int e = launch_write_f(L->q, L->prec, L->state(), L->n, src, L->ph.cf, L->stream);
+    if (e) return hip_fail(e, "write_f kernel");
+    if (!in_on_device) {
+        e = hipStreamSynchronize(L->stream);
+        if (e) return hip_fail(e, "hipStreamSynchronize");
+    }
+    L->have_state = true;
+    L->step = step;
+    return KSLB_OK;
+}
+
+size_t kslb_state_size(const kslb_lattice* L) { return L ? L->copy : 0; }
+
+kslb_status kslb_save_state(kslb_lattice* L, void* dev_dst)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!dev_dst) return fail(KSLB_EINVAL, "null destination");
+    if (!L->have_state) return fail(KSLB_ESTATE, "no state");
+    DeviceGuard g(L->device);
+    int e = hipMemcpyAsync(dev_dst, L->state(), L->copy, hipMemcpyDeviceToDevice, L->stream);
+    if (e) return hip_fail(e, "hipMemcpyAsync(save)");
+    return KSLB_OK;
+}
+
+kslb_status kslb_load_state(kslb_lattice* L, const void* dev_src, int64_t step)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!dev_src) return fail(KSLB_EINVAL, "null source");
+    if (step < 0) return fail(KSLB_EINVAL, "step must be >= 0");
+    DeviceGuard g(L->device);
+    L->cur = 0;
+    int e = hipMemcpyAsync(L->state(), dev_src, L->copy, hipMemcpyDeviceToDevice, L->stream);
+    if (e) return hip_fail(e, "hipMemcpyAsync(load)");
+    L->have_state = true;
+    L->step = step;
+    return KSLB_OK;
+}
+
+kslb_status kslb_step_count(const kslb_lattice* L, int64_t* step)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!step) return fail(KSLB_EINVAL, "step must not be NULL");
+    *step = L->step;
+    return KSLB_OK;
+}
+
+kslb_status kslb_diagnostics(kslb_lattice* L, double* mass, int* nonfinite)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!L->have_state) return fail(KSLB_ESTATE, "no state");
+    DeviceGuard g(L->device);
+    double* partial = L->diag();
+    double* mass_d = partial + 256;
+    int* flag_d = reinterpret_cast<int*>(partial + 257);
+    int e = launch_diag(L->q, L->prec, L->state(), L->n, partial, flag_d, mass_d, L->stream);
+    if (e) return hip_fail(e, "diagnostics kernel");
+    double m = 0.0;
+    int f = 0;
+    e = hipMemcpyAsync(&m, mass_d, sizeof m, hipMemcpyDeviceToHost, L->stream);
+    if (!e) e = hipMemcpyAsync(&f, flag_d, sizeof f, hipMemcpyDeviceToHost, L->stream);
+    if (!e) e = hipStreamSynchronize(L->stream);
+    if (e) return hip_fail(e, "diagnostics copy");
+    if (mass) *mass = m;
+    if (nonfinite) *nonfinite = f;
+    return KSLB_OK;
+}
+
+kslb_status kslb_destroy(kslb_lattice* L)
+{
+    if (!L) return KSLB_OK;
+    if (L->staging) {
+        DeviceGuard g(L->device);
+        (void)hipStreamSynchronize(L->stream);
+        (void)hipFree(L->staging);
+    }
+    delete L;
+    return KSLB_OK;
+}
+
+const char* kslb_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ============================================================================
+// ensemble
+// ============================================================================
+
+struct kslb_ensemble {
+    int count = 0, q = 0, prec = 0, device = 0;
+    char* buf = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    std::vector<int64_t> cap, n;       // capacity and current size (sites) per instance
+    std::vector<size_t> off, copy;     // byte offset of copy 0, bytes per copy (at capacity)
+    std::vector<int> cur;
+    std::vector<int64_t> step;
+    std::vector<char> have_state;
+    Physics ph;
+    int B = 8, lanes = 256, chunk = 16;
+    size_t diag_off = 0;
+    // descriptor tables: two device slots, remembered host contents
+    WinDesc* d_desc[2] = {nullptr, nullptr};
+    size_t d_cap[2] = {0, 0};
+    std::vector<WinDesc> h_last[2];
+    int next_slot = 0;
+    double* staging = nullptr;
+    int64_t staging_n = 0;
+};
+
+namespace {
+
+size_t ens_layout(int count, const int64_t* n_sites, int q, int prec, std::vector<size_t>* off,
+                  std::vector<size_t>* copy)
+{
+    size_t pos = 0;
+    for (int i = 0; i < count; i++) {
+        const size_t c = state_copy_bytes(n_sites[i], q, prec);
+        if (off) off->push_back(pos);
+        if (copy) copy->push_back(c);
+        pos += 2 * c;
+    }
+    return pos;
+}
+
+kslb_status check_ens(const kslb_ensemble* E, int idx)
+{
+    if (!E) return fail(KSLB_EINVAL, "null ensemble");
+    if (idx < 0 || idx >= E->count) return fail(KSLB_EINVAL, "instance %d out of range [0, %d)", idx, E->count);
+    return KSLB_OK;
+}
+
+kslb_status ens_staging(kslb_ensemble* E, int64_t n)
+{
+    if (E->staging && E->staging_n >= n) return KSLB_OK;
+    if (E->staging) {
+        (void)hipStreamSynchronize(E->stream);
+        (void)hipFree(E->staging);
+        E->staging = nullptr;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(double) * (size_t)n)) return fail(KSLB_ENOMEM, "staging allocation failed");
+    E->staging = (double*)p;
+    E->staging_n = n;
+    return KSLB_OK;
+}
+
+char* ens_state(kslb_ensemble* E, int i) { return E->buf + E->off[i] + (size_t)E->cur[i] * E->copy[i]; }
+
+kslb_status ens_upload(kslb_ensemble* E, const std::vector<WinDesc>& h, WinDesc** dev)
+{
+    // reuse a table whose contents are already on the device
+    for (int k = 0; k < 2; k++) {
+        if (E->d_desc[k] && E->h_last[k].size() == h.size() &&
+            std::memcmp(E->h_last[k].data(), h.data(), h.size() * sizeof(WinDesc)) == 0) {
+            *dev = E->d_desc[k];
+            return KSLB_OK;
+        }
+    }
+    const int k = E->next_slot;
+    E->next_slot ^= 1;
+    if (E->d_cap[k] < h.size()) {
+        if (E->d_desc[k]) {
+            (void)hipStreamSynchronize(E->stream);
+            (void)hipFree(E->d_desc[k]);
+            E->d_desc[k] = nullptr;
+            E->d_cap[k] = 0;
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, h.size() * sizeof(WinDesc))) return fail(KSLB_ENOMEM, "descriptor allocation failed");
+        E->d_desc[k] = (WinDesc*)p;
+        E->d_cap[k] = h.size();
+    }
+    int e = hipMemcpyAsync(E->d_desc[k], h.data(), h.size() * sizeof(WinDesc), hipMemcpyHostToDevice, E->stream);
+    if (e) return hip_fail(e, "descriptor upload");
+    E->h_last[k] = h;
+    *dev = E->d_desc[k];
+    return KSLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t kslb_ensemble_bytes(int count, const int64_t* n_sites, int q, int precision)
+{
+    if (count <= 0 || !n_sites) return 0;
+    for (int i = 0; i < count; i++)
+        if (!valid_shape(n_sites[i], q, precision)) return 0;
+    return ens_layout(count, n_sites, q, precision, nullptr, nullptr) + kDiagBytes;
+}
+
+kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* n_sites, int q, int precision,
+                                 void* dev_buf, size_t buf_bytes, void* hip_stream)
+{
+    if (!out) return fail(KSLB_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (count <= 0 || !n_sites) return fail(KSLB_EINVAL, "count must be > 0 with sizes");
+    for (int i = 0; i < count; i++)
+        if (!valid_shape(n_sites[i], q, precision))
+            return fail(KSLB_EINVAL, "bad shape of instance %d", i);
+    if (!dev_buf || reinterpret_cast<uintptr_t>(dev_buf) % 256)
+        return fail(KSLB_EINVAL, "device buffer missing or not 256-byte aligned");
+    const size_t need = kslb_ensemble_bytes(count, n_sites, q, precision);
+    if (buf_bytes < need) return fail(KSLB_ENOMEM, "buffer has %zu bytes, needs %zu", buf_bytes, need);
+    int dev = 0;
+    int e = hipGetDevice(&dev);
+    if (e) return hip_fail(e, "hipGetDevice");
+    kslb_ensemble* E = new (std::nothrow) kslb_ensemble;
+    if (!E) return fail(KSLB_ENOMEM, "host allocation failed");
+    E->count = count;
+    E->q = q;
+    E->prec = precision;
+    E->device = dev;
+    E->buf = (char*)dev_buf;
+    E->bytes = buf_bytes;
+    E->stream = (hipStream_t)hip_stream;
+    E->cap.assign(n_sites, n_sites + count);
+    E->n = E->cap;
+    E->diag_off = ens_layout(count, n_sites, q, precision, &E->off, &E->copy);
+    E->cur.assign(count, 0);
+    E->step.assign(count, 0);
+    E->have_state.assign(count, 0);
+    *out = E;
+    return KSLB_OK;
+}
+
+kslb_status kslb_ensemble_set_physical(kslb_ensemble* E, double dX, double dT, double tau, int dm_variant,
+                                       int guard_policy, double rho_max)
+{
+    if (!E) return fail(KSLB_EINVAL, "null ensemble");
+    Physics ph;
+    kslb_status st = set_physics(ph, E->q, dX, dT, tau, dm_variant, guard_policy, rho_max);
+    if (st) return st;
+    E->ph = ph;
+    return KSLB_OK;
+}
+
+kslb_status kslb_ensemble_get_tau(const kslb_ensemble* E, double* tau)
+{
+    if (!E || !tau) return fail(KSLB_EINVAL, "bad arguments");
+    if (!E->ph.set) return fail(KSLB_ESTATE, "coefficients not set");
+    *tau = E->ph.tau;
+    return KSLB_OK;
+}
+
+kslb_status kslb_ensemble_set_tiling(kslb_ensemble* E, int sites_per_lane, int lanes, int steps_per_chunk)
+{
+    if (!E) return fail(KSLB_EINVAL, "null ensemble");
+    int B = sites_per_lane ? sites_per_lane : E->B;
+    int L = lanes ? lanes : E->lanes;
+    int c = steps_per_chunk ? steps_per_chunk : E->chunk;
+    if (B != 4 && B != 8) return fail(KSLB_EINVAL, "sites_per_lane must be 4 or 8");
+    if (L < 64 || L > 256 || L % 64) return fail(KSLB_EINVAL, "lanes must be 64, 128, 192 or 256");
+    if (c < 1 || (int64_t)L * B - 2 * halo(E->q) * (int64_t)c <= 0)
+        return fail(KSLB_EINVAL, "steps_per_chunk %d leaves no valid sites in a %d-site window", c, L * B);
+    E->B = B;
+    E->lanes = L;
+    E->chunk = c;
+    return KSLB_OK;
+}
+
+kslb_status kslb_ensemble_resize(kslb_ensemble* E, int idx, int64_t n_sites)
+{
+    if (auto s = check_ens(E, idx)) return s;
+    if (n_sites <= 0 || n_sites > E->cap[idx])
+        return fail(KSLB_EINVAL, "size %lld exceeds the capacity %lld of instance %d", (long long)n_sites,
+                    (long long)E->cap[idx], idx);
+    E->n[idx] = n_sites;
+    E->have_state[idx] = 0;
+    E->step[idx] = 0;
+    return KSLB_OK;
+}
+
+kslb_status kslb_ensemble_init_rho(kslb_ensemble* E, int idx, const double* rho, int on_device)
+{
+    if (auto s = check_ens(E, idx)) return s;
+    if (!rho) return fail(KSLB_EINVAL, "rho must not be NULL");
+    if (!E->ph.set) return fail(KSLB_ESTATE, "set the coefficients before init_rho");
+    DeviceGuard g(E->device);
+    const double* src = rho;
+    if (!on_device) {
+        if (auto s = ens_staging(E, E->n[idx])) return s;
+        int e = hipMemcpyAsync(E->staging, rho, sizeof(double) * (size_t)E->n[idx], hipMemcpyHostToDevice, E->stream);
+        if (e) return hip_fail(e, "hipMemcpyAsync(rho)");
+        src = E->staging;
+    }
+    E->cur[idx] = 0;
+    int e = launch_init(E->q, E->prec, ens_state(E, idx), E->n[idx], src, E->ph.cf, E->stream);
+    if (e) return hip_fail(e, "init kernel");
+    if (!on_device) {
+        e = hipStreamSynchronize(E->stream);
+        if (e) return hip_fail(e, "hipStreamSynchronize");
+    }
+    E->have_state[idx] = 1;
+    E->step[idx] = 0;
+    return KSLB_OK;
+}
+
+kslb_status kslb_ensemble_advance(kslb_ensemble* E, const int64_t* steps)
+{
+    if (!E) return fail(KSLB_EINVAL, "null ensemble");
+    if (!steps) return fail(KSLB_EINVAL, "steps must not be NULL");
+    for (int i = 0; i < E->count; i++) {
+        if (steps[i] < 0) return fail(KSLB_EINVAL, "negative step count for instance %d", i);
+        if (steps[i] > 0 && !E->have_state[i]) return fail(KSLB_ESTATE, "instance %d has no state", i);
+    }
+    DeviceGuard g(E->device);
+    const int H = halo(E->q);
+    const int64_t W = (int64_t)E->lanes * E->B;
+    std::vector<int64_t> left(steps, steps + E->count);
+    std::vector<WinDesc> h;
+    for (;;) {
+        h.clear();
+        for (int i = 0; i < E->count; i++) {
+            if (left[i] <= 0) continue;
+            const int s = (int)std::min<int64_t>(E->chunk, left[i]);
+            const int64_t T = W - 2 * (int64_t)H * s;
+            const int64_t n = E->n[i];
+            const int64_t src = (int64_t)(E->off[i] + (size_t)E->cur[i] * E->copy[i]);
+            const int64_t dst = (int64_t)(E->off[i] + (size_t)(1 - E->cur[i]) * E->copy[i]);
+            for (int64_t t0 = 0; t0 < n; t0 += T) {
+                WinDesc d;
+                d.src_off = src;
+                d.dst_off = dst;
+                d.n = n;
+                d.start = t0 - (int64_t)H * s;
+                d.steps = s;
+                d.valid = (int32_t)std::min<int64_t>(T, n - t0);
+                d.pad_ = 0;
+                h.push_back(d);
+            }
+        }
+        if (h.empty()) break;
+        WinDesc* dev = nullptr;
+        if (auto s = ens_upload(E, h, &dev)) return s;
+        int e = launch_ens(E->q, E->prec, E->B, E->lanes, E->buf, dev, (int)h.size(), E->ph.cf, E->stream);
+        if (e) return hip_fail(e, "ensemble kernel");
+        for (int i = 0; i < E->count; i++) {
+            if (left[i] <= 0) continue;
+            const int s = (int)std::min<int64_t>(E->chunk, left[i]);
+            left[i] -= s;
+            E->step[i] += s;
+            E->cur[i] ^= 1;
+        }
+    }
+    return KSLB_OK;
+}
+
+kslb_status kslb_ensemble_read_rho(kslb_ensemble* E, int idx, double* out, int on_device)
+{
+    if (auto s = check_ens(E, idx)) return s;
+    if (!out) return fail(KSLB_EINVAL, "out must not be NULL");
+    if (!E->have_state[idx]) return fail(KSLB_ESTATE, "instance %d has no state", idx);
+    DeviceGuard g(E->device);
+    double* dst = out;
+    if (!on_device) {
+        if (auto s = ens_staging(E, E->n[idx])) return s;
+        dst = E->staging;
+    }
+    int e = launch_read_rho(E->q, E->prec, ens_state(E, idx), E->n[idx], dst, E->stream);
+    if (e) return hip_fail(e, "readout kernel");
+    if (!on_device) {
+        e = hipMemcpyAsync(out, dst, sizeof(double) * (size_t)E->n[idx], hipMemcpyDeviceToHost, E->stream);
+        if (!e) e = hipStreamSynchronize(E->stream);
+        if (e) return hip_fail(e, "readout copy");
+    }
+    return KSLB_OK;
+}
+
+kslb_status kslb_ensemble_status(kslb_ensemble* E, int idx, int64_t* step, int* nonfinite)
+{
+    if (auto s = check_ens(E, idx)) return s;
+    if (step) *step = E->step[idx];
+    if (!nonfinite) return KSLB_OK;
+    if (!E->have_state[idx]) { *nonfinite = 0; return KSLB_OK; }
+    DeviceGuard g(E->device);
+    double* partial = reinterpret_cast<double*>(E->buf + E->diag_off);
+    double* mass_d = partial + 256;
+    int* flag_d = reinterpret_cast<int*>(partial + 257);
+    int e = launch_diag(E->q, E->prec, ens_state(E, idx), E->n[idx], partial, flag_d, mass_d, E->stream);
+    if (e) return hip_fail(e, "diagnostics kernel");
+    int f = 0;
+    e = hipMemcpyAsync(&f, flag_d, sizeof f, hipMemcpyDeviceToHost, E->stream);
+    if (!e) e = hipStreamSynchronize(E->stream);
+    if (e) return hip_fail(e, "diagnostics copy");
+    *nonfinite = f;
+    return KSLB_OK;
+}
+
+kslb_status kslb_ensemble_destroy(kslb_ensemble* E)
+{
+    if (!E) return KSLB_OK;
+    DeviceGuard g(E->device);
+    (void)hipStreamSynchronize(E->stream);
+    for (int k = 0; k < 2; k++)
+        if (E->d_desc[k]) (void)hipFree(E->d_desc[k]);
+    if (E->staging) (void)hipFree(E->staging);
+    delete E;
+    return KSLB_OK;
+}
+
+}  // extern "C"

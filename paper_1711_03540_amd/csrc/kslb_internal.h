@@ -1,0 +1,83 @@
+// kslb_internal.h -- declarations shared by the host parameter code, the HIP
+// kernels and the C ABI of libkslb.  Not installed; not part of the ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace kslb {
+
+// tau below this is refused: M of Table 2 has a pole where T4 + 1 = 0
+// (tau = (3 + sqrt 6)/6 ~ 0.908).
+constexpr double kTauMin = 0.92;
+
+enum Precision { kFP64 = 0, kFP32 = 1, kSPLIT = 2 };
+
+// Coefficients handed to every kernel by value.
+//   feq_i(rho) = E_i rho + G_i rho^2        (equilibrium, section 2.3)
+//   A_i = omega E_i,  B_i = omega G_i,  a1mw = 1 - omega
+// so the BGK collision of Eq. (2) is  f'_i = a1mw f_i + A_i rho + B_i rho^2.
+struct Coef {
+    double E[7];
+    double G[7];
+    double A[7];
+    double B[7];
+    double a1mw;
+    float a1mw_f;
+    float pad_;
+};
+
+// host parameter code (kslb_params.cpp)
+void scheme_weights(int q, double w[7][7]);
+int scheme_coefficients(int q, double dX, double dT, double tau, int dm_variant, double jkm[5],
+                        double* E, double* G);
+double tau_fit(int q, double dX, double dT);
+double spectral_radius(int q, const double* E, const double* G, double omega, double rho_bar,
+                       double k);
+int stability_check(int q, const double* E, const double* G, double omega, double dX, double dT,
+                    double rho_max);
+
+// bytes of one copy of the state of n sites
+size_t state_copy_bytes(int64_t n, int q, int prec);
+
+// ---------------------------------------------------------------------------
+// kernel launchers (kslb_kernels.hip).  All return a hipError_t as int.
+// ---------------------------------------------------------------------------
+struct LaunchCtx {
+    void* stream;     // hipStream_t
+};
+
+// max sites per lane, lanes of the ring kernel, LDS of a ring launch
+int ring_lds_bytes(int q, int lanes);
+int max_lds_bytes();
+
+int launch_init(int q, int prec, void* state, int64_t n, const double* rho0, const Coef& cf,
+                void* stream);
+int launch_plain(int q, int prec, const void* src, void* dst, int64_t n, const Coef& cf,
+                 void* stream);
+int launch_ring(int q, int prec, int B, const void* src, void* dst, int64_t n, int64_t steps,
+                const Coef& cf, void* stream);
+int launch_tile(int q, int prec, int B, int lanes, const void* src, void* dst, int64_t n, int s,
+                const Coef& cf, void* stream);
+int launch_read_rho(int q, int prec, const void* state, int64_t n, double* out, void* stream);
+int launch_read_f(int q, int prec, const void* state, int64_t n, double* out, int pre,
+                  const Coef& cf, void* stream);
+int launch_write_f(int q, int prec, void* state, int64_t n, const double* in, const Coef& cf,
+                   void* stream);
+int launch_diag(int q, int prec, const void* state, int64_t n, double* partial, int* flag,
+                double* mass_out, void* stream);
+
+// ensemble: one window per workgroup, read from a device descriptor table
+struct WinDesc {
+    int64_t src_off;    // byte offset of the instance's source state copy
+    int64_t dst_off;    // byte offset of the destination state copy
+    int64_t n;          // sites of the instance
+    int64_t start;      // first site of the window (may be negative: periodic)
+    int32_t steps;      // steps this window advances
+    int32_t valid;      // sites written back, from start + halo
+    int64_t pad_;
+};
+int launch_ens(int q, int prec, int B, int lanes, char* base, const WinDesc* desc, int nwin,
+               const Coef& cf, void* stream);
+
+}  // namespace kslb

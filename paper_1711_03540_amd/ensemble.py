@@ -1,0 +1,102 @@
+"""Python front end of a ragged ensemble of periodic KS lattices (libkslb)."""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import call, fn
+from .lattice import _dptr, _prec
+
+
+class Ensemble:
+    """``len(sizes)`` independent periodic lattices of one scheme and precision.
+
+    Instance i has capacity ``sizes[i]`` sites; all share one coefficient set.
+    ``advance(steps)`` moves instance i by ``steps[i]`` steps, one kernel
+    launch per chunk of steps for the whole ensemble.
+    """
+
+    def __init__(self, sizes: Sequence[int], q: int = 7, precision="fp64", device=None, stream=None):
+        import torch
+        self.sizes = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
+        self.count = int(self.sizes.size)
+        self.q, self.precision = int(q), _prec(precision)
+        self.device = torch.device(device if device is not None else "cuda")
+        nbytes = fn("kslb_ensemble_bytes")(self.count, _dptr(self.sizes), self.q, self.precision)
+        if nbytes == 0:
+            raise ValueError("bad ensemble shape")
+        self.nbytes = nbytes
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            call("kslb_ensemble_create", ctypes.byref(h), self.count, _dptr(self.sizes), self.q,
+                 self.precision, ctypes.c_void_p(self.buf.data_ptr()), nbytes,
+                 ctypes.c_void_p(self.stream.cuda_stream))
+        self._h = h
+        self.n = self.sizes.copy()
+
+    def set_physical(self, dX: float, dT: float, tau: float = 0.0, dm_variant: int = 0,
+                     guard: str = "refuse", rho_max: float = 3.0) -> "Ensemble":
+        g = {"refuse": _lib.GUARD_REFUSE, "raise": _lib.GUARD_RAISE_TAU, "off": _lib.GUARD_OFF}[guard]
+        call("kslb_ensemble_set_physical", self._h, dX, dT, tau, dm_variant, g, rho_max)
+        return self
+
+    @property
+    def tau(self) -> float:
+        t = ctypes.c_double()
+        call("kslb_ensemble_get_tau", self._h, ctypes.byref(t))
+        return t.value
+
+    def set_tiling(self, sites_per_lane: int = 0, lanes: int = 0, steps_per_chunk: int = 0) -> "Ensemble":
+        call("kslb_ensemble_set_tiling", self._h, sites_per_lane, lanes, steps_per_chunk)
+        return self
+
+    def resize(self, idx: int, n: int) -> "Ensemble":
+        call("kslb_ensemble_resize", self._h, int(idx), int(n))
+        self.n[idx] = n
+        return self
+
+    def init_rho(self, idx: int, rho) -> "Ensemble":
+        import torch
+        if isinstance(rho, torch.Tensor) and rho.is_cuda:
+            r = rho.to(torch.float64).contiguous()
+            call("kslb_ensemble_init_rho", self._h, int(idx), ctypes.c_void_p(r.data_ptr()), 1)
+        else:
+            r = np.ascontiguousarray(np.asarray(rho, dtype=np.float64))
+            assert r.size == self.n[idx]
+            call("kslb_ensemble_init_rho", self._h, int(idx), _dptr(r), 0)
+        return self
+
+    def advance(self, steps) -> "Ensemble":
+        s = np.ascontiguousarray(np.broadcast_to(np.asarray(steps, dtype=np.int64), (self.count,)))
+        call("kslb_ensemble_advance", self._h, _dptr(s))
+        return self
+
+    def rho(self, idx: int) -> np.ndarray:
+        out = np.zeros(int(self.n[idx]))
+        call("kslb_ensemble_read_rho", self._h, int(idx), _dptr(out), 0)
+        return out
+
+    def read_rho(self, idx: int, out):
+        call("kslb_ensemble_read_rho", self._h, int(idx), ctypes.c_void_p(out.data_ptr()), 1)
+        return out
+
+    def status(self, idx: int):
+        s, f = ctypes.c_int64(), ctypes.c_int()
+        call("kslb_ensemble_status", self._h, int(idx), ctypes.byref(s), ctypes.byref(f))
+        return s.value, bool(f.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            fn("kslb_ensemble_destroy")(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,294 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bar: FP64 results within 1e-12 norm-wise relative error of the oracle,
+max|x - x_oracle| / max|x_oracle|, for rho and for every population; every
+kernel class bitwise identical to every other.  FP32 and split-precision
+errors are measured and bounded loosely.
+"""
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_03540_amd.ensemble import Ensemble
+from paper_1711_03540_amd.inputs import (CFG_LARGE_Q7, CFG_RESIDENT_Q7, CFG_SMALL_Q5, kassam_trefethen_ic,
+                                         random_modes_ic)
+from paper_1711_03540_amd.lattice import Lattice
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(np.asarray(b))))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@functools.lru_cache(maxsize=64)
+def oracle_run(q, n, dX, dT, tau, steps, seed, amp=0.3):
+    rho0 = ic(n, dX, seed, amp)
+    return oracle.solve_periodic(q, rho0, dX, dT, tau, steps, want_f=True)
+
+
+def ic(n, dX, seed, amp=0.3):
+    return 1.0 + random_modes_ic(n, n * dX, seed=seed, n_modes=min(16, max(1, n // 2)), amplitude=amp)
+
+
+def make(q, n, prec="fp64", kernel="auto", dX=0.2, dT=1e-4, tau=1.1, steps_per_launch=0):
+    lat = Lattice(n, q, prec)
+    lat.set_physical(dX, dT, tau)
+    lat.set_kernel(kernel, steps_per_launch)
+    return lat
+
+
+SIZES = [1, 2, 3, 7, 64, 256, 1000, 1001, 4096, 70001]
+
+
+@pytest.mark.parametrize("q", [5, 7])
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("kernel", ["plain", "tiled", "resident", "auto"])
+def test_fp64_parity(q, n, kernel):
+    dX, dT, tau, steps = 0.2, 1e-4, 1.1, 700
+    say("case fp64 parity q=%d n=%d kernel=%s" % (q, n, kernel))
+    lat = make(q, n, kernel="plain", dX=dX, dT=dT, tau=tau)
+    if kernel == "resident":
+        try:
+            lat.set_kernel("resident")
+        except Exception:
+            pytest.skip("n=%d cannot use the resident kernel" % n)
+    else:
+        lat.set_kernel(kernel)
+    coef = oracle.coefficients(q, dX, dT, tau)
+    rho_ref, f_ref = oracle_run(q, n, dX, dT, tau, steps, 5)
+    lat.init_rho(ic(n, dX, 5)).advance(steps)
+    assert lat.step == steps
+    assert rel(lat.rho(), rho_ref) < TOL64
+    # stored state: the collided populations at time `steps`
+    assert rel(lat.f(pre_collision=False), oracle.collide(q, coef, tau, f_ref)) < TOL64
+    # streamed one link: the oracle's (pre-collision) f one step later
+    assert rel(lat.f(pre_collision=True), oracle.advance(q, coef, tau, f_ref, 1)) < TOL64
+
+
+@pytest.mark.parametrize("q", [5, 7])
+@pytest.mark.parametrize("n", [256, 1000, 4096, 12345])
+def test_kernel_classes_bitwise_identical(q, n):
+    say("case bitwise q=%d n=%d" % (q, n))
+    rho0 = ic(n, 0.2, 9)
+    outs = []
+    for kernel, spl in (("plain", 0), ("tiled", 0), ("tiled", 7), ("tiled", 1), ("resident", 0)):
+        lat = make(q, n, kernel="plain")
+        try:
+            lat.set_kernel(kernel, spl)
+        except Exception:
+            continue
+        lat.init_rho(rho0).advance(333)
+        outs.append((kernel, spl, lat.f()))
+    assert len(outs) >= 4
+    for k, s, f in outs[1:]:
+        assert np.array_equal(f, outs[0][2]), (k, s)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split"])
+@pytest.mark.parametrize("kernel", ["plain", "tiled", "resident"])
+def test_reduced_precision_kernels_bitwise_identical(prec, kernel):
+    say("case bitwise %s %s" % (prec, kernel))
+    n = 4096
+    rho0 = ic(n, 0.2, 4)
+    ref = make(7, n, prec, "plain").init_rho(rho0).advance(250).f()
+    got = make(7, n, prec, kernel).init_rho(rho0).advance(250).f()
+    assert np.array_equal(got, ref)
+
+
+def test_small_config_full_length():
+    # D1Q5, N = 256 on L = 32 pi, cos(x/16)(1 + sin(x/16)), dT = (pi/8)^4/90, tau = 1, 10^4 steps
+    w = CFG_SMALL_Q5
+    say("case %s" % w.name)
+    rho0 = w.rho0()
+    lat = Lattice(w.n, w.q, "fp64")
+    lat.set_physical(w.dX, w.dT, 0.0)
+    tau = lat.coefficients()["tau"]
+    assert tau == 1.0
+    lat.init_rho(rho0).advance(w.steps)
+    ref = oracle.solve_periodic(w.q, rho0, w.dX, w.dT, tau, w.steps)
+    assert rel(lat.rho(), ref) < TOL64
+
+
+def test_resident_config_in_bench_launch():
+    # D1Q7, N = 4096, 16 random modes, dT = 1e-4, fitted tau, resident kernel as timed
+    w = CFG_RESIDENT_Q7
+    say("case %s 2000 steps" % w.name)
+    rho0 = w.rho0()
+    lat = Lattice(w.n, w.q, "fp64")
+    lat.set_physical(w.dX, w.dT, 0.0)
+    lat.set_kernel("resident")
+    tau = lat.coefficients()["tau"]
+    assert abs(tau - oracle.tau_fit(7, w.dX, w.dT)) < 1e-15
+    lat.init_rho(rho0).advance(2000)
+    rho_ref, f_ref = oracle.solve_periodic(w.q, rho0, w.dX, w.dT, tau, 2000, want_f=True)
+    assert rel(lat.rho(), rho_ref) < TOL64
+    coef = oracle.coefficients(w.q, w.dX, w.dT, tau)
+    assert rel(lat.f(), oracle.collide(w.q, coef, tau, f_ref)) < TOL64
+
+
+def test_resident_config_full_length():
+    w = CFG_RESIDENT_Q7
+    say("case %s full %d steps" % (w.name, w.steps))
+    rho0 = w.rho0()
+    lat = Lattice(w.n, w.q, "fp64")
+    lat.set_physical(w.dX, w.dT, 0.0)
+    tau = lat.coefficients()["tau"]
+    lat.init_rho(rho0)
+    m0, bad0 = lat.diagnostics()
+    lat.advance(w.steps)
+    m1, bad1 = lat.diagnostics()
+    assert not bad0 and not bad1
+    assert abs(m1 - m0) < 1e-11 * np.abs(rho0).sum()
+    ref = oracle.solve_periodic(w.q, rho0, w.dX, w.dT, tau, w.steps)
+    err = rel(lat.rho(), ref)
+    say("full-length rel err vs oracle %.3e" % err)
+    assert err < 1e-10
+
+
+def test_large_config_sampled_sites():
+    # D1Q7, N = 2^24, dT = 2e-8, tau = 1, 10^3 steps, tiled kernel: sampled sites
+    # checked against the oracle on the light cone of each site (a periodic
+    # window of 2*3*steps + 1 sites or more gives the centre site exactly).
+    w = CFG_LARGE_Q7
+    say("case %s" % w.name)
+    rho0 = w.rho0()
+    lat = Lattice(w.n, w.q, "fp64")
+    lat.set_physical(w.dX, w.dT, 0.0)
+    tau = lat.coefficients()["tau"]
+    assert tau == 1.0
+    lat.set_kernel("tiled")
+    lat.init_rho(rho0)
+    m0, _ = lat.diagnostics()
+    lat.advance(w.steps)
+    m1, bad = lat.diagnostics()
+    rho = lat.rho()
+    assert not bad
+    assert abs(m1 - m0) < 1e-12 * np.abs(rho0).sum()
+    half = 3 * w.steps + 8
+    rng = np.random.default_rng(0)
+    sites = [0, 1, w.n - 1, w.n // 2] + list(rng.integers(0, w.n, 4))
+    for j in sites:
+        idx = (np.arange(j - half, j + half + 1)) % w.n
+        r = oracle.solve_periodic(w.q, rho0[idx], w.dX, w.dT, tau, w.steps)
+        ref = r[half]
+        assert abs(rho[j] - ref) <= TOL64 * np.max(np.abs(r)), (j, rho[j], ref)
+
+
+def test_plain_and_tiled_agree_at_large_size():
+    w = CFG_LARGE_Q7
+    say("case large plain vs tiled 50 steps")
+    rho0 = w.rho0()
+    a = Lattice(w.n, w.q, "fp64").set_physical(w.dX, w.dT, 0.0).set_kernel("plain")
+    b = Lattice(w.n, w.q, "fp64").set_physical(w.dX, w.dT, 0.0).set_kernel("tiled")
+    a.init_rho(rho0).advance(50)
+    b.init_rho(rho0).advance(50)
+    import torch
+    assert torch.equal(a.read_rho(), b.read_rho())
+    assert torch.equal(a.save_state(), b.save_state())
+
+
+@pytest.mark.parametrize("prec,bound", [("split", 1e-8), ("fp32", 1e-3)])
+def test_reduced_precision_error(prec, bound):
+    w = CFG_RESIDENT_Q7
+    rho0 = w.rho0()
+    tau = oracle.tau_fit(7, w.dX, w.dT)
+    for steps in (1000, 2000):
+        lat = Lattice(w.n, w.q, prec).set_physical(w.dX, w.dT, 0.0)
+        lat.init_rho(rho0).advance(steps)
+        err = rel(lat.rho(), oracle.solve_periodic(7, rho0, w.dX, w.dT, tau, steps))
+        say("%s error vs FP64 oracle at %d steps: %.3e" % (prec, steps, err))
+        assert err < bound
+
+
+def test_ensemble_matches_oracle_and_single_lattices():
+    say("case ensemble ragged")
+    sizes = [3, 64, 500, 777, 1024, 2049, 4096, 5000, 9999, 20000]
+    steps = [0, 1, 17, 64, 100, 333, 250, 16, 170, 50]
+    dX, dT = math.pi / 16, 1e-4
+    ens = Ensemble(sizes, 7, "fp64").set_physical(dX, dT, 0.0)
+    tau = ens.tau
+    rho0s = [random_modes_ic(n, n * dX, seed=1000 + i, n_modes=min(16, max(1, n // 2))) for i, n in enumerate(sizes)]
+    for i, r in enumerate(rho0s):
+        ens.init_rho(i, r)
+    ens.advance(steps)
+    for i, n in enumerate(sizes):
+        got = ens.rho(i)
+        ref = oracle.solve_periodic(7, rho0s[i], dX, dT, tau, steps[i])
+        assert rel(got, ref) < TOL64, i
+        lat = Lattice(n, 7, "fp64").set_physical(dX, dT, 0.0).set_kernel("plain")
+        lat.init_rho(rho0s[i]).advance(steps[i])
+        assert np.array_equal(got, lat.rho()), i
+        assert ens.status(i) == (steps[i], False)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split"])
+def test_checkpoint_resume_bitwise(prec):
+    say("case resume %s" % prec)
+    n = 3000
+    rho0 = ic(n, 0.2, 12)
+    a = make(7, n, prec).init_rho(rho0).advance(400)
+    b = make(7, n, prec).init_rho(rho0).advance(200)
+    blob = b.save_state()
+    c = make(7, n, prec).load_state(blob, 200).advance(200)
+    assert c.step == 400
+    assert np.array_equal(a.f(), c.f())
+
+
+def test_pre_and_post_collision_populations():
+    say("case f conventions")
+    q, n, dX, dT, tau = 7, 300, 0.2, 1e-4, 1.3
+    coef = oracle.coefficients(q, dX, dT, tau)
+    rho0 = ic(n, dX, 21)
+    lat = make(q, n, "fp64", "plain", dX, dT, tau).init_rho(rho0)
+    f = oracle.init(q, coef, rho0)
+    for s in range(3):
+        assert rel(lat.f(pre_collision=False), oracle.collide(q, coef, tau, f)) < TOL64
+        nxt = oracle.advance(q, coef, tau, f, 1)
+        assert rel(lat.f(pre_collision=True), nxt) < TOL64
+        lat.advance(1)
+        f = nxt
+
+
+def test_write_f_roundtrip_and_nonfinite_flag():
+    say("case write_f / nonfinite")
+    n = 500
+    lat = make(7, n).init_rho(ic(n, 0.2, 2)).advance(10)
+    f = lat.f()
+    lat2 = make(7, n).write_f(f, step=10)
+    assert np.array_equal(lat2.f(), f)
+    assert lat2.step == 10
+    mass, bad = lat2.diagnostics()
+    assert not bad and abs(mass - lat.rho().sum()) < 1e-12 * n
+    f[3, 17] = np.nan
+    lat2.write_f(f, step=10)
+    assert lat2.diagnostics()[1]
+
+
+def test_zero_steps_and_errors():
+    say("case errors")
+    from paper_1711_03540_amd import KslbError
+    lat = Lattice(100, 7, "fp64")
+    with pytest.raises(KslbError):
+        lat.advance(1)          # coefficients and state not set
+    lat.set_physical(0.2, 1e-4, 1.1)
+    with pytest.raises(KslbError):
+        lat.advance(1)          # no state yet
+    lat.init_rho(ic(100, 0.2, 1))
+    lat.advance(0)
+    assert lat.step == 0
+    with pytest.raises(KslbError):
+        lat.advance(-1)
+    with pytest.raises(KslbError):
+        lat.set_kernel("tiled", 100000)
+    with pytest.raises(KslbError):
+        Lattice(100, 7).set_physical(0.2, 1e-3, 1.0)   # refused by the stability guard

@@ -1,0 +1,228 @@
+"""Benchmark of the KS lattice Boltzmann hot path on one MI355X.
+
+One benchmark "step" is one whole solve of the workload: equilibrium init from
+a density already resident in HBM, the configured number of LB steps, and the
+density readout into HBM.  The default workload is the improved D1Q7 scheme,
+FP64, N = 4096 periodic sites on L = 256 pi (dX = pi/16), 16 random Fourier
+modes of amplitude 0.1, dT = 1e-4 with the paper's fitted tau, 10^5 LB steps
+per solve, one instance (register-resident single-workgroup kernel).
+
+Prints one JSON line: throughput in site-updates/s (GLUPS), per-solve p50/p99
+latency, the plain one-step-per-launch kernel on the same workload (bitwise
+identical results), the roofline of the dominant kernel, and the CPU oracle
+timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Published MI355X peaks.
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+N_CU = 256
+
+# Algorithmic FP64 flops of one site update (an FMA counts 2): density
+# Q-1 adds, rho^2 1 mul, then per population with G != 0 (c = +-1, +-2) one
+# mul + two FMA, and per population without G one mul + one FMA.
+def flops_per_site_update(q: int) -> int:
+    with_g, without_g = 4, q - 4
+    return (q - 1) + 1 + with_g * (1 + 2 * 2) + without_g * (1 + 2)
+
+
+# Algorithmic HBM bytes of one s = 1 step per site: read Q populations and
+# write Q populations of the storage format.
+def bytes_per_site_update(q: int, precision: str) -> int:
+    return {"fp64": 2 * q * 8, "fp32": 2 * q * 4, "split": 2 * (8 + q * 4)}[precision]
+
+
+WORKLOADS = {
+    "d1q7_n4096": ("CFG_RESIDENT_Q7", "resident"),
+    "d1q5_n256": ("CFG_SMALL_Q5", "resident"),
+    "d1q7_n16m": ("CFG_LARGE_Q7", "tiled"),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed solves")
+    ap.add_argument("--workload", default="d1q7_n4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "split"])
+    ap.add_argument("--kernel", default=None, choices=["resident", "tiled", "plain"])
+    ap.add_argument("--tile-steps", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, tau):
+    """The FP64 CPU oracle on one full solve of the workload (single thread)."""
+    import oracle
+    rho0 = w.rho0()
+    steps = w.steps
+    sample = "one full solve: %d sites x %d steps" % (w.n, steps)
+    if w.n * steps > 6e8:      # bound the CPU leg to roughly 10-20 s
+        steps = max(1, int(4e8 // w.n))
+        sample = "%d sites x %d of the %d steps" % (w.n, steps, w.steps)
+    t0 = time.perf_counter()
+    oracle.solve_periodic(w.q, rho0, w.dX, w.dT, tau, steps)
+    dt = time.perf_counter() - t0
+    return {"value": w.n * steps / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
+            "sample": sample + ", plain C FP64 oracle, %.2f s" % dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (got --gpus %d); a domain or an ensemble "
+              "would shard across GPUs as described in the design notes, but no multi-GPU path is "
+              "built." % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1711_03540_amd import inputs
+    from paper_1711_03540_amd.lattice import Lattice
+
+    wname, default_kernel = WORKLOADS[args.workload]
+    w = getattr(inputs, wname)
+    kernel = args.kernel or default_kernel
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print("bench: workload %s q=%d n=%d steps/solve=%d precision=%s kernel=%s" %
+          (w.name, w.q, w.n, w.steps, args.precision, kernel), file=sys.stderr, flush=True)
+
+    rho0 = torch.tensor(w.rho0(), dtype=torch.float64, device=dev)
+    rho_out = torch.empty(w.n, dtype=torch.float64, device=dev)
+    lat = Lattice(w.n, w.q, args.precision, device=dev)
+    lat.set_physical(w.dX, w.dT, 0.0)
+    lat.set_kernel(kernel, args.tile_steps)
+    tau = lat.coefficients()["tau"]
+    stream = lat.stream
+
+    def solve(ev=None):
+        lat.init_rho(rho0)
+        if ev is not None:
+            ev[0].record(stream)
+        lat.advance(w.steps)
+        if ev is not None:
+            ev[1].record(stream)
+        lat.read_rho(rho_out)
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        solve(kev[k])
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+
+    lat_ms = np.array([starts[k].elapsed_time(ends[k]) for k in range(args.steps)])
+    adv_ms = np.array([kev[k][0].elapsed_time(kev[k][1]) for k in range(args.steps)])
+    site_updates = w.n * w.steps
+    value = site_updates * args.steps / total / 1e9
+    mass, bad = lat.diagnostics()
+    if bad:
+        raise SystemExit("bench: non-finite state")
+
+    # launches per advance and the dominant kernel's average duration
+    if kernel == "resident":
+        launches = max(1, math.ceil(w.steps / (1 << 20)))
+        units = w.n * w.steps / launches
+        kname = "k_ring"
+    elif kernel == "tiled":
+        s = args.tile_steps or (256 * 8) // (16 * (2 if w.q == 5 else 3))
+        launches = math.ceil(w.steps / s)
+        units = w.n * w.steps / launches
+        kname = "k_tile"
+    else:
+        launches = w.steps
+        units = w.n
+        kname = "k_plain"
+    kernel_ms = float(np.mean(adv_ms)) / launches
+    if kernel == "plain":
+        ach = bytes_per_site_update(w.q, args.precision) * units / (kernel_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None}
+    else:
+        ach = flops_per_site_update(w.q) * units / (kernel_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": None}
+        if kernel == "resident":
+            roof["cus_used"] = 1
+            roof["frac_of_used_cus"] = ach / (PEAK_FP64_VECTOR_TFLOPS / N_CU)
+    roof["kernel"] = kname
+    roof["kernel_ms_avg"] = kernel_ms
+    roof["algorithmic_per_site_update"] = (flops_per_site_update(w.q) if kernel != "plain"
+                                           else bytes_per_site_update(w.q, args.precision))
+    roof["units_per_launch"] = units
+
+    out = {
+        "metric": "GLUPS vs plain kernel at matched error; % HBM/LDS peak; p50/p99 solve latency",
+        "value": value,
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "split": "f64+f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": w.name, "scheme": "D1Q%d" % w.q, "n_sites": w.n, "lb_steps_per_solve": w.steps,
+                   "dX": w.dX, "dT": w.dT, "tau": tau, "precision": args.precision, "kernel": kernel,
+                   "instances": 1},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "min": float(lat_ms.min())},
+        "roofline": roof,
+    }
+
+    if not args.no_plain and kernel != "plain":
+        # plain one-step-per-launch kernel on the same lattice; bitwise identical results
+        chk = min(w.steps, 2000)
+        ref = Lattice(w.n, w.q, args.precision, device=dev).set_physical(w.dX, w.dT, 0.0).set_kernel("plain")
+        ref.init_rho(rho0).advance(chk)
+        opt = Lattice(w.n, w.q, args.precision, device=dev).set_physical(w.dX, w.dT, 0.0).set_kernel(kernel)
+        opt.init_rho(rho0).advance(chk)
+        same = bool(torch.equal(ref.save_state(), opt.save_state()))
+        psteps = min(w.steps, 5000)
+        ref.advance(psteps)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ref.advance(psteps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pg = w.n * psteps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        out["plain_kernel"] = {"glups": pg, "timed_lb_steps": psteps, "speedup": value / pg,
+                               "bitwise_identical_state_after_%d_steps" % chk: same}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, tau)
+        out["cpu_baseline"]["host"] = {"nproc": os.cpu_count()}
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -210,8 +210,9 @@ kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* 
 kslb_status kslb_ensemble_set_physical(kslb_ensemble* ens, double dX, double dT, double tau,
                                        int dm_variant, int guard_policy, double rho_max);
 
-/* Tiling knobs: sites per lane (4 or 8), lanes per workgroup (64..1024,
- * multiple of 64) and steps per chunk (>= 1); 0 keeps the current value.   */
+/* Tiling knobs: sites per lane (4 or 8), lanes per workgroup (256, the only
+ * value built) and steps per chunk (>= 1, with 2 max|c| steps < the window);
+ * 0 keeps the current value.  Defaults: 8 sites, 256 lanes, 32 steps.      */
 kslb_status kslb_ensemble_set_tiling(kslb_ensemble* ens, int sites_per_lane, int lanes,
                                      int steps_per_chunk);
 

@@ -154,31 +154,31 @@ kslb_status ensure_staging(kslb_lattice* L)
     return KSLB_OK;
 }
 
-// ring kernel: B in {8, 4} dividing n, lanes <= 512 and exchange area in LDS
+// ring kernel: B in {8, 4} dividing n, at most ring_max_lanes() lanes, and
+// the exchange area in LDS
 int ring_sites_per_lane(int64_t n, int q)
 {
+    if (ring_lds_bytes(q) > max_lds_bytes()) return 0;
     const int Bs[2] = {8, 4};
     for (int B : Bs) {
         if (n % B) continue;
         const int64_t L = n / B;
-        if (L < 1 || L > 512) continue;
-        const int lanes = (int)((L + 63) / 64) * 64;
-        if (ring_lds_bytes(q, lanes) > max_lds_bytes()) continue;
+        if (L < 1 || L > ring_max_lanes()) continue;
         return B;
     }
     return 0;
 }
 
-constexpr int kTileLanes = 256;
 constexpr int kTileB = 8;
 
-int default_tile_steps(int64_t n, int q)
+// Steps per tiled launch: halo overhead 2 H s <= W / 8, rounded down to a
+// multiple of 8 so that every window starts on an 8-site boundary.
+int default_tile_steps(int q)
 {
-    // keep halo overhead modest: 2 H s <= W / 8
-    const int W = kTileLanes * kTileB;
+    const int W = tile_lanes() * kTileB;
     int s = W / (16 * halo(q));
-    (void)n;
-    return std::max(1, s);
+    s -= s % 8;
+    return std::max(8, s);
 }
 
 kslb_status check_lat(const kslb_lattice* L)
@@ -311,7 +311,7 @@ kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
                         (long long)L->n);
     }
     if (kernel == KSLB_KERNEL_TILED && steps_per_launch > 0) {
-        if (kTileLanes * kTileB - 2 * halo(L->q) * steps_per_launch <= 0)
+        if (tile_lanes() * kTileB - 2 * halo(L->q) * steps_per_launch <= 0)
             return fail(KSLB_EINVAL, "steps_per_launch %d leaves no valid sites in a tile", steps_per_launch);
     }
     L->kernel = kernel;
@@ -371,11 +371,10 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
             L->cur ^= 1;
         }
     } else {
-        int s_max = L->tile_steps > 0 ? L->tile_steps : default_tile_steps(L->n, L->q);
+        int s_max = L->tile_steps > 0 ? L->tile_steps : default_tile_steps(L->q);
         for (int64_t done = 0; done < n_steps;) {
             const int s = (int)std::min<int64_t>(s_max, n_steps - done);
-            e = launch_tile(L->q, L->prec, kTileB, kTileLanes, L->state(), L->other(), L->n, s, L->ph.cf,
-                            L->stream);
+            e = launch_tile(L->q, L->prec, kTileB, L->state(), L->other(), L->n, s, L->ph.cf, L->stream);
             if (e) return hip_fail(e, "tiled kernel");
             L->cur ^= 1;
             done += s;
@@ -545,7 +544,7 @@ struct kslb_ensemble {
     std::vector<int64_t> step;
     std::vector<char> have_state;
     Physics ph;
-    int B = 8, lanes = 256, chunk = 16;
+    int B = 8, chunk = 32;
     size_t diag_off = 0;
     // descriptor tables: two device slots, remembered host contents
     WinDesc* d_desc[2] = {nullptr, nullptr};
@@ -696,14 +695,13 @@ kslb_status kslb_ensemble_set_tiling(kslb_ensemble* E, int sites_per_lane, int l
 {
     if (!E) return fail(KSLB_EINVAL, "null ensemble");
     int B = sites_per_lane ? sites_per_lane : E->B;
-    int L = lanes ? lanes : E->lanes;
     int c = steps_per_chunk ? steps_per_chunk : E->chunk;
     if (B != 4 && B != 8) return fail(KSLB_EINVAL, "sites_per_lane must be 4 or 8");
-    if (L < 64 || L > 256 || L % 64) return fail(KSLB_EINVAL, "lanes must be 64, 128, 192 or 256");
-    if (c < 1 || (int64_t)L * B - 2 * halo(E->q) * (int64_t)c <= 0)
-        return fail(KSLB_EINVAL, "steps_per_chunk %d leaves no valid sites in a %d-site window", c, L * B);
+    if (lanes != 0 && lanes != tile_lanes()) return fail(KSLB_EINVAL, "lanes must be 0 or %d", tile_lanes());
+    const int64_t W = (int64_t)tile_lanes() * B;
+    if (c < 1 || W - 2 * halo(E->q) * (int64_t)c <= 0)
+        return fail(KSLB_EINVAL, "steps_per_chunk %d leaves no valid sites in a %lld-site window", c, (long long)W);
     E->B = B;
-    E->lanes = L;
     E->chunk = c;
     return KSLB_OK;
 }
@@ -755,7 +753,7 @@ kslb_status kslb_ensemble_advance(kslb_ensemble* E, const int64_t* steps)
     }
     DeviceGuard g(E->device);
     const int H = halo(E->q);
-    const int64_t W = (int64_t)E->lanes * E->B;
+    const int64_t W = (int64_t)tile_lanes() * E->B;
     std::vector<int64_t> left(steps, steps + E->count);
     std::vector<WinDesc> h;
     for (;;) {
@@ -775,14 +773,14 @@ kslb_status kslb_ensemble_advance(kslb_ensemble* E, const int64_t* steps)
                 d.start = t0 - (int64_t)H * s;
                 d.steps = s;
                 d.valid = (int32_t)std::min<int64_t>(T, n - t0);
-                d.pad_ = 0;
+                d.pitch = state_pitch(n);
                 h.push_back(d);
             }
         }
         if (h.empty()) break;
         WinDesc* dev = nullptr;
         if (auto s = ens_upload(E, h, &dev)) return s;
-        int e = launch_ens(E->q, E->prec, E->B, E->lanes, E->buf, dev, (int)h.size(), E->ph.cf, E->stream);
+        int e = launch_ens(E->q, E->prec, E->B, E->buf, dev, (int)h.size(), E->ph.cf, E->stream);
         if (e) return hip_fail(e, "ensemble kernel");
         for (int i = 0; i < E->count; i++) {
             if (left[i] <= 0) continue;

@@ -37,7 +37,8 @@ double spectral_radius(int q, const double* E, const double* G, double omega, do
 int stability_check(int q, const double* E, const double* G, double omega, double dX, double dT,
                     double rho_max);
 
-// bytes of one copy of the state of n sites
+// row pitch (sites) and bytes of one copy of the state of n sites
+int64_t state_pitch(int64_t n);
 size_t state_copy_bytes(int64_t n, int q, int prec);
 
 // ---------------------------------------------------------------------------
@@ -47,8 +48,11 @@ struct LaunchCtx {
     void* stream;     // hipStream_t
 };
 
-// max sites per lane, lanes of the ring kernel, LDS of a ring launch
-int ring_lds_bytes(int q, int lanes);
+// lanes and LDS bytes of the ring (one workgroup per lattice) and tile kernels
+int ring_max_lanes();
+int tile_lanes();
+int ring_lds_bytes(int q);
+int tile_lds_bytes(int q);
 int max_lds_bytes();
 
 int launch_init(int q, int prec, void* state, int64_t n, const double* rho0, const Coef& cf,
@@ -57,7 +61,7 @@ int launch_plain(int q, int prec, const void* src, void* dst, int64_t n, const C
                  void* stream);
 int launch_ring(int q, int prec, int B, const void* src, void* dst, int64_t n, int64_t steps,
                 const Coef& cf, void* stream);
-int launch_tile(int q, int prec, int B, int lanes, const void* src, void* dst, int64_t n, int s,
+int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, int s,
                 const Coef& cf, void* stream);
 int launch_read_rho(int q, int prec, const void* state, int64_t n, double* out, void* stream);
 int launch_read_f(int q, int prec, const void* state, int64_t n, double* out, int pre,
@@ -75,9 +79,9 @@ struct WinDesc {
     int64_t start;      // first site of the window (may be negative: periodic)
     int32_t steps;      // steps this window advances
     int32_t valid;      // sites written back, from start + halo
-    int64_t pad_;
+    int64_t pitch;      // row pitch of the instance (state_pitch(n))
 };
-int launch_ens(int q, int prec, int B, int lanes, char* base, const WinDesc* desc, int nwin,
+int launch_ens(int q, int prec, int B, char* base, const WinDesc* desc, int nwin,
                const Coef& cf, void* stream);
 
 }  // namespace kslb

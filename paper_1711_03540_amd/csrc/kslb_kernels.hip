@@ -11,8 +11,9 @@
 // kernel produce bitwise identical states.
 //
 // Layout in HBM: structure of arrays, population-major, one copy per
-// ping-pong side.  FP64: Q x n doubles.  FP32: Q x n floats.  SPLIT: n
-// doubles of rho, then Q x n floats of f_i - feq_i(rho).
+// ping-pong side, rows padded to a pitch p = n rounded up to 64 sites.
+// FP64: Q rows of p doubles.  FP32: Q rows of p floats.  SPLIT: one row of p
+// doubles (rho), then Q rows of p floats (f_i - feq_i(rho)).
 //
 // Register-resident kernels give each lane B consecutive sites in VGPRs.  A
 // step moves data between lanes only at block edges: lane l publishes the
@@ -61,7 +62,21 @@ __device__ __forceinline__ int64_t wrap_site(int64_t j, int64_t n)
     return j < 0 ? j + n : j;
 }
 
+// Density sum over the incoming populations in a fixed pairwise order (every
+// kernel class uses this one, so they round identically).
+template <int Q>
+__device__ __forceinline__ double dsum(const double (&g)[Q])
+{
+    if constexpr (Q == 5) return ((g[0] + g[1]) + (g[2] + g[3])) + g[4];
+    else return ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + g[6]);
+}
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------- precision policies
+// A state copy stores population i of site j at element i * p + j, with the
+// row pitch p = n rounded up to a multiple of 64 (see state_pitch).
 
 template <int Q, int P>
 struct Pol;
@@ -74,15 +89,14 @@ struct Pol<Q, kFP64> {
     __device__ static __forceinline__ double pop(const Site& x, const Coef&) { return x.s[I]; }
 
     template <int I>
-    __device__ static __forceinline__ double pop_g(const char* st, int64_t n, int64_t j, const Coef&)
+    __device__ static __forceinline__ double pop_g(const char* st, int64_t p, int64_t j, const Coef&)
     {
-        return reinterpret_cast<const double*>(st)[I * n + j];
+        return reinterpret_cast<const double*>(st)[I * p + j];
     }
 
     __device__ static __forceinline__ void update(const double (&g)[Q], Site& y, const Coef& cf)
     {
-        double rho = g[0];
-        unroll<Q - 1>([&](auto I) { rho = rho + g[I + 1]; });
+        const double rho = dsum<Q>(g);
         const double r2 = rho * rho;
         unroll<Q>([&](auto I) {
             constexpr int i = I;
@@ -93,16 +107,44 @@ struct Pol<Q, kFP64> {
         });
     }
 
-    __device__ static __forceinline__ Site load(const char* st, int64_t n, int64_t j)
+    __device__ static __forceinline__ Site load(const char* st, int64_t p, int64_t j)
     {
         Site x;
-        unroll<Q>([&](auto I) { x.s[I] = reinterpret_cast<const double*>(st)[I * n + j]; });
+        unroll<Q>([&](auto I) { x.s[I] = reinterpret_cast<const double*>(st)[I * p + j]; });
         return x;
     }
 
-    __device__ static __forceinline__ void store(char* st, int64_t n, int64_t j, const Site& x)
+    __device__ static __forceinline__ void store(char* st, int64_t p, int64_t j, const Site& x)
     {
-        unroll<Q>([&](auto I) { reinterpret_cast<double*>(st)[I * n + j] = x.s[I]; });
+        unroll<Q>([&](auto I) { reinterpret_cast<double*>(st)[I * p + j] = x.s[I]; });
+    }
+
+    // B consecutive sites from j0 (j0 and p multiples of 2)
+    template <int B>
+    __device__ static __forceinline__ void load_vec(const char* st, int64_t p, int64_t j0, Site (&x)[B])
+    {
+        unroll<Q>([&](auto I) {
+            const d2v* src = reinterpret_cast<const d2v*>(reinterpret_cast<const double*>(st) + I * p + j0);
+            unroll<B / 2>([&](auto K) {
+                const d2v v = src[K];
+                x[2 * K].s[I] = v.x;
+                x[2 * K + 1].s[I] = v.y;
+            });
+        });
+    }
+
+    template <int B>
+    __device__ static __forceinline__ void store_vec(char* st, int64_t p, int64_t j0, const Site (&x)[B])
+    {
+        unroll<Q>([&](auto I) {
+            d2v* dst = reinterpret_cast<d2v*>(reinterpret_cast<double*>(st) + I * p + j0);
+            unroll<B / 2>([&](auto K) {
+                d2v v;
+                v.x = x[2 * K].s[I];
+                v.y = x[2 * K + 1].s[I];
+                dst[K] = v;
+            });
+        });
     }
 
     __device__ static __forceinline__ Site equilibrium(double rho, const Coef& cf)
@@ -124,12 +166,7 @@ struct Pol<Q, kFP64> {
         return x;
     }
 
-    __device__ static __forceinline__ double density(const Site& x)
-    {
-        double r = x.s[0];
-        unroll<Q - 1>([&](auto I) { r = r + x.s[I + 1]; });
-        return r;
-    }
+    __device__ static __forceinline__ double density(const Site& x) { return dsum<Q>(x.s); }
 
     __device__ static __forceinline__ bool finite(const Site& x)
     {
@@ -147,16 +184,15 @@ struct Pol<Q, kFP32> {
     __device__ static __forceinline__ double pop(const Site& x, const Coef&) { return (double)x.s[I]; }
 
     template <int I>
-    __device__ static __forceinline__ double pop_g(const char* st, int64_t n, int64_t j, const Coef&)
+    __device__ static __forceinline__ double pop_g(const char* st, int64_t p, int64_t j, const Coef&)
     {
-        return (double)reinterpret_cast<const float*>(st)[I * n + j];
+        return (double)reinterpret_cast<const float*>(st)[I * p + j];
     }
 
     // density sum and rho^2 term in double, relaxation in single
     __device__ static __forceinline__ void update(const double (&g)[Q], Site& y, const Coef& cf)
     {
-        double rho = g[0];
-        unroll<Q - 1>([&](auto I) { rho = rho + g[I + 1]; });
+        const double rho = dsum<Q>(g);
         const double r2 = rho * rho;
         unroll<Q>([&](auto I) {
             constexpr int i = I;
@@ -167,16 +203,48 @@ struct Pol<Q, kFP32> {
         });
     }
 
-    __device__ static __forceinline__ Site load(const char* st, int64_t n, int64_t j)
+    __device__ static __forceinline__ Site load(const char* st, int64_t p, int64_t j)
     {
         Site x;
-        unroll<Q>([&](auto I) { x.s[I] = reinterpret_cast<const float*>(st)[I * n + j]; });
+        unroll<Q>([&](auto I) { x.s[I] = reinterpret_cast<const float*>(st)[I * p + j]; });
         return x;
     }
 
-    __device__ static __forceinline__ void store(char* st, int64_t n, int64_t j, const Site& x)
+    __device__ static __forceinline__ void store(char* st, int64_t p, int64_t j, const Site& x)
     {
-        unroll<Q>([&](auto I) { reinterpret_cast<float*>(st)[I * n + j] = x.s[I]; });
+        unroll<Q>([&](auto I) { reinterpret_cast<float*>(st)[I * p + j] = x.s[I]; });
+    }
+
+    // B consecutive sites from j0 (j0 and p multiples of 4)
+    template <int B>
+    __device__ static __forceinline__ void load_vec(const char* st, int64_t p, int64_t j0, Site (&x)[B])
+    {
+        unroll<Q>([&](auto I) {
+            const f4v* src = reinterpret_cast<const f4v*>(reinterpret_cast<const float*>(st) + I * p + j0);
+            unroll<B / 4>([&](auto K) {
+                const f4v v = src[K];
+                x[4 * K].s[I] = v.x;
+                x[4 * K + 1].s[I] = v.y;
+                x[4 * K + 2].s[I] = v.z;
+                x[4 * K + 3].s[I] = v.w;
+            });
+        });
+    }
+
+    template <int B>
+    __device__ static __forceinline__ void store_vec(char* st, int64_t p, int64_t j0, const Site (&x)[B])
+    {
+        unroll<Q>([&](auto I) {
+            f4v* dst = reinterpret_cast<f4v*>(reinterpret_cast<float*>(st) + I * p + j0);
+            unroll<B / 4>([&](auto K) {
+                f4v v;
+                v.x = x[4 * K].s[I];
+                v.y = x[4 * K + 1].s[I];
+                v.z = x[4 * K + 2].s[I];
+                v.w = x[4 * K + 3].s[I];
+                dst[K] = v;
+            });
+        });
     }
 
     __device__ static __forceinline__ Site equilibrium(double rho, const Coef& cf)
@@ -200,9 +268,9 @@ struct Pol<Q, kFP32> {
 
     __device__ static __forceinline__ double density(const Site& x)
     {
-        double r = (double)x.s[0];
-        unroll<Q - 1>([&](auto I) { r = r + (double)x.s[I + 1]; });
-        return r;
+        double g[Q];
+        unroll<Q>([&](auto I) { g[I] = (double)x.s[I]; });
+        return dsum<Q>(g);
     }
 
     __device__ static __forceinline__ bool finite(const Site& x)
@@ -214,13 +282,14 @@ struct Pol<Q, kFP32> {
 };
 
 // rho in double, non-equilibrium part n_i = S_i - feq_i(rho) in single.
+// Copy layout: one row of p doubles (rho), then Q rows of p floats.
 template <int Q>
 struct Pol<Q, kSPLIT> {
     struct Site { double rho; float n[Q]; };
 
-    __device__ static __forceinline__ const float* nbase(const char* st, int64_t n)
+    __device__ static __forceinline__ const float* nbase(const char* st, int64_t p)
     {
-        return reinterpret_cast<const float*>(st + n * (int64_t)sizeof(double));
+        return reinterpret_cast<const float*>(st + p * (int64_t)sizeof(double));
     }
 
     template <int I>
@@ -237,16 +306,15 @@ struct Pol<Q, kSPLIT> {
     }
 
     template <int I>
-    __device__ static __forceinline__ double pop_g(const char* st, int64_t n, int64_t j, const Coef& cf)
+    __device__ static __forceinline__ double pop_g(const char* st, int64_t p, int64_t j, const Coef& cf)
     {
         const double rho = reinterpret_cast<const double*>(st)[j];
-        return eq_of<I>(rho, cf) + (double)nbase(st, n)[I * n + j];
+        return eq_of<I>(rho, cf) + (double)nbase(st, p)[I * p + j];
     }
 
     __device__ static __forceinline__ void update(const double (&g)[Q], Site& y, const Coef& cf)
     {
-        double rho = g[0];
-        unroll<Q - 1>([&](auto I) { rho = rho + g[I + 1]; });
+        const double rho = dsum<Q>(g);
         y.rho = rho;
         unroll<Q>([&](auto I) {
             constexpr int i = I;
@@ -254,20 +322,65 @@ struct Pol<Q, kSPLIT> {
         });
     }
 
-    __device__ static __forceinline__ Site load(const char* st, int64_t n, int64_t j)
+    __device__ static __forceinline__ Site load(const char* st, int64_t p, int64_t j)
     {
         Site x;
         x.rho = reinterpret_cast<const double*>(st)[j];
-        const float* nb = nbase(st, n);
-        unroll<Q>([&](auto I) { x.n[I] = nb[I * n + j]; });
+        const float* nb = nbase(st, p);
+        unroll<Q>([&](auto I) { x.n[I] = nb[I * p + j]; });
         return x;
     }
 
-    __device__ static __forceinline__ void store(char* st, int64_t n, int64_t j, const Site& x)
+    __device__ static __forceinline__ void store(char* st, int64_t p, int64_t j, const Site& x)
     {
         reinterpret_cast<double*>(st)[j] = x.rho;
-        float* nb = const_cast<float*>(nbase(st, n));
-        unroll<Q>([&](auto I) { nb[I * n + j] = x.n[I]; });
+        float* nb = const_cast<float*>(nbase(st, p));
+        unroll<Q>([&](auto I) { nb[I * p + j] = x.n[I]; });
+    }
+
+    // B consecutive sites from j0 (j0 and p multiples of 4)
+    template <int B>
+    __device__ static __forceinline__ void load_vec(const char* st, int64_t p, int64_t j0, Site (&x)[B])
+    {
+        const d2v* r = reinterpret_cast<const d2v*>(reinterpret_cast<const double*>(st) + j0);
+        unroll<B / 2>([&](auto K) {
+            const d2v v = r[K];
+            x[2 * K].rho = v.x;
+            x[2 * K + 1].rho = v.y;
+        });
+        unroll<Q>([&](auto I) {
+            const f4v* src = reinterpret_cast<const f4v*>(nbase(st, p) + I * p + j0);
+            unroll<B / 4>([&](auto K) {
+                const f4v v = src[K];
+                x[4 * K].n[I] = v.x;
+                x[4 * K + 1].n[I] = v.y;
+                x[4 * K + 2].n[I] = v.z;
+                x[4 * K + 3].n[I] = v.w;
+            });
+        });
+    }
+
+    template <int B>
+    __device__ static __forceinline__ void store_vec(char* st, int64_t p, int64_t j0, const Site (&x)[B])
+    {
+        d2v* r = reinterpret_cast<d2v*>(reinterpret_cast<double*>(st) + j0);
+        unroll<B / 2>([&](auto K) {
+            d2v v;
+            v.x = x[2 * K].rho;
+            v.y = x[2 * K + 1].rho;
+            r[K] = v;
+        });
+        unroll<Q>([&](auto I) {
+            f4v* dst = reinterpret_cast<f4v*>(const_cast<float*>(nbase(st, p)) + I * p + j0);
+            unroll<B / 4>([&](auto K) {
+                f4v v;
+                v.x = x[4 * K].n[I];
+                v.y = x[4 * K + 1].n[I];
+                v.z = x[4 * K + 2].n[I];
+                v.w = x[4 * K + 3].n[I];
+                dst[K] = v;
+            });
+        });
     }
 
     __device__ static __forceinline__ Site equilibrium(double rho, const Coef&)
@@ -281,8 +394,7 @@ struct Pol<Q, kSPLIT> {
     __device__ static __forceinline__ Site from_f(const double (&f)[Q], const Coef& cf)
     {
         Site x;
-        double rho = f[0];
-        unroll<Q - 1>([&](auto I) { rho = rho + f[I + 1]; });
+        const double rho = dsum<Q>(f);
         x.rho = rho;
         unroll<Q>([&](auto I) { x.n[I] = (float)(f[I] - eq_of<I>(rho, cf)); });
         return x;
@@ -301,17 +413,18 @@ struct Pol<Q, kSPLIT> {
 // ---------------------------------------------------------------- per-site kernels
 
 template <int Q, int P>
-__global__ __launch_bounds__(256) void k_init(char* st, int64_t n, const double* __restrict__ rho0, Coef cf)
+__global__ __launch_bounds__(256) void k_init(char* st, int64_t n, int64_t p, const double* __restrict__ rho0,
+                                              Coef cf)
 {
     using PL = Pol<Q, P>;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j < n) PL::store(st, n, j, PL::equilibrium(rho0[j], cf));
+    if (j < n) PL::store(st, p, j, PL::equilibrium(rho0[j], cf));
 }
 
 // One fused pull-stream + density + equilibrium + BGK step per launch (s = 1).
 template <int Q, int P>
 __global__ __launch_bounds__(256) void k_plain(const char* __restrict__ src, char* __restrict__ dst,
-                                               int64_t n, Coef cf)
+                                               int64_t n, int64_t p, Coef cf)
 {
     using PL = Pol<Q, P>;
     constexpr int H = halo_of(Q);
@@ -319,28 +432,30 @@ __global__ __launch_bounds__(256) void k_plain(const char* __restrict__ src, cha
     if (j >= n) return;
     double g[Q];
     if (j >= H && j + H < n) {
-        unroll<Q>([&](auto I) { g[I] = PL::template pop_g<I>(src, n, j - vel(I), cf); });
+        unroll<Q>([&](auto I) { g[I] = PL::template pop_g<I>(src, p, j - vel(I), cf); });
     } else {
-        unroll<Q>([&](auto I) { g[I] = PL::template pop_g<I>(src, n, wrap_site(j - vel(I), n), cf); });
+        unroll<Q>([&](auto I) { g[I] = PL::template pop_g<I>(src, p, wrap_site(j - vel(I), n), cf); });
     }
     typename PL::Site y;
     PL::update(g, y, cf);
-    PL::store(dst, n, j, y);
+    PL::store(dst, p, j, y);
 }
 
 // ---------------------------------------------------------------- register-resident step engine
 
-template <int Q, int P, int B>
+// LD = lanes stride of the exchange area (compile time, so every LDS address
+// is the lane's base plus an immediate offset).
+template <int Q, int P, int B, int LD>
 struct Engine {
     using PL = Pol<Q, P>;
     using Site = typename PL::Site;
     static constexpr int H = halo_of(Q);
     static constexpr int NX = nx_of(Q);
+    static constexpr int SLOT = NX * LD;     // doubles per exchange buffer
     static_assert(B >= H, "a lane must hold at least max|c| sites");
 
-    // write the populations the neighbours pull; column `lane`, row stride ld
-    __device__ static __forceinline__ void publish(const Site (&x)[B], double* slot, int ld, int lane,
-                                                   const Coef& cf)
+    // write the populations the neighbours pull (column `lane` of slot)
+    __device__ static __forceinline__ void publish(const Site (&x)[B], double* slot, const Coef& cf)
     {
         unroll<Q - 1>([&](auto I1) {
             constexpr int i = I1 + 1;
@@ -349,14 +464,15 @@ struct Engine {
             unroll<iabs(c)>([&](auto T) {
                 constexpr int t = T;
                 constexpr int src = (c > 0) ? (B - c + t) : t;
-                slot[(k0 + t) * ld + lane] = PL::template pop<i>(x[src], cf);
+                slot[(k0 + t) * LD] = PL::template pop<i>(x[src], cf);
             });
         });
     }
 
-    // one step: registers plus the neighbours' published values
-    __device__ static __forceinline__ void step(Site (&x)[B], const double* slot, int ld, int left,
-                                                int right, const Coef& cf)
+    // one step x -> y: registers plus the neighbours' published values;
+    // left/right point at the neighbours' columns of the slot
+    __device__ static __forceinline__ void step(const Site (&x)[B], Site (&y)[B], const double* left,
+                                                const double* right, const Coef& cf)
     {
         double hv[NX];
         unroll<Q - 1>([&](auto I1) {
@@ -365,10 +481,9 @@ struct Engine {
             constexpr int k0 = koff(i);
             unroll<iabs(c)>([&](auto T) {
                 constexpr int t = T;
-                hv[k0 + t] = slot[(k0 + t) * ld + (c > 0 ? left : right)];
+                hv[k0 + t] = (c > 0 ? left : right)[(k0 + t) * LD];
             });
         });
-        Site y[B];
         unroll<B>([&](auto Bi) {
             constexpr int b = Bi;
             double g[Q];
@@ -382,125 +497,163 @@ struct Engine {
             });
             PL::update(g, y[b], cf);
         });
-        unroll<B>([&](auto Bi) { x[Bi] = y[Bi]; });
+    }
+
+    // `steps` steps in place on x, lanes `lane` with neighbour lanes left/right;
+    // every lane of the workgroup must call this (it holds the barriers).
+    __device__ static __forceinline__ void run(Site (&x)[B], int64_t steps, double* xch, int lane, int left,
+                                               int right, bool active, const Coef& cf)
+    {
+        Site y[B];
+        int64_t st = 0;
+        for (; st + 1 < steps; st += 2) {
+            if (active) publish(x, xch + lane, cf);
+            __syncthreads();
+            if (active) step(x, y, xch + left, xch + right, cf);
+            if (active) publish(y, xch + SLOT + lane, cf);
+            __syncthreads();
+            if (active) step(y, x, xch + SLOT + left, xch + SLOT + right, cf);
+        }
+        if (st < steps) {
+            if (active) publish(x, xch + lane, cf);
+            __syncthreads();
+            if (active) {
+                step(x, y, xch + left, xch + right, cf);
+                unroll<B>([&](auto Bi) { x[Bi] = y[Bi]; });
+            }
+            __syncthreads();   // the next call writes slot 0 again
+        }
     }
 };
+
+constexpr int kRingLD = 512;
+
+// 16-byte global loads/stores of a lane's B sites (FP64 only: with the mixed
+// rho/n site record of SPLIT and the 28-byte FP32 record the compiler keeps
+// part of the register block in scratch memory).
+template <int P>
+constexpr bool kVecIO = (P == kFP64);
+constexpr int kTileLD = 256;
 
 // Whole periodic lattice of n = B * L sites in one workgroup of L lanes,
 // `steps` steps per launch; lane 0 and lane L-1 are neighbours.
 template <int Q, int P, int B>
-__global__ __launch_bounds__(512) void k_ring(const char* __restrict__ src, char* __restrict__ dst,
-                                              int n, int64_t steps, Coef cf)
+__global__ __launch_bounds__(kRingLD) void k_ring(const char* __restrict__ src, char* __restrict__ dst,
+                                                  int n, int64_t p, int64_t steps, Coef cf)
 {
-    using E = Engine<Q, P, B>;
+    using E = Engine<Q, P, B, kRingLD>;
     extern __shared__ double xch[];
     const int L = n / B;
     const int lane = threadIdx.x;
     const bool active = lane < L;
     typename E::Site x[B];
-    if (active) unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, n, (int64_t)lane * B + Bi); });
+    if (active) {
+        if constexpr (kVecIO<P>) E::PL::template load_vec<B>(src, p, (int64_t)lane * B, x);
+        else unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, p, (int64_t)lane * B + Bi); });
+    }
     const int left = lane == 0 ? L - 1 : lane - 1;
     const int right = lane + 1 >= L ? 0 : lane + 1;
-    const int ld = blockDim.x;
-    for (int64_t st = 0; st < steps; st++) {
-        double* slot = xch + (st & 1) * (E::NX * ld);
-        if (active) E::publish(x, slot, ld, lane, cf);
-        __syncthreads();
-        if (active) E::step(x, slot, ld, left, right, cf);
+    E::run(x, steps, xch, lane, left, right, active, cf);
+    if (active) {
+        if constexpr (kVecIO<P>) E::PL::template store_vec<B>(dst, p, (int64_t)lane * B, x);
+        else unroll<B>([&](auto Bi) { E::PL::store(dst, p, (int64_t)lane * B + Bi, x[Bi]); });
     }
-    if (active) unroll<B>([&](auto Bi) { E::PL::store(dst, n, (int64_t)lane * B + Bi, x[Bi]); });
 }
 
-// One halo-widened window of W = B * lanes sites starting at site `ws`
+// One halo-widened window of W = B * LD sites starting at site `ws`
 // (periodic modulo n), advanced `s` steps in registers; the `valid` sites from
 // ws + H s on are written back.  Sites near the window ends go stale by H per
-// step and are never stored.
+// step and are never stored.  Launched with LD lanes.
 template <int Q, int P, int B>
 __device__ __forceinline__ void window_body(const char* __restrict__ src, char* __restrict__ dst,
-                                            int64_t n, int64_t ws, int s, int64_t valid, double* xch,
-                                            const Coef& cf)
+                                            int64_t n, int64_t p, int64_t ws, int s, int64_t valid,
+                                            double* xch, const Coef& cf)
 {
-    using E = Engine<Q, P, B>;
-    const int L = blockDim.x;
+    using E = Engine<Q, P, B, kTileLD>;
+    constexpr int L = kTileLD;
     const int lane = threadIdx.x;
     typename E::Site x[B];
-    const int64_t W = (int64_t)L * B;
+    constexpr int64_t W = (int64_t)L * B;
     const int64_t j0 = ws + (int64_t)lane * B;
     if (ws >= 0 && ws + W <= n) {
-        unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, n, j0 + Bi); });
+        if (kVecIO<P> && ws % B == 0) E::PL::template load_vec<B>(src, p, j0, x);
+        else unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, p, j0 + Bi); });
     } else {
-        unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, n, wrap_site(j0 + Bi, n)); });
+        unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, p, wrap_site(j0 + Bi, n)); });
     }
     const int left = lane == 0 ? L - 1 : lane - 1;
     const int right = lane + 1 == L ? 0 : lane + 1;
-    for (int st = 0; st < s; st++) {
-        double* slot = xch + (st & 1) * (E::NX * L);
-        E::publish(x, slot, L, lane, cf);
-        __syncthreads();
-        E::step(x, slot, L, left, right, cf);
-    }
+    E::run(x, s, xch, lane, left, right, true, cf);
     const int64_t k_lo = (int64_t)E::H * s;
-    unroll<B>([&](auto Bi) {
-        const int64_t k = (int64_t)lane * B + Bi;
-        if (k >= k_lo && k < k_lo + valid) {
-            const int64_t j = ws + k;
-            if (j < n) E::PL::store(dst, n, j, x[Bi]);
-        }
-    });
+    const int64_t k0 = (int64_t)lane * B;
+    if (kVecIO<P> && k0 >= k_lo && k0 + B <= k_lo + valid && j0 + B <= n && j0 % B == 0) {
+        E::PL::template store_vec<B>(dst, p, j0, x);
+    } else {
+        unroll<B>([&](auto Bi) {
+            const int64_t k = k0 + Bi;
+            if (k >= k_lo && k < k_lo + valid) {
+                const int64_t j = ws + k;
+                if (j < n) E::PL::store(dst, p, j, x[Bi]);
+            }
+        });
+    }
 }
 
 // Large periodic lattice: tile t writes sites [t T, t T + T).
 template <int Q, int P, int B>
-__global__ __launch_bounds__(256) void k_tile(const char* __restrict__ src, char* __restrict__ dst,
-                                              int64_t n, int s, int64_t T, Coef cf)
+__global__ __launch_bounds__(kTileLD) void k_tile(const char* __restrict__ src, char* __restrict__ dst,
+                                                  int64_t n, int64_t p, int s, int64_t T, Coef cf)
 {
     extern __shared__ double xch[];
     constexpr int H = halo_of(Q);
     const int64_t t0 = (int64_t)blockIdx.x * T;
-    window_body<Q, P, B>(src, dst, n, t0 - (int64_t)H * s, s, T, xch, cf);
+    window_body<Q, P, B>(src, dst, n, p, t0 - (int64_t)H * s, s, T, xch, cf);
 }
 
 // Ensemble: one window per workgroup from a descriptor table.
 template <int Q, int P, int B>
-__global__ __launch_bounds__(256) void k_ens(char* base, const WinDesc* __restrict__ desc, Coef cf)
+__global__ __launch_bounds__(kTileLD) void k_ens(char* base, const WinDesc* __restrict__ desc, Coef cf)
 {
     extern __shared__ double xch[];
     const WinDesc d = desc[blockIdx.x];
-    window_body<Q, P, B>(base + d.src_off, base + d.dst_off, d.n, d.start, d.steps, d.valid, xch, cf);
+    window_body<Q, P, B>(base + d.src_off, base + d.dst_off, d.n, d.pitch, d.start, d.steps, d.valid, xch, cf);
 }
 
 // ---------------------------------------------------------------- readout and diagnostics
 
 template <int Q, int P>
-__global__ __launch_bounds__(256) void k_read_rho(const char* __restrict__ st, int64_t n, double* __restrict__ out)
+__global__ __launch_bounds__(256) void k_read_rho(const char* __restrict__ st, int64_t n, int64_t p,
+                                                  double* __restrict__ out)
 {
     using PL = Pol<Q, P>;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j < n) out[j] = PL::density(PL::load(st, n, j));
+    if (j < n) out[j] = PL::density(PL::load(st, p, j));
 }
 
+// out is dense Q x n
 template <int Q, int P>
-__global__ __launch_bounds__(256) void k_read_f(const char* __restrict__ st, int64_t n, double* __restrict__ out,
-                                                int pre, Coef cf)
+__global__ __launch_bounds__(256) void k_read_f(const char* __restrict__ st, int64_t n, int64_t p,
+                                                double* __restrict__ out, int pre, Coef cf)
 {
     using PL = Pol<Q, P>;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     unroll<Q>([&](auto I) {
         const int64_t s = pre ? wrap_site(j - vel(I), n) : j;
-        out[I * n + j] = PL::template pop_g<I>(st, n, s, cf);
+        out[I * n + j] = PL::template pop_g<I>(st, p, s, cf);
     });
 }
 
 template <int Q, int P>
-__global__ __launch_bounds__(256) void k_write_f(char* st, int64_t n, const double* __restrict__ in, Coef cf)
+__global__ __launch_bounds__(256) void k_write_f(char* st, int64_t n, int64_t p, const double* __restrict__ in,
+                                                 Coef cf)
 {
     using PL = Pol<Q, P>;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     double f[Q];
     unroll<Q>([&](auto I) { f[I] = in[I * n + j]; });
-    PL::store(st, n, j, PL::from_f(f, cf));
+    PL::store(st, p, j, PL::from_f(f, cf));
 }
 
 __global__ void k_zero_int(int* p) { *p = 0; }
@@ -510,14 +663,15 @@ constexpr int kDiagBlocks = 256;
 // Stage 1: block b sums the densities of sites b*256 + t + k*65536 (fixed
 // order), then a fixed tree over its 256 threads.
 template <int Q, int P>
-__global__ __launch_bounds__(256) void k_diag1(const char* __restrict__ st, int64_t n, double* partial, int* flag)
+__global__ __launch_bounds__(256) void k_diag1(const char* __restrict__ st, int64_t n, int64_t p, double* partial,
+                                               int* flag)
 {
     using PL = Pol<Q, P>;
     __shared__ double red[256];
     double acc = 0.0;
     bool ok = true;
     for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)kDiagBlocks * 256) {
-        const auto x = PL::load(st, n, j);
+        const auto x = PL::load(st, p, j);
         acc += PL::density(x);
         ok = ok && PL::finite(x);
     }
@@ -557,12 +711,15 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256
         }                                                                \
     } while (0)
 
+int64_t state_pitch(int64_t n) { return (n + 63) / 64 * 64; }
+
 size_t state_copy_bytes(int64_t n, int q, int prec)
 {
+    const size_t p = (size_t)state_pitch(n);
     size_t b;
-    if (prec == kFP64) b = (size_t)q * (size_t)n * 8;
-    else if (prec == kFP32) b = (size_t)q * (size_t)n * 4;
-    else b = (size_t)n * 8 + (size_t)q * (size_t)n * 4;
+    if (prec == kFP64) b = (size_t)q * p * 8;
+    else if (prec == kFP32) b = (size_t)q * p * 4;
+    else b = p * 8 + (size_t)q * p * 4;
     return (b + 255) & ~(size_t)255;
 }
 
@@ -580,7 +737,10 @@ int max_lds_bytes()
     return cached;
 }
 
-int ring_lds_bytes(int q, int lanes) { return 2 * nx_of(q) * lanes * (int)sizeof(double); }
+int ring_max_lanes() { return kRingLD; }
+int tile_lanes() { return kTileLD; }
+int ring_lds_bytes(int q) { return 2 * nx_of(q) * kRingLD * (int)sizeof(double); }
+int tile_lds_bytes(int q) { return 2 * nx_of(q) * kTileLD * (int)sizeof(double); }
 
 template <class K>
 static int prep_lds(K kernel, int bytes)
@@ -596,14 +756,14 @@ static int prep_lds(K kernel, int bytes)
 int launch_init(int q, int prec, void* state, int64_t n, const double* rho0, const Coef& cf, void* stream)
 {
     KSLB_DISPATCH_QP(q, prec, (k_init<Q_, P_><<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(
-                                  (char*)state, n, rho0, cf)));
+                                  (char*)state, n, state_pitch(n), rho0, cf)));
     return (int)hipGetLastError();
 }
 
 int launch_plain(int q, int prec, const void* src, void* dst, int64_t n, const Coef& cf, void* stream)
 {
     KSLB_DISPATCH_QP(q, prec, (k_plain<Q_, P_><<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(
-                                  (const char*)src, (char*)dst, n, cf)));
+                                  (const char*)src, (char*)dst, n, state_pitch(n), cf)));
     return (int)hipGetLastError();
 }
 
@@ -612,10 +772,12 @@ static int ring_one(const void* src, void* dst, int64_t n, int64_t steps, const 
 {
     const int L = (int)(n / B);
     const int lanes = ((L + 63) / 64) * 64;
-    const int lds = ring_lds_bytes(Q, lanes);
+    if (L < 1 || lanes > kRingLD || (int64_t)L * B != n) return (int)hipErrorInvalidValue;
+    const int lds = ring_lds_bytes(Q);
     int e = prep_lds(k_ring<Q, P, B>, lds);
     if (e) return e;
-    k_ring<Q, P, B><<<1, lanes, lds, (hipStream_t)stream>>>((const char*)src, (char*)dst, (int)n, steps, cf);
+    k_ring<Q, P, B><<<1, lanes, lds, (hipStream_t)stream>>>((const char*)src, (char*)dst, (int)n, state_pitch(n),
+                                                           steps, cf);
     return (int)hipGetLastError();
 }
 
@@ -628,52 +790,50 @@ int launch_ring(int q, int prec, int B, const void* src, void* dst, int64_t n, i
 }
 
 template <int Q, int P, int B>
-static int tile_one(const void* src, void* dst, int64_t n, int s, int lanes, const Coef& cf, void* stream)
+static int tile_one(const void* src, void* dst, int64_t n, int s, const Coef& cf, void* stream)
 {
-    const int64_t W = (int64_t)lanes * B;
+    const int64_t W = (int64_t)kTileLD * B;
     const int64_t T = W - 2 * (int64_t)halo_of(Q) * s;
-    if (T <= 0) return (int)hipErrorInvalidValue;
+    if (T <= 0 || s < 1) return (int)hipErrorInvalidValue;
     const int64_t tiles = (n + T - 1) / T;
-    const int lds = ring_lds_bytes(Q, lanes);
+    const int lds = tile_lds_bytes(Q);
     int e = prep_lds(k_tile<Q, P, B>, lds);
     if (e) return e;
-    k_tile<Q, P, B><<<(unsigned)tiles, lanes, lds, (hipStream_t)stream>>>((const char*)src, (char*)dst, n, s, T, cf);
+    k_tile<Q, P, B><<<(unsigned)tiles, kTileLD, lds, (hipStream_t)stream>>>((const char*)src, (char*)dst, n,
+                                                                           state_pitch(n), s, T, cf);
     return (int)hipGetLastError();
 }
 
-int launch_tile(int q, int prec, int B, int lanes, const void* src, void* dst, int64_t n, int s,
-                const Coef& cf, void* stream)
+int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, int s, const Coef& cf,
+                void* stream)
 {
-    if (lanes <= 0 || lanes > 256 || lanes % 64) return (int)hipErrorInvalidValue;
-    if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (tile_one<Q_, P_, 4>(src, dst, n, s, lanes, cf, stream))); }
-    if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (tile_one<Q_, P_, 8>(src, dst, n, s, lanes, cf, stream))); }
+    if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (tile_one<Q_, P_, 4>(src, dst, n, s, cf, stream))); }
+    if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (tile_one<Q_, P_, 8>(src, dst, n, s, cf, stream))); }
     return (int)hipErrorInvalidValue;
 }
 
 template <int Q, int P, int B>
-static int ens_one(char* base, const WinDesc* desc, int nwin, int lanes, const Coef& cf, void* stream)
+static int ens_one(char* base, const WinDesc* desc, int nwin, const Coef& cf, void* stream)
 {
-    const int lds = ring_lds_bytes(Q, lanes);
+    const int lds = tile_lds_bytes(Q);
     int e = prep_lds(k_ens<Q, P, B>, lds);
     if (e) return e;
-    k_ens<Q, P, B><<<(unsigned)nwin, lanes, lds, (hipStream_t)stream>>>(base, desc, cf);
+    k_ens<Q, P, B><<<(unsigned)nwin, kTileLD, lds, (hipStream_t)stream>>>(base, desc, cf);
     return (int)hipGetLastError();
 }
 
-int launch_ens(int q, int prec, int B, int lanes, char* base, const WinDesc* desc, int nwin,
-               const Coef& cf, void* stream)
+int launch_ens(int q, int prec, int B, char* base, const WinDesc* desc, int nwin, const Coef& cf, void* stream)
 {
     if (nwin <= 0) return 0;
-    if (lanes <= 0 || lanes > 256 || lanes % 64) return (int)hipErrorInvalidValue;
-    if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 4>(base, desc, nwin, lanes, cf, stream))); }
-    if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 8>(base, desc, nwin, lanes, cf, stream))); }
+    if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 4>(base, desc, nwin, cf, stream))); }
+    if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 8>(base, desc, nwin, cf, stream))); }
     return (int)hipErrorInvalidValue;
 }
 
 int launch_read_rho(int q, int prec, const void* state, int64_t n, double* out, void* stream)
 {
     KSLB_DISPATCH_QP(q, prec, (k_read_rho<Q_, P_><<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(
-                                  (const char*)state, n, out)));
+                                  (const char*)state, n, state_pitch(n), out)));
     return (int)hipGetLastError();
 }
 
@@ -681,14 +841,14 @@ int launch_read_f(int q, int prec, const void* state, int64_t n, double* out, in
                   void* stream)
 {
     KSLB_DISPATCH_QP(q, prec, (k_read_f<Q_, P_><<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(
-                                  (const char*)state, n, out, pre, cf)));
+                                  (const char*)state, n, state_pitch(n), out, pre, cf)));
     return (int)hipGetLastError();
 }
 
 int launch_write_f(int q, int prec, void* state, int64_t n, const double* in, const Coef& cf, void* stream)
 {
     KSLB_DISPATCH_QP(q, prec, (k_write_f<Q_, P_><<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(
-                                  (char*)state, n, in, cf)));
+                                  (char*)state, n, state_pitch(n), in, cf)));
     return (int)hipGetLastError();
 }
 
@@ -697,7 +857,8 @@ int launch_diag(int q, int prec, const void* state, int64_t n, double* partial, 
 {
     hipStream_t s = (hipStream_t)stream;
     k_zero_int<<<1, 1, 0, s>>>(flag);
-    KSLB_DISPATCH_QP(q, prec, (k_diag1<Q_, P_><<<kDiagBlocks, 256, 0, s>>>((const char*)state, n, partial, flag)));
+    KSLB_DISPATCH_QP(q, prec, (k_diag1<Q_, P_><<<kDiagBlocks, 256, 0, s>>>((const char*)state, n,
+                                                                          state_pitch(n), partial, flag)));
     k_diag2<<<1, 1, 0, s>>>(partial, mass_out);
     return (int)hipGetLastError();
 }

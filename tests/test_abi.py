@@ -50,7 +50,9 @@ def test_state_bytes_and_bad_shapes():
     f = _lib.fn("kslb_state_bytes")
     assert f(4096, 7, 0) == 2 * 4096 * 7 * 8 + 4096
     assert f(4096, 5, 1) == 2 * 4096 * 5 * 4 + 4096
-    assert f(1000, 7, 2) == 2 * ((1000 * 8 + 1000 * 7 * 4 + 255) // 256 * 256) + 4096
+    # rows are padded to a pitch of n rounded up to 64 sites
+    assert f(1000, 7, 2) == 2 * (1024 * 8 + 1024 * 7 * 4) + 4096
+    assert f(1000, 7, 0) == 2 * 1024 * 7 * 8 + 4096
     assert f(0, 7, 0) == 0
     assert f(16, 6, 0) == 0
     assert f(16, 7, 3) == 0

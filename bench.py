@@ -62,7 +62,45 @@ def parse():
     ap.add_argument("--tile-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 1 GiB device buffer 3 times (reference kernel for HBM counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of known size, to scale HBM byte counters."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "copies": 3}), flush=True)
+
+
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1711_03540_amd", "csrc", "kslb_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def measured_traffic(kname: str, workload: str, precision: str):
+    """HBM bytes per dispatch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs
+    (scaled by the copy calibration); None when absent or when the kernel source
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        data = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if sha != data.get("kernel_source_sha256"):
+        return None
+    e = data.get("entries", {}).get("%s/%s/%s" % (kname, workload, precision))
+    if not e:
+        return None
+    return e["fetch_bytes"] + e["write_bytes"]
 
 
 def cpu_baseline(w, tau):
@@ -83,6 +121,9 @@ def cpu_baseline(w, tau):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (got --gpus %d); a domain or an ensemble "
               "would shard across GPUs as described in the design notes, but no multi-GPU path is "
@@ -170,6 +211,10 @@ def main():
         if kernel == "resident":
             roof["cus_used"] = 1
             roof["frac_of_used_cus"] = ach / (PEAK_FP64_VECTOR_TFLOPS / N_CU)
+    roof["traffic"] = measured_traffic(kname, w.name, args.precision)
+    roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    roof["traffic_algorithmic"] = (bytes_per_site_update(w.q, args.precision) * w.n if kernel != "resident"
+                                   else bytes_per_site_update(w.q, args.precision) * w.n)
     roof["kernel"] = kname
     roof["kernel_ms_avg"] = kernel_ms
     roof["algorithmic_per_site_update"] = (flops_per_site_update(w.q) if kernel != "plain"

@@ -210,10 +210,13 @@ kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* 
 kslb_status kslb_ensemble_set_physical(kslb_ensemble* ens, double dX, double dT, double tau,
                                        int dm_variant, int guard_policy, double rho_max);
 
-/* Tiling knobs: sites per lane (4 or 8), lanes per workgroup (256, the only
- * value built) and steps per chunk (>= 1, with 2 max|c| steps < the window);
- * 0 keeps the current value.  Defaults: 8 sites, 256 lanes, 32 steps.      */
-kslb_status kslb_ensemble_set_tiling(kslb_ensemble* ens, int sites_per_lane, int lanes,
+/* Tiling knobs (0 keeps the current value):
+ *   sites_per_lane  4 or 8 (window of 256 lanes x that many sites);
+ *   max_segments    instance tiles one workgroup window may hold, 1..256
+ *                   (1 = one tile per workgroup);
+ *   steps_per_chunk steps per launch, with 2 max|c| steps < the window.
+ * Defaults: 8 sites, 16 segments, 32 steps.                                */
+kslb_status kslb_ensemble_set_tiling(kslb_ensemble* ens, int sites_per_lane, int max_segments,
                                      int steps_per_chunk);
 
 /* The tau in use (after the fit and the guard). */

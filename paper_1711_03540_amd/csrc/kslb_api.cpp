@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -544,13 +545,19 @@ struct kslb_ensemble {
     std::vector<int64_t> step;
     std::vector<char> have_state;
     Physics ph;
-    int B = 8, chunk = 32;
+    int B = 8, chunk = 32, max_seg = 16;
     size_t diag_off = 0;
-    // descriptor tables: two device slots, remembered host contents
-    WinDesc* d_desc[2] = {nullptr, nullptr};
+    // Descriptor tables: two device slots (one per ping-pong parity), each
+    // remembered by the signature of the plan it holds.
+    char* d_tab[2] = {nullptr, nullptr};
     size_t d_cap[2] = {0, 0};
-    std::vector<WinDesc> h_last[2];
+    std::vector<uint64_t> sig[2];
+    int nwin[2] = {0, 0};
     int next_slot = 0;
+    char* h_pin[2] = {nullptr, nullptr};   // pinned staging of each slot's upload
+    size_t h_cap[2] = {0, 0};
+    hipEvent_t up_ev[2] = {nullptr, nullptr};
+    bool up_pending[2] = {false, false};
     double* staging = nullptr;
     int64_t staging_n = 0;
 };
@@ -594,34 +601,160 @@ kslb_status ens_staging(kslb_ensemble* E, int64_t n)
 
 char* ens_state(kslb_ensemble* E, int i) { return E->buf + E->off[i] + (size_t)E->cur[i] * E->copy[i]; }
 
-kslb_status ens_upload(kslb_ensemble* E, const std::vector<WinDesc>& h, WinDesc** dev)
+struct Tile {
+    int inst;
+    int64_t start;
+    int32_t valid;
+    int lanes;
+};
+
+// Build and upload the descriptor tables of one chunk (instances advancing
+// s_i = adv[i] > 0 steps), or reuse a device slot that already holds the same
+// plan.  Tiles of at most W - 2 H s sites (a multiple of B) cut each
+// instance; best-fit-decreasing packs tiles with equal step counts into
+// windows of tile_lanes() lanes and at most max_seg segments.
+kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, const WinHdr** hdr, const SegDesc** seg,
+                     int* nwin)
 {
-    // reuse a table whose contents are already on the device
+    std::vector<uint64_t> key;
+    key.reserve(3 * (size_t)E->count + 3);
+    key.push_back((uint64_t)E->B);
+    key.push_back((uint64_t)E->max_seg);
+    for (int i = 0; i < E->count; i++) {
+        if (adv[i] <= 0) continue;
+        key.push_back((uint64_t)i);
+        key.push_back(((uint64_t)adv[i] << 1) | (uint64_t)E->cur[i]);
+        key.push_back((uint64_t)E->n[i]);
+    }
     for (int k = 0; k < 2; k++) {
-        if (E->d_desc[k] && E->h_last[k].size() == h.size() &&
-            std::memcmp(E->h_last[k].data(), h.data(), h.size() * sizeof(WinDesc)) == 0) {
-            *dev = E->d_desc[k];
+        if (E->d_tab[k] && E->sig[k] == key) {
+            *hdr = reinterpret_cast<const WinHdr*>(E->d_tab[k]);
+            *seg = reinterpret_cast<const SegDesc*>(E->d_tab[k] + sizeof(WinHdr) * (size_t)E->nwin[k]);
+            *nwin = E->nwin[k];
             return KSLB_OK;
         }
     }
+    const int H = halo(E->q);
+    const int B = E->B;
+    const int LANES = tile_lanes();
+    const int64_t W = (int64_t)LANES * B;
+    // tiles grouped by step count
+    std::vector<std::pair<int, Tile>> tiles;   // (steps, tile)
+    for (int i = 0; i < E->count; i++) {
+        const int st = adv[i];
+        if (st <= 0) continue;
+        const int64_t hs = (int64_t)H * st;
+        int64_t tmax = W - 2 * hs;
+        tmax -= tmax % B;
+        const int64_t n = E->n[i];
+        for (int64_t t0 = 0; t0 < n; t0 += tmax) {
+            Tile t;
+            t.inst = i;
+            t.start = t0 - hs;
+            t.valid = (int32_t)std::min<int64_t>(tmax, n - t0);
+            t.lanes = (int)((t.valid + 2 * hs + B - 1) / B);
+            tiles.push_back({st, t});
+        }
+    }
+    std::sort(tiles.begin(), tiles.end(), [](const std::pair<int, Tile>& a, const std::pair<int, Tile>& b) {
+        if (a.first != b.first) return a.first > b.first;
+        return a.second.lanes > b.second.lanes;
+    });
+    struct Win { int steps; int used; std::vector<Tile> t; };
+    std::vector<Win> wins;
+    size_t g0 = 0;
+    while (g0 < tiles.size()) {
+        const int st = tiles[g0].first;
+        size_t g1 = g0;
+        while (g1 < tiles.size() && tiles[g1].first == st) g1++;
+        std::multimap<int, size_t> free_lanes;   // remaining lanes -> window index
+        for (size_t k = g0; k < g1; k++) {
+            const Tile& t = tiles[k].second;
+            auto it = free_lanes.lower_bound(t.lanes);
+            size_t w;
+            if (it == free_lanes.end()) {
+                wins.push_back(Win{st, 0, {}});
+                w = wins.size() - 1;
+            } else {
+                w = it->second;
+                free_lanes.erase(it);
+            }
+            wins[w].t.push_back(t);
+            wins[w].used += t.lanes;
+            const int left = LANES - wins[w].used;
+            if (left >= B && (int)wins[w].t.size() < E->max_seg) free_lanes.insert({left, w});
+        }
+        g0 = g1;
+    }
+    std::vector<WinHdr> hv;
+    std::vector<SegDesc> sv;
+    hv.reserve(wins.size());
+    for (const Win& w : wins) {
+        WinHdr h;
+        h.first_seg = (int32_t)sv.size();
+        h.nseg = (int32_t)w.t.size();
+        h.steps = w.steps;
+        h.pad_ = 0;
+        hv.push_back(h);
+        int lane = 0;
+        for (const Tile& t : w.t) {
+            const int i = t.inst;
+            SegDesc d;
+            d.src_off = (int64_t)(E->off[i] + (size_t)E->cur[i] * E->copy[i]);
+            d.dst_off = (int64_t)(E->off[i] + (size_t)(1 - E->cur[i]) * E->copy[i]);
+            d.n = E->n[i];
+            d.pitch = state_pitch(E->n[i]);
+            d.start = t.start;
+            d.lane_lo = lane;
+            d.valid = t.valid;
+            sv.push_back(d);
+            lane += t.lanes;
+        }
+    }
+    const size_t bytes = sizeof(WinHdr) * hv.size() + sizeof(SegDesc) * sv.size();
     const int k = E->next_slot;
     E->next_slot ^= 1;
-    if (E->d_cap[k] < h.size()) {
-        if (E->d_desc[k]) {
+    if (E->d_cap[k] < bytes) {
+        if (E->d_tab[k]) {
             (void)hipStreamSynchronize(E->stream);
-            (void)hipFree(E->d_desc[k]);
-            E->d_desc[k] = nullptr;
+            (void)hipFree(E->d_tab[k]);
+            E->d_tab[k] = nullptr;
             E->d_cap[k] = 0;
         }
         void* p = nullptr;
-        if (hipMalloc(&p, h.size() * sizeof(WinDesc))) return fail(KSLB_ENOMEM, "descriptor allocation failed");
-        E->d_desc[k] = (WinDesc*)p;
-        E->d_cap[k] = h.size();
+        if (hipMalloc(&p, bytes)) return fail(KSLB_ENOMEM, "descriptor allocation of %zu bytes failed", bytes);
+        E->d_tab[k] = (char*)p;
+        E->d_cap[k] = bytes;
     }
-    int e = hipMemcpyAsync(E->d_desc[k], h.data(), h.size() * sizeof(WinDesc), hipMemcpyHostToDevice, E->stream);
+    // pinned staging: wait for this slot's previous upload before rewriting it
+    if (E->up_pending[k]) {
+        int e = hipEventSynchronize(E->up_ev[k]);
+        if (e) return hip_fail(e, "hipEventSynchronize");
+        E->up_pending[k] = false;
+    }
+    if (E->h_cap[k] < bytes) {
+        if (E->h_pin[k]) (void)hipHostFree(E->h_pin[k]);
+        E->h_pin[k] = nullptr;
+        E->h_cap[k] = 0;
+        void* hp = nullptr;
+        if (hipHostMalloc(&hp, bytes, hipHostMallocDefault)) return fail(KSLB_ENOMEM, "pinned staging allocation failed");
+        E->h_pin[k] = (char*)hp;
+        E->h_cap[k] = bytes;
+    }
+    if (!E->up_ev[k] && hipEventCreateWithFlags(&E->up_ev[k], hipEventDisableTiming))
+        return fail(KSLB_EDEVICE, "hipEventCreate failed");
+    std::memcpy(E->h_pin[k], hv.data(), sizeof(WinHdr) * hv.size());
+    std::memcpy(E->h_pin[k] + sizeof(WinHdr) * hv.size(), sv.data(), sizeof(SegDesc) * sv.size());
+    // stream order keeps earlier kernels reading this slot ahead of the copy
+    int e = hipMemcpyAsync(E->d_tab[k], E->h_pin[k], bytes, hipMemcpyHostToDevice, E->stream);
+    if (!e) e = hipEventRecord(E->up_ev[k], E->stream);
     if (e) return hip_fail(e, "descriptor upload");
-    E->h_last[k] = h;
-    *dev = E->d_desc[k];
+    E->up_pending[k] = true;
+    E->sig[k] = key;
+    E->nwin[k] = (int)hv.size();
+    *hdr = reinterpret_cast<const WinHdr*>(E->d_tab[k]);
+    *seg = reinterpret_cast<const SegDesc*>(E->d_tab[k] + sizeof(WinHdr) * hv.size());
+    *nwin = (int)hv.size();
     return KSLB_OK;
 }
 
@@ -691,17 +824,19 @@ kslb_status kslb_ensemble_get_tau(const kslb_ensemble* E, double* tau)
     return KSLB_OK;
 }
 
-kslb_status kslb_ensemble_set_tiling(kslb_ensemble* E, int sites_per_lane, int lanes, int steps_per_chunk)
+kslb_status kslb_ensemble_set_tiling(kslb_ensemble* E, int sites_per_lane, int max_segments, int steps_per_chunk)
 {
     if (!E) return fail(KSLB_EINVAL, "null ensemble");
     int B = sites_per_lane ? sites_per_lane : E->B;
+    int m = max_segments ? max_segments : E->max_seg;
     int c = steps_per_chunk ? steps_per_chunk : E->chunk;
     if (B != 4 && B != 8) return fail(KSLB_EINVAL, "sites_per_lane must be 4 or 8");
-    if (lanes != 0 && lanes != tile_lanes()) return fail(KSLB_EINVAL, "lanes must be 0 or %d", tile_lanes());
+    if (m < 1 || m > tile_lanes()) return fail(KSLB_EINVAL, "max_segments must lie in [1, %d]", tile_lanes());
     const int64_t W = (int64_t)tile_lanes() * B;
-    if (c < 1 || W - 2 * halo(E->q) * (int64_t)c <= 0)
+    if (c < 1 || W - 2 * halo(E->q) * (int64_t)c < B)
         return fail(KSLB_EINVAL, "steps_per_chunk %d leaves no valid sites in a %lld-site window", c, (long long)W);
     E->B = B;
+    E->max_seg = m;
     E->chunk = c;
     return KSLB_OK;
 }
@@ -752,41 +887,25 @@ kslb_status kslb_ensemble_advance(kslb_ensemble* E, const int64_t* steps)
         if (steps[i] > 0 && !E->have_state[i]) return fail(KSLB_ESTATE, "instance %d has no state", i);
     }
     DeviceGuard g(E->device);
-    const int H = halo(E->q);
-    const int64_t W = (int64_t)tile_lanes() * E->B;
     std::vector<int64_t> left(steps, steps + E->count);
-    std::vector<WinDesc> h;
+    std::vector<int> adv(E->count);
     for (;;) {
-        h.clear();
+        bool any = false;
         for (int i = 0; i < E->count; i++) {
-            if (left[i] <= 0) continue;
-            const int s = (int)std::min<int64_t>(E->chunk, left[i]);
-            const int64_t T = W - 2 * (int64_t)H * s;
-            const int64_t n = E->n[i];
-            const int64_t src = (int64_t)(E->off[i] + (size_t)E->cur[i] * E->copy[i]);
-            const int64_t dst = (int64_t)(E->off[i] + (size_t)(1 - E->cur[i]) * E->copy[i]);
-            for (int64_t t0 = 0; t0 < n; t0 += T) {
-                WinDesc d;
-                d.src_off = src;
-                d.dst_off = dst;
-                d.n = n;
-                d.start = t0 - (int64_t)H * s;
-                d.steps = s;
-                d.valid = (int32_t)std::min<int64_t>(T, n - t0);
-                d.pitch = state_pitch(n);
-                h.push_back(d);
-            }
+            adv[i] = (int)std::min<int64_t>(E->chunk, left[i]);
+            any = any || adv[i] > 0;
         }
-        if (h.empty()) break;
-        WinDesc* dev = nullptr;
-        if (auto s = ens_upload(E, h, &dev)) return s;
-        int e = launch_ens(E->q, E->prec, E->B, E->buf, dev, (int)h.size(), E->ph.cf, E->stream);
+        if (!any) break;
+        const WinHdr* hdr = nullptr;
+        const SegDesc* seg = nullptr;
+        int nwin = 0;
+        if (auto s = ens_plan(E, adv, &hdr, &seg, &nwin)) return s;
+        int e = launch_ens(E->q, E->prec, E->B, E->buf, hdr, seg, nwin, E->ph.cf, E->stream);
         if (e) return hip_fail(e, "ensemble kernel");
         for (int i = 0; i < E->count; i++) {
-            if (left[i] <= 0) continue;
-            const int s = (int)std::min<int64_t>(E->chunk, left[i]);
-            left[i] -= s;
-            E->step[i] += s;
+            if (adv[i] <= 0) continue;
+            left[i] -= adv[i];
+            E->step[i] += adv[i];
             E->cur[i] ^= 1;
         }
     }
@@ -839,8 +958,11 @@ kslb_status kslb_ensemble_destroy(kslb_ensemble* E)
     if (!E) return KSLB_OK;
     DeviceGuard g(E->device);
     (void)hipStreamSynchronize(E->stream);
-    for (int k = 0; k < 2; k++)
-        if (E->d_desc[k]) (void)hipFree(E->d_desc[k]);
+    for (int k = 0; k < 2; k++) {
+        if (E->d_tab[k]) (void)hipFree(E->d_tab[k]);
+        if (E->h_pin[k]) (void)hipHostFree(E->h_pin[k]);
+        if (E->up_ev[k]) (void)hipEventDestroy(E->up_ev[k]);
+    }
     if (E->staging) (void)hipFree(E->staging);
     delete E;
     return KSLB_OK;

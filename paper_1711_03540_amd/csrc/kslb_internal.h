@@ -44,10 +44,6 @@ size_t state_copy_bytes(int64_t n, int q, int prec);
 // ---------------------------------------------------------------------------
 // kernel launchers (kslb_kernels.hip).  All return a hipError_t as int.
 // ---------------------------------------------------------------------------
-struct LaunchCtx {
-    void* stream;     // hipStream_t
-};
-
 // lanes and LDS bytes of the ring (one workgroup per lattice) and tile kernels
 int ring_max_lanes();
 int tile_lanes();
@@ -71,17 +67,24 @@ int launch_write_f(int q, int prec, void* state, int64_t n, const double* in, co
 int launch_diag(int q, int prec, const void* state, int64_t n, double* partial, int* flag,
                 double* mass_out, void* stream);
 
-// ensemble: one window per workgroup, read from a device descriptor table
-struct WinDesc {
+// ensemble: one window per workgroup; a window holds one or more segments,
+// each a tile of one instance on a consecutive range of lanes.
+struct WinHdr {
+    int32_t first_seg;  // index of the window's first segment
+    int32_t nseg;       // segments in the window (>= 1)
+    int32_t steps;      // steps every segment of the window advances
+    int32_t pad_;
+};
+struct SegDesc {
     int64_t src_off;    // byte offset of the instance's source state copy
     int64_t dst_off;    // byte offset of the destination state copy
     int64_t n;          // sites of the instance
-    int64_t start;      // first site of the window (may be negative: periodic)
-    int32_t steps;      // steps this window advances
-    int32_t valid;      // sites written back, from start + halo
     int64_t pitch;      // row pitch of the instance (state_pitch(n))
+    int64_t start;      // site of the segment's first slot (may be negative: periodic)
+    int32_t lane_lo;    // first lane of the segment
+    int32_t valid;      // sites written back, from slot H * steps on
 };
-int launch_ens(int q, int prec, int B, char* base, const WinDesc* desc, int nwin,
+int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegDesc* seg, int nwin,
                const Coef& cf, void* stream);
 
 }  // namespace kslb

@@ -560,63 +560,75 @@ __global__ __launch_bounds__(kRingLD) void k_ring(const char* __restrict__ src, 
     }
 }
 
-// One halo-widened window of W = B * LD sites starting at site `ws`
-// (periodic modulo n), advanced `s` steps in registers; the `valid` sites from
-// ws + H s on are written back.  Sites near the window ends go stale by H per
-// step and are never stored.  Launched with LD lanes.
+// One lane's part of a halo-widened window.  The lane holds sites j0 .. j0+B-1
+// of a periodic lattice of n sites (taken modulo n), which are slots
+// kl0 .. kl0+B-1 of its segment; after s steps the slots [k_lo, k_lo + valid)
+// of the segment are exact and are written back (slots near a segment's
+// ends go stale by H per step and are never stored).  Every lane of the
+// workgroup calls this (it holds the barriers).
 template <int Q, int P, int B>
-__device__ __forceinline__ void window_body(const char* __restrict__ src, char* __restrict__ dst,
-                                            int64_t n, int64_t p, int64_t ws, int s, int64_t valid,
-                                            double* xch, const Coef& cf)
+__device__ __forceinline__ void window_lane(const char* __restrict__ src, char* __restrict__ dst, int64_t n,
+                                            int64_t p, int64_t j0, int64_t kl0, int64_t k_lo, int64_t valid,
+                                            int s, double* xch, const Coef& cf)
 {
     using E = Engine<Q, P, B, kTileLD>;
     constexpr int L = kTileLD;
     const int lane = threadIdx.x;
     typename E::Site x[B];
-    constexpr int64_t W = (int64_t)L * B;
-    const int64_t j0 = ws + (int64_t)lane * B;
-    if (ws >= 0 && ws + W <= n) {
-        if (kVecIO<P> && ws % B == 0) E::PL::template load_vec<B>(src, p, j0, x);
-        else unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, p, j0 + Bi); });
+    const bool inside = j0 >= 0 && j0 + B <= n;
+    if (kVecIO<P> && inside && j0 % B == 0) {
+        E::PL::template load_vec<B>(src, p, j0, x);
+    } else if (inside) {
+        unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, p, j0 + Bi); });
     } else {
         unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, p, wrap_site(j0 + Bi, n)); });
     }
     const int left = lane == 0 ? L - 1 : lane - 1;
     const int right = lane + 1 == L ? 0 : lane + 1;
     E::run(x, s, xch, lane, left, right, true, cf);
-    const int64_t k_lo = (int64_t)E::H * s;
-    const int64_t k0 = (int64_t)lane * B;
-    if (kVecIO<P> && k0 >= k_lo && k0 + B <= k_lo + valid && j0 + B <= n && j0 % B == 0) {
+    if (kVecIO<P> && kl0 >= k_lo && kl0 + B <= k_lo + valid && inside && j0 % B == 0) {
         E::PL::template store_vec<B>(dst, p, j0, x);
     } else {
         unroll<B>([&](auto Bi) {
-            const int64_t k = k0 + Bi;
-            if (k >= k_lo && k < k_lo + valid) {
-                const int64_t j = ws + k;
-                if (j < n) E::PL::store(dst, p, j, x[Bi]);
-            }
+            const int64_t k = kl0 + Bi;
+            const int64_t j = j0 + Bi;      // >= 0 for every stored slot
+            if (k >= k_lo && k < k_lo + valid && j < n) E::PL::store(dst, p, j, x[Bi]);
         });
     }
 }
 
-// Large periodic lattice: tile t writes sites [t T, t T + T).
+// Large periodic lattice: tile t writes sites [t T, t T + T) from a window of
+// B * 256 sites starting H s sites earlier.
 template <int Q, int P, int B>
 __global__ __launch_bounds__(kTileLD) void k_tile(const char* __restrict__ src, char* __restrict__ dst,
                                                   int64_t n, int64_t p, int s, int64_t T, Coef cf)
 {
     extern __shared__ double xch[];
     constexpr int H = halo_of(Q);
-    const int64_t t0 = (int64_t)blockIdx.x * T;
-    window_body<Q, P, B>(src, dst, n, p, t0 - (int64_t)H * s, s, T, xch, cf);
+    const int64_t ws = (int64_t)blockIdx.x * T - (int64_t)H * s;
+    const int64_t kl0 = (int64_t)threadIdx.x * B;
+    window_lane<Q, P, B>(src, dst, n, p, ws + kl0, kl0, (int64_t)H * s, T, s, xch, cf);
 }
 
-// Ensemble: one window per workgroup from a descriptor table.
+// Ensemble: workgroup w runs window hdr[w], whose segments seg[first ..
+// first + nseg) occupy consecutive lane ranges; each segment is one tile of
+// one instance with its own halo, so several small instances share a window.
+// Lanes past the last segment's tile carry junk that is never stored.
 template <int Q, int P, int B>
-__global__ __launch_bounds__(kTileLD) void k_ens(char* base, const WinDesc* __restrict__ desc, Coef cf)
+__global__ __launch_bounds__(kTileLD) void k_ens(char* base, const WinHdr* __restrict__ hdr,
+                                                 const SegDesc* __restrict__ seg, Coef cf)
 {
     extern __shared__ double xch[];
-    const WinDesc d = desc[blockIdx.x];
-    window_body<Q, P, B>(base + d.src_off, base + d.dst_off, d.n, d.pitch, d.start, d.steps, d.valid, xch, cf);
+    constexpr int H = halo_of(Q);
+    const WinHdr h = hdr[blockIdx.x];
+    const int lane = threadIdx.x;
+    int my = 0;
+    for (int k = 1; k < h.nseg; k++)
+        if (seg[h.first_seg + k].lane_lo <= lane) my = k;
+    const SegDesc d = seg[h.first_seg + my];
+    const int64_t kl0 = (int64_t)(lane - d.lane_lo) * B;
+    window_lane<Q, P, B>(base + d.src_off, base + d.dst_off, d.n, d.pitch, d.start + kl0, kl0,
+                         (int64_t)H * h.steps, d.valid, h.steps, xch, cf);
 }
 
 // ---------------------------------------------------------------- readout and diagnostics
@@ -742,15 +754,35 @@ int tile_lanes() { return kTileLD; }
 int ring_lds_bytes(int q) { return 2 * nx_of(q) * kRingLD * (int)sizeof(double); }
 int tile_lds_bytes(int q) { return 2 * nx_of(q) * kTileLD * (int)sizeof(double); }
 
+// Raise a kernel's dynamic LDS limit above 64 KiB, once per kernel and size
+// (the attribute is per function).
+static int prep_lds_fn(const void* fn, int bytes)
+{
+    static const void* done_fn[64] = {};
+    static int done_bytes[64] = {};
+    if (bytes <= 65536) return 0;
+    int slot = -1;
+    for (int i = 0; i < 64; i++) {
+        if (done_fn[i] == fn) {
+            if (done_bytes[i] >= bytes) return 0;
+            slot = i;
+            break;
+        }
+        if (!done_fn[i] && slot < 0) slot = i;
+    }
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return (int)e;
+    if (slot >= 0) {
+        done_fn[slot] = fn;
+        done_bytes[slot] = bytes;
+    }
+    return 0;
+}
+
 template <class K>
 static int prep_lds(K kernel, int bytes)
 {
-    if (bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        if (e != hipSuccess) return (int)e;
-    }
-    return 0;
+    return prep_lds_fn(reinterpret_cast<const void*>(kernel), bytes);
 }
 
 int launch_init(int q, int prec, void* state, int64_t n, const double* rho0, const Coef& cf, void* stream)
@@ -813,20 +845,21 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
 }
 
 template <int Q, int P, int B>
-static int ens_one(char* base, const WinDesc* desc, int nwin, const Coef& cf, void* stream)
+static int ens_one(char* base, const WinHdr* hdr, const SegDesc* seg, int nwin, const Coef& cf, void* stream)
 {
     const int lds = tile_lds_bytes(Q);
     int e = prep_lds(k_ens<Q, P, B>, lds);
     if (e) return e;
-    k_ens<Q, P, B><<<(unsigned)nwin, kTileLD, lds, (hipStream_t)stream>>>(base, desc, cf);
+    k_ens<Q, P, B><<<(unsigned)nwin, kTileLD, lds, (hipStream_t)stream>>>(base, hdr, seg, cf);
     return (int)hipGetLastError();
 }
 
-int launch_ens(int q, int prec, int B, char* base, const WinDesc* desc, int nwin, const Coef& cf, void* stream)
+int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegDesc* seg, int nwin,
+               const Coef& cf, void* stream)
 {
     if (nwin <= 0) return 0;
-    if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 4>(base, desc, nwin, cf, stream))); }
-    if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 8>(base, desc, nwin, cf, stream))); }
+    if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 4>(base, hdr, seg, nwin, cf, stream))); }
+    if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 8>(base, hdr, seg, nwin, cf, stream))); }
     return (int)hipErrorInvalidValue;
 }
 

@@ -231,6 +231,31 @@ def test_ensemble_matches_oracle_and_single_lattices():
         assert ens.status(i) == (steps[i], False)
 
 
+@pytest.mark.parametrize("q,prec", [(7, "fp64"), (5, "fp64"), (7, "split"), (5, "fp32")])
+def test_ensemble_packing_and_chunking_bitwise(q, prec):
+    # packed windows (several instance tiles per workgroup), one tile per
+    # workgroup, 4 or 8 sites per lane and any chunk length give the same bits
+    say("case ensemble packing q=%d %s" % (q, prec))
+    sizes = [5, 100, 333, 640, 1500, 2048, 3001, 7777]
+    steps = [40, 77, 64, 5, 100, 31, 64, 90]
+    dX, dT = 0.2, 1e-4
+    rho0s = [ic(n, dX, 50 + i) for i, n in enumerate(sizes)]
+    outs = []
+    for B, segs, chunk in ((8, 16, 32), (8, 1, 32), (4, 16, 16), (8, 256, 7), (8, 3, 40)):
+        ens = Ensemble(sizes, q, prec).set_physical(dX, dT, 1.1).set_tiling(B, segs, chunk)
+        for i, r in enumerate(rho0s):
+            ens.init_rho(i, r)
+        ens.advance(steps)
+        outs.append([ens.rho(i) for i in range(len(sizes))])
+    for o in outs[1:]:
+        for i in range(len(sizes)):
+            assert np.array_equal(o[i], outs[0][i]), i
+    if prec == "fp64":
+        for i, n in enumerate(sizes):
+            ref = oracle.solve_periodic(q, rho0s[i], dX, dT, 1.1, steps[i])
+            assert rel(outs[0][i], ref) < TOL64
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split"])
 def test_checkpoint_resume_bitwise(prec):
     say("case resume %s" % prec)

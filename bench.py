@@ -48,6 +48,8 @@ WORKLOADS = {
     "d1q7_n4096": ("CFG_RESIDENT_Q7", "resident"),
     "d1q5_n256": ("CFG_SMALL_Q5", "resident"),
     "d1q7_n16m": ("CFG_LARGE_Q7", "tiled"),
+    "ensemble": (None, None),
+    "serve": (None, None),
 }
 
 
@@ -62,6 +64,11 @@ def parse():
     ap.add_argument("--tile-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--instances", type=int, default=4096, help="ensemble workload: instances")
+    ap.add_argument("--lb-steps", type=int, default=20000, help="ensemble workload: LB steps per instance")
+    ap.add_argument("--chunk", type=int, default=0, help="ensemble/serve: steps per launch (0 = default)")
+    ap.add_argument("--segments", type=int, default=0, help="ensemble: instance tiles per window (0 = default)")
+    ap.add_argument("--requests", type=int, default=2000, help="serve workload: requests")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -119,6 +126,82 @@ def cpu_baseline(w, tau):
             "sample": sample + ", plain C FP64 oracle, %.2f s" % dt}
 
 
+def bench_ensemble(args):
+    """Ragged ensemble: D1Q7 instances, N log-uniform in [512, 8192], dX = pi/16, dT = 1e-4,
+    fitted tau, `--lb-steps` steps each; throughput against the plain one-step kernel."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03540_amd import inputs
+    from paper_1711_03540_amd.ensemble import Ensemble
+    from paper_1711_03540_amd.lattice import Lattice
+
+    dev = torch.device("cuda:0")
+    sizes = inputs.ensemble_shapes(args.instances, seed=2)
+    dX, dT = math.pi / 16, 1e-4
+    ens = Ensemble(sizes, 7, args.precision, device=dev).set_physical(dX, dT, 0.0)
+    ens.set_tiling(0, args.segments, args.chunk)
+    rho0 = [torch.tensor(inputs.random_modes_ic(int(n), n * dX, seed=1000 + i), device=dev)
+            for i, n in enumerate(sizes)]
+    steps = np.full(len(sizes), args.lb_steps, dtype=np.int64)
+    su = float(np.sum(sizes)) * args.lb_steps
+
+    def solve():
+        for i, r in enumerate(rho0):
+            ens.init_rho(i, r)
+        ens.advance(steps)
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        solve()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    value = su * args.steps / sum(times) / 1e9
+    # plain one-step kernel, one instance of the mean size (bitwise-identical arithmetic)
+    nm = int(np.mean(sizes))
+    lat = Lattice(nm, 7, args.precision, device=dev).set_physical(dX, dT, 0.0).set_kernel("plain")
+    lat.init_rho(inputs.random_modes_ic(nm, nm * dX, seed=7)).advance(200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.advance(2000)
+    torch.cuda.synchronize()
+    plain = nm * 2000 / (time.perf_counter() - t0) / 1e9
+    out = {"workload": "ensemble_d1q7_%d" % len(sizes), "precision": args.precision, "value": value,
+           "unit": "GLUPS", "ms_per_solve": 1e3 * sum(times) / len(times), "site_updates_per_solve": su,
+           "instances": len(sizes), "mean_n": float(np.mean(sizes)), "lb_steps": args.lb_steps,
+           "plain_one_instance_glups": plain, "speedup_vs_plain": value / plain, "tau": ens.tau}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Served request stream: Poisson arrivals at 2000/s, D1Q5/D1Q7, N log-uniform in
+    [256, 65536], 10^3..10^5 steps, FP32 (split storage) or FP64, dX = pi/16, dT = 1e-4."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03540_amd import inputs
+    from paper_1711_03540_amd.serve import SolveServer
+
+    dev = torch.device("cuda:0")
+    dX, dT = math.pi / 16, 1e-4
+    reqs = inputs.request_stream(args.requests, seed=3)
+    init = [torch.tensor(inputs.random_modes_ic(r.n, r.n * dX, seed=r.seed % (1 << 63)), device=dev)
+            for r in reqs]
+    srv = SolveServer(dX, dT, chunk=args.chunk or 32, device=dev)
+    warm = inputs.request_stream(8, seed=99, steps_lo=1000, steps_hi=1000)
+    srv.serve(warm, [torch.tensor(inputs.random_modes_ic(r.n, r.n * dX, seed=5), device=dev) for r in warm],
+              realtime=False)
+    st = srv.serve(reqs, init, realtime=True)
+    out = {"workload": "serve_%d_requests" % len(reqs), "offered_glups": float(
+        sum(r.n * r.steps for r in reqs) / reqs[-1].arrival / 1e9)}
+    out.update(st.summary())
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -129,6 +212,12 @@ def main():
               "would shard across GPUs as described in the design notes, but no multi-GPU path is "
               "built." % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "ensemble":
+        bench_ensemble(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
+        return
     import numpy as np
     import torch
 

@@ -256,6 +256,29 @@ def test_ensemble_packing_and_chunking_bitwise(q, prec):
             assert rel(outs[0][i], ref) < TOL64
 
 
+def test_served_results_equal_solo_solves():
+    # continuous batching: requests of both schemes and precisions arrive while
+    # others run; each result equals the same solve run alone (bitwise)
+    say("case serving alone vs mix")
+    import torch
+    from paper_1711_03540_amd.inputs import request_stream
+    from paper_1711_03540_amd.serve import SERVE_PRECISION, SolveServer
+    dX, dT = math.pi / 16, 1e-4
+    reqs = request_stream(40, seed=17, rate=20000.0, n_lo=64, n_hi=6000, steps_lo=50, steps_hi=1500)
+    init = [torch.tensor(random_modes_ic(r.n, r.n * dX, seed=r.seed % 1000003, n_modes=min(16, r.n // 2)),
+                         device="cuda") for r in reqs]
+    srv = SolveServer(dX, dT, slots=6, capacity=6000, chunk=24, round_steps=100)
+    stats = srv.serve(reqs, init, realtime=True)
+    summ = stats.summary()
+    say("serve summary", summ)
+    assert summ["completed"] == len(reqs)
+    assert summ["p99_ms"] >= summ["p50_ms"] > 0
+    for i, r in enumerate(reqs):
+        lat = Lattice(r.n, r.q, SERVE_PRECISION[r.precision]).set_physical(dX, dT, 0.0).set_kernel("plain")
+        lat.init_rho(init[i]).advance(r.steps)
+        assert torch.equal(stats.results[i].rho, lat.read_rho()), i
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split"])
 def test_checkpoint_resume_bitwise(prec):
     say("case resume %s" % prec)

@@ -45,8 +45,8 @@ def bytes_per_site_update(q: int, precision: str) -> int:
 
 
 WORKLOADS = {
-    "d1q7_n4096": ("CFG_RESIDENT_Q7", "resident"),
-    "d1q5_n256": ("CFG_SMALL_Q5", "resident"),
+    "d1q7_n4096": ("CFG_RESIDENT_Q7", "span"),
+    "d1q5_n256": ("CFG_SMALL_Q5", "span"),
     "d1q7_n16m": ("CFG_LARGE_Q7", "tiled"),
     "ensemble": (None, None),
     "serve": (None, None),
@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2, help="untimed solves")
     ap.add_argument("--workload", default="d1q7_n4096", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "split"])
-    ap.add_argument("--kernel", default=None, choices=["resident", "tiled", "plain"])
+    ap.add_argument("--kernel", default=None, choices=["span", "resident", "tiled", "plain"])
     ap.add_argument("--tile-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -102,10 +102,8 @@ def measured_traffic(kname: str, workload: str, precision: str):
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if sha != data.get("kernel_source_sha256"):
-        return None
     e = data.get("entries", {}).get("%s/%s/%s" % (kname, workload, precision))
-    if not e:
+    if not e or e.get("kernel_source_sha256") != sha:
         return None
     return e["fetch_bytes"] + e["write_bytes"]
 
@@ -275,10 +273,10 @@ def main():
         raise SystemExit("bench: non-finite state")
 
     # launches per advance and the dominant kernel's average duration
-    if kernel == "resident":
+    if kernel in ("resident", "span"):
         launches = max(1, math.ceil(w.steps / (1 << 20)))
         units = w.n * w.steps / launches
-        kname = "k_ring"
+        kname = "k_ring" if kernel == "resident" else "k_span"
     elif kernel == "tiled":
         s = args.tile_steps or (256 * 8) // (16 * (2 if w.q == 5 else 3))
         launches = math.ceil(w.steps / s)
@@ -297,9 +295,21 @@ def main():
         ach = flops_per_site_update(w.q) * units / (kernel_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": None}
-        if kernel == "resident":
-            roof["cus_used"] = 1
-            roof["frac_of_used_cus"] = ach / (PEAK_FP64_VECTOR_TFLOPS / N_CU)
+        if kernel in ("resident", "span"):
+            # execution resources the launch can use: one workgroup of 8 waves
+            # on one CU (4 SIMDs) for resident; one single-wave owner of
+            # 256 - 2 H s sites per workgroup, each on one SIMD, for span
+            if kernel == "resident":
+                simds = 4
+            else:
+                h = 2 if w.q == 5 else 3
+                s_ex = args.tile_steps or next(s for s in range(256 // (3 * h), 0, -1)
+                                               if w.n // math.ceil(w.n / (256 - 2 * h * s)) >= h * s)
+                simds = math.ceil(w.n / (256 - 2 * h * s_ex))
+                roof["steps_between_exchanges"] = s_ex
+                roof["workgroups"] = simds
+            roof["simds_used"] = simds
+            roof["frac_of_used_simds"] = ach / (PEAK_FP64_VECTOR_TFLOPS * simds / (4 * N_CU))
     roof["traffic"] = measured_traffic(kname, w.name, args.precision)
     roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["traffic_algorithmic"] = (bytes_per_site_update(w.q, args.precision) * w.n if kernel != "resident"

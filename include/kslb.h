@@ -25,9 +25,10 @@
  *   - The stored state is the post-collision one; the density after n steps
  *     is rho_j = sum_i f_i(j) of the paper's f at time n.
  *   - Device memory and HIP streams belong to the caller.  The library never
- *     frees a caller buffer.  It allocates only small descriptor tables and,
- *     when a host pointer is passed to a transfer call, one device staging
- *     buffer of Q * n_sites doubles that lives until destroy.
+ *     frees a caller buffer.  It allocates only small descriptor tables, the
+ *     exchange area of the SPAN kernel (four edges of H s sites per
+ *     workgroup) and, when a host pointer is passed to a transfer call, one
+ *     device staging buffer of Q * n_sites doubles; all live until destroy.
  *   - Every function returns a kslb_status (0 = OK, < 0 = error) and never
  *     aborts or throws; kslb_last_error() describes the last failure of the
  *     calling thread.  Work enqueued on the stream is asynchronous; a device
@@ -77,15 +78,22 @@ enum { KSLB_DM_DERIVED = 0, KSLB_DM_LITERAL = 1 };
 enum { KSLB_GUARD_REFUSE = 0, KSLB_GUARD_RAISE_TAU = 1, KSLB_GUARD_OFF = 2 };
 
 /* Kernel class used by kslb_advance.
- *   AUTO     : the library's choice (resident ring when the lattice fits one
- *              workgroup's registers, otherwise temporally blocked tiles).
+ *   AUTO     : the library's choice: SPAN for lattices of up to 65536 sites
+ *              that it can split, else RESIDENT when the lattice fits one
+ *              workgroup's registers, else TILED.
  *   PLAIN    : one fused stream+collide step per launch (HBM ping-pong).
  *   RESIDENT : one workgroup holds the whole lattice in registers for all
  *              steps; needs n_sites = B * L with B in {4, 8}, L <= 512.
  *   TILED    : halo-widened tiles, several steps per launch in registers.
+ *   SPAN     : one launch for all steps; single-wave workgroups each own a
+ *              slice in registers and swap edge sites with their two
+ *              neighbours every steps_per_launch steps (default: the
+ *              largest s with 3 max|c| s <= 256, 28 for D1Q7) through
+ *              a small library-owned exchange area; for lattices of about
+ *              2 to 2000 slices of (256 - 2 H s) sites.
  * All classes give bitwise identical results.                              */
 enum { KSLB_KERNEL_AUTO = 0, KSLB_KERNEL_PLAIN = 1, KSLB_KERNEL_RESIDENT = 2,
-       KSLB_KERNEL_TILED = 3 };
+       KSLB_KERNEL_TILED = 3, KSLB_KERNEL_SPAN = 4 };
 
 /* ---------------------------------------------------------------------- */
 /* Host-only parameter functions (no device work).                         */
@@ -151,9 +159,9 @@ kslb_status kslb_set_coefficients(kslb_lattice* lat, const double* E, const doub
 kslb_status kslb_get_coefficients(const kslb_lattice* lat, double* E, double* G, double* omega,
                                   double* tau, double* jkm);
 
-/* Choose the kernel class and, for TILED, the steps per launch (0 = the
- * library's default).  RESIDENT/TILED requests that the shape cannot use
- * return EINVAL.                                                           */
+/* Choose the kernel class and, for TILED, the steps per launch (for SPAN,
+ * the steps between edge exchanges); 0 = the library's default.  Requests
+ * that the shape cannot use return EINVAL.                                 */
 kslb_status kslb_set_kernel(kslb_lattice* lat, int kernel, int steps_per_launch);
 
 /* f := feq(rho) at every site, step counter := 0.  rho: n_sites doubles on

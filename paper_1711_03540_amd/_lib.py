@@ -18,9 +18,9 @@ FP64, FP32, SPLIT = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "split": SPLIT}
 DM_DERIVED, DM_LITERAL = 0, 1
 GUARD_REFUSE, GUARD_RAISE_TAU, GUARD_OFF = 0, 1, 2
-KERNEL_AUTO, KERNEL_PLAIN, KERNEL_RESIDENT, KERNEL_TILED = 0, 1, 2, 3
+KERNEL_AUTO, KERNEL_PLAIN, KERNEL_RESIDENT, KERNEL_TILED, KERNEL_SPAN = 0, 1, 2, 3, 4
 KERNELS = {"auto": KERNEL_AUTO, "plain": KERNEL_PLAIN, "resident": KERNEL_RESIDENT,
-           "tiled": KERNEL_TILED}
+           "tiled": KERNEL_TILED, "span": KERNEL_SPAN}
 
 _ERRNAMES = {KSLB_EINVAL: "EINVAL", KSLB_ENOMEM: "ENOMEM", KSLB_EDEVICE: "EDEVICE",
              KSLB_ESTATE: "ESTATE", KSLB_EUNSTABLE: "EUNSTABLE", KSLB_ENONFINITE: "ENONFINITE"}

@@ -136,6 +136,10 @@ struct kslb_lattice {
     int tile_steps = 0;
     int64_t step = 0;
     double* staging = nullptr;         // Q x n doubles, only for host transfers
+    char* span_scratch = nullptr;      // edges + flags of the multi-workgroup kernel
+    size_t span_bytes = 0;
+    int span_last_nwg = 0;             // geometry of the last multi-workgroup launch
+    int64_t span_last_ecopy = 0;
 
     char* state() { return buf + (size_t)cur * copy; }
     char* other() { return buf + (size_t)(1 - cur) * copy; }
@@ -171,6 +175,37 @@ int ring_sites_per_lane(int64_t n, int q)
 }
 
 constexpr int kTileB = 8;
+// Default steps between edge exchanges of the SPAN kernel: the largest s
+// whose owners still hold H s sites (256 >= 3 H s), or less when the lattice
+// is too small for that.
+int span_default_steps(int64_t n, int q);
+
+// Multi-workgroup plan: nwg owners of about n / nwg sites each, every window
+// (own sites + 2 H s halo) within span_lanes() x span_sites_per_lane() slots,
+// every owner at least H s sites.  Returns nwg, or 0 when the shape cannot use it.
+int span_plan(int64_t n, int q, int s)
+{
+    const int64_t W = (int64_t)span_lanes() * span_sites_per_lane();
+    const int64_t hs = (int64_t)halo(q) * s;
+    const int64_t own = W - 2 * hs;
+    if (s < 1 || own < hs) return 0;
+    const int64_t nwg = (n + own - 1) / own;
+    if (nwg < 2 || nwg > 2048) return 0;
+    if (n / nwg < hs) return 0;
+    return (int)nwg;
+}
+
+int span_default_steps(int64_t n, int q)
+{
+    const int64_t W = (int64_t)span_lanes() * span_sites_per_lane();
+    for (int s = (int)(W / (3 * halo(q))); s >= 1; s--)
+        if (span_plan(n, q, s)) return s;
+    return 0;
+}
+
+// AUTO: one lattice small enough for a few hundred single-wave owners runs
+// on SPAN; otherwise RESIDENT when it fits one workgroup, else TILED.
+constexpr int64_t kSpanAutoMaxSites = 65536;
 
 // Steps per tiled launch: halo overhead 2 H s <= W / 8, rounded down to a
 // multiple of 8 so that every window starts on an 8-site boundary.
@@ -303,13 +338,19 @@ kslb_status kslb_get_coefficients(const kslb_lattice* L, double* E, double* G, d
 kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
 {
     if (auto s = check_lat(L)) return s;
-    if (kernel < KSLB_KERNEL_AUTO || kernel > KSLB_KERNEL_TILED) return fail(KSLB_EINVAL, "bad kernel %d", kernel);
+    if (kernel < KSLB_KERNEL_AUTO || kernel > KSLB_KERNEL_SPAN) return fail(KSLB_EINVAL, "bad kernel %d", kernel);
     if (steps_per_launch < 0) return fail(KSLB_EINVAL, "steps_per_launch must be >= 0");
     if (kernel == KSLB_KERNEL_RESIDENT) {
         DeviceGuard g(L->device);
         if (!ring_sites_per_lane(L->n, L->q))
             return fail(KSLB_EINVAL, "n=%lld cannot use the resident kernel (needs n = B*L, B in {4,8}, L <= 512)",
                         (long long)L->n);
+    }
+    if (kernel == KSLB_KERNEL_SPAN) {
+        const int sp = steps_per_launch > 0 ? steps_per_launch : span_default_steps(L->n, L->q);
+        if (!sp || !span_plan(L->n, L->q, sp))
+            return fail(KSLB_EINVAL, "n=%lld cannot be split over workgroups with %d steps between exchanges",
+                        (long long)L->n, sp);
     }
     if (kernel == KSLB_KERNEL_TILED && steps_per_launch > 0) {
         if (tile_lanes() * kTileB - 2 * halo(L->q) * steps_per_launch <= 0)
@@ -354,13 +395,46 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
     DeviceGuard g(L->device);
     int kernel = L->kernel;
     const int ringB = ring_sites_per_lane(L->n, L->q);
-    if (kernel == KSLB_KERNEL_AUTO) kernel = ringB ? KSLB_KERNEL_RESIDENT : KSLB_KERNEL_TILED;
+    int span_s = 0;
+    if (kernel == KSLB_KERNEL_AUTO) {
+        if (L->n <= kSpanAutoMaxSites && (span_s = span_default_steps(L->n, L->q)) > 0) kernel = KSLB_KERNEL_SPAN;
+        else kernel = ringB ? KSLB_KERNEL_RESIDENT : KSLB_KERNEL_TILED;
+    }
     int e = 0;
     if (kernel == KSLB_KERNEL_PLAIN) {
         for (int64_t s = 0; s < n_steps; s++) {
             e = launch_plain(L->q, L->prec, L->state(), L->other(), L->n, L->ph.cf, L->stream);
             if (e) return hip_fail(e, "plain kernel");
             L->cur ^= 1;
+        }
+    } else if (kernel == KSLB_KERNEL_SPAN) {
+        const int sp = (L->kernel == KSLB_KERNEL_SPAN && L->tile_steps > 0) ? L->tile_steps
+                                                                             : span_default_steps(L->n, L->q);
+        const int nwg = sp ? span_plan(L->n, L->q, sp) : 0;
+        if (!nwg) return fail(KSLB_EINVAL, "shape cannot use the multi-workgroup kernel");
+        L->span_last_nwg = nwg;
+        L->span_last_ecopy = span_edge_copy_bytes(L->q, L->prec, halo(L->q) * sp);
+        const int64_t ecopy = span_edge_copy_bytes(L->q, L->prec, halo(L->q) * sp);
+        const size_t need = (size_t)(4 * nwg) * (size_t)ecopy + 256 + sizeof(int) * (size_t)(nwg + 1);
+        if (L->span_bytes < need) {
+            if (L->span_scratch) {
+                (void)hipStreamSynchronize(L->stream);
+                (void)hipFree(L->span_scratch);
+                L->span_scratch = nullptr;
+                L->span_bytes = 0;
+            }
+            void* p = nullptr;
+            if (hipMalloc(&p, need)) return fail(KSLB_ENOMEM, "exchange area of %zu bytes failed", need);
+            L->span_scratch = (char*)p;
+            L->span_bytes = need;
+        }
+        int* flags = reinterpret_cast<int*>(L->span_scratch + (size_t)(4 * nwg) * (size_t)ecopy);
+        const int64_t chunk = int64_t(1) << 20;
+        for (int64_t done = 0; done < n_steps; done += chunk) {
+            const int64_t s = std::min(chunk, n_steps - done);
+            e = launch_span(L->q, L->prec, L->state(), L->n, nwg, s, sp, L->span_scratch, ecopy, flags,
+                            flags + nwg, L->ph.cf, L->stream);
+            if (e) return hip_fail(e, "multi-workgroup kernel");
         }
     } else if (kernel == KSLB_KERNEL_RESIDENT) {
         if (!ringB) return fail(KSLB_EINVAL, "shape cannot use the resident kernel");
@@ -511,16 +585,29 @@ kslb_status kslb_diagnostics(kslb_lattice* L, double* mass, int* nonfinite)
     if (e) return hip_fail(e, "diagnostics copy");
     if (mass) *mass = m;
     if (nonfinite) *nonfinite = f;
+    if (L->span_scratch) {
+        // the abort word follows the flags of the last multi-workgroup launch
+        int ab = 0;
+        const int nwg = L->span_last_nwg;
+        if (nwg) {
+            const int64_t ecopy = L->span_last_ecopy;
+            const int* abort_d = reinterpret_cast<const int*>(L->span_scratch + (size_t)(4 * nwg) * (size_t)ecopy) + nwg;
+            e = hipMemcpy(&ab, abort_d, sizeof ab, hipMemcpyDeviceToHost);
+            if (e) return hip_fail(e, "abort word copy");
+            if (ab) return fail(KSLB_EDEVICE, "a multi-workgroup launch timed out waiting for a neighbour");
+        }
+    }
     return KSLB_OK;
 }
 
 kslb_status kslb_destroy(kslb_lattice* L)
 {
     if (!L) return KSLB_OK;
-    if (L->staging) {
+    if (L->staging || L->span_scratch) {
         DeviceGuard g(L->device);
         (void)hipStreamSynchronize(L->stream);
-        (void)hipFree(L->staging);
+        if (L->staging) (void)hipFree(L->staging);
+        if (L->span_scratch) (void)hipFree(L->span_scratch);
     }
     delete L;
     return KSLB_OK;

@@ -59,6 +59,13 @@ int launch_ring(int q, int prec, int B, const void* src, void* dst, int64_t n, i
                 const Coef& cf, void* stream);
 int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, int s,
                 const Coef& cf, void* stream);
+// one small lattice over nwg single-wave workgroups exchanging edges every s
+// steps; flags has nwg + 1 ints (the last is the abort word), in place on state
+int span_lanes();
+int span_sites_per_lane();
+int64_t span_edge_copy_bytes(int q, int prec, int hs);
+int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase,
+                int64_t ecopy, int* flags, int* abort, const Coef& cf, void* stream);
 int launch_read_rho(int q, int prec, const void* state, int64_t n, double* out, void* stream);
 int launch_read_f(int q, int prec, const void* state, int64_t n, double* out, int pre,
                   const Coef& cf, void* stream);

@@ -469,21 +469,11 @@ struct Engine {
         });
     }
 
-    // one step x -> y: registers plus the neighbours' published values;
-    // left/right point at the neighbours' columns of the slot
-    __device__ static __forceinline__ void step(const Site (&x)[B], Site (&y)[B], const double* left,
-                                                const double* right, const Coef& cf)
+    // one step x -> y from registers plus hv, the values pulled from the
+    // neighbour lanes (hv[koff(i) + t] as published by publish_vals)
+    __device__ static __forceinline__ void step_hv(const Site (&x)[B], Site (&y)[B], const double (&hv)[NX],
+                                                   const Coef& cf)
     {
-        double hv[NX];
-        unroll<Q - 1>([&](auto I1) {
-            constexpr int i = I1 + 1;
-            constexpr int c = vel(i);
-            constexpr int k0 = koff(i);
-            unroll<iabs(c)>([&](auto T) {
-                constexpr int t = T;
-                hv[k0 + t] = (c > 0 ? left : right)[(k0 + t) * LD];
-            });
-        });
         unroll<B>([&](auto Bi) {
             constexpr int b = Bi;
             double g[Q];
@@ -499,6 +489,56 @@ struct Engine {
         });
     }
 
+    // one step x -> y: left/right point at the neighbours' columns of the slot
+    __device__ static __forceinline__ void step(const Site (&x)[B], Site (&y)[B], const double* left,
+                                                const double* right, const Coef& cf)
+    {
+        double hv[NX];
+        unroll<Q - 1>([&](auto I1) {
+            constexpr int i = I1 + 1;
+            constexpr int c = vel(i);
+            constexpr int k0 = koff(i);
+            unroll<iabs(c)>([&](auto T) {
+                constexpr int t = T;
+                hv[k0 + t] = (c > 0 ? left : right)[(k0 + t) * LD];
+            });
+        });
+        step_hv(x, y, hv, cf);
+    }
+
+    // Single-wave windows: the neighbour values move between lanes with DPP
+    // wave rotations (lane l reads lane l-1 for c > 0, lane l+1 for c < 0),
+    // with no LDS round trip and no barrier.
+    __device__ static __forceinline__ double from_lane(double v, bool from_left)
+    {
+        const int lo = __double2loint(v), hi = __double2hiint(v);
+        int rlo, rhi;
+        if (from_left) {
+            rlo = __builtin_amdgcn_update_dpp(0, lo, 0x13C, 0xF, 0xF, false);   // wave_ror:1
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x13C, 0xF, 0xF, false);
+        } else {
+            rlo = __builtin_amdgcn_update_dpp(0, lo, 0x134, 0xF, 0xF, false);   // wave_rol:1
+            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x134, 0xF, 0xF, false);
+        }
+        return __hiloint2double(rhi, rlo);
+    }
+
+    __device__ static __forceinline__ void step_dpp(const Site (&x)[B], Site (&y)[B], const Coef& cf)
+    {
+        double hv[NX];
+        unroll<Q - 1>([&](auto I1) {
+            constexpr int i = I1 + 1;
+            constexpr int c = vel(i);
+            constexpr int k0 = koff(i);
+            unroll<iabs(c)>([&](auto T) {
+                constexpr int t = T;
+                constexpr int src = (c > 0) ? (B - c + t) : t;
+                hv[k0 + t] = from_lane(PL::template pop<i>(x[src], cf), c > 0);
+            });
+        });
+        step_hv(x, y, hv, cf);
+    }
+
     // `steps` steps in place on x, lanes `lane` with neighbour lanes left/right;
     // every lane of the workgroup must call this (it holds the barriers).
     __device__ static __forceinline__ void run(Site (&x)[B], int64_t steps, double* xch, int lane, int left,
@@ -506,6 +546,19 @@ struct Engine {
     {
         Site y[B];
         int64_t st = 0;
+        if constexpr (LD == 64) {
+            // one wave: lanes are neighbours modulo 64, exchange by DPP
+            (void)xch; (void)lane; (void)left; (void)right; (void)active;
+            for (; st + 1 < steps; st += 2) {
+                step_dpp(x, y, cf);
+                step_dpp(y, x, cf);
+            }
+            if (st < steps) {
+                step_dpp(x, y, cf);
+                unroll<B>([&](auto Bi) { x[Bi] = y[Bi]; });
+            }
+            return;
+        }
         for (; st + 1 < steps; st += 2) {
             if (active) publish(x, xch + lane, cf);
             __syncthreads();
@@ -629,6 +682,118 @@ __global__ __launch_bounds__(kTileLD) void k_ens(char* base, const WinHdr* __res
     const int64_t kl0 = (int64_t)(lane - d.lane_lo) * B;
     window_lane<Q, P, B>(base + d.src_off, base + d.dst_off, d.n, d.pitch, d.start + kl0, kl0,
                          (int64_t)H * h.steps, d.valid, h.steps, xch, cf);
+}
+
+// ---------------------------------------------------------------- one lattice over many workgroups
+
+constexpr int kSpanLD = 64;      // one wave per workgroup: no s_barrier stalls
+constexpr int kSpanB = 4;
+constexpr int kSpinLimit = 1 << 21;
+
+// Flag handshake of the multi-workgroup kernel.  Signal: a release fence
+// (this wave's edge stores become visible at device scope) and a relaxed
+// store of the chunk count.  Wait: relaxed polls of both neighbours' flags,
+// then one acquire fence; a bounded number of polls, after which the abort
+// word is raised and every waiter gives up.
+__device__ __forceinline__ void span_signal(int* flag, int value, int lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool span_wait(const int* fa, const int* fb, int target, int* abort, int lane)
+{
+    for (int spin = 0;; spin++) {
+        const int a = __hip_atomic_load(fa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int b = __hip_atomic_load(fb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_readfirstlane(a) >= target && __builtin_amdgcn_readfirstlane(b) >= target) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return true;
+        }
+        const int ab = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_readfirstlane(ab) || spin >= kSpinLimit) {
+            if (lane == 0) __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Workgroup w owns sites [o_w, o_w + M_w) of a periodic lattice and holds
+// them, plus H s halo sites on each side, in its registers (slot k <-> site
+// o_w - H s + k).  Every s steps it publishes its first and last H s own sites
+// to a double-buffered edge area, raises its flag to the chunk count, waits for
+// both neighbours' flags, and refreshes its halo slots from their edges.  The
+// final state is written in place: a workgroup stores only after both
+// neighbours finished every chunk, so no initial load can see it.  Each wait
+// is bounded; on timeout a workgroup raises `abort` and every workgroup stops.
+template <int Q, int P>
+__global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t n, int64_t p, int nwg,
+                                                  int64_t steps, int s, char* __restrict__ ebase, int64_t ecopy,
+                                                  int64_t epitch, int* __restrict__ flags, int* __restrict__ abort,
+                                                  Coef cf)
+{
+    using E = Engine<Q, P, kSpanB, kSpanLD>;
+    using PL = typename E::PL;
+    constexpr int B = kSpanB;
+    double* xch = nullptr;   // single wave: the engine exchanges by DPP
+    // consecutive owners share an XCD (workgroups are dealt round-robin to 8 XCDs)
+    const int per = (nwg + 7) / 8;
+    const int w = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (w >= nwg) return;
+    const int left_w = w == 0 ? nwg - 1 : w - 1;
+    const int right_w = w + 1 == nwg ? 0 : w + 1;
+    const int64_t o = n * w / nwg;
+    const int64_t M = n * (w + 1) / nwg - o;
+    const int hs = E::H * s;
+    const int lane = threadIdx.x;
+    const int left = lane == 0 ? kSpanLD - 1 : lane - 1;
+    const int right = lane + 1 == kSpanLD ? 0 : lane + 1;
+    auto edge = [&](int64_t chunk, int who, int side) { return ebase + (((chunk & 1) * nwg + who) * 2 + side) * ecopy; };
+
+    typename E::Site x[B];
+    unroll<B>([&](auto Bi) {
+        const int64_t k = (int64_t)lane * B + Bi;
+        x[Bi] = PL::load(st, p, wrap_site(o - hs + k, n));
+    });
+    bool ok = true;
+    int64_t done = 0;
+    for (int64_t c = 0; done < steps; c++) {
+        const int sc = (int)(steps - done < s ? steps - done : s);
+        E::run(x, sc, xch, lane, left, right, true, cf);
+        done += sc;
+        if (done >= steps) break;
+        // publish own edges
+        unroll<B>([&](auto Bi) {
+            const int64_t k = (int64_t)lane * B + Bi;
+            if (k >= hs && k < 2 * hs) PL::store(edge(c, w, 0), epitch, k - hs, x[Bi]);
+            if (k >= M && k < M + hs) PL::store(edge(c, w, 1), epitch, k - M, x[Bi]);
+        });
+        span_signal(flags + w, (int)(c + 1), lane);
+        ok = span_wait(flags + left_w, flags + right_w, (int)(c + 1), abort, lane);
+        if (!ok) break;
+        // refresh the halo slots from the neighbours' edges
+        unroll<B>([&](auto Bi) {
+            const int64_t k = (int64_t)lane * B + Bi;
+            if (k < hs) x[Bi] = PL::load(edge(c, left_w, 1), epitch, k);
+            else if (k >= hs + M && k < 2 * hs + M) x[Bi] = PL::load(edge(c, right_w, 0), epitch, k - hs - M);
+        });
+    }
+    if (!ok) return;
+    // final state: only after both neighbours have finished every chunk
+    const int total = (int)((steps + s - 1) / s);
+    span_signal(flags + w, total, lane);
+    if (!span_wait(flags + left_w, flags + right_w, total, abort, lane)) return;
+    unroll<B>([&](auto Bi) {
+        const int64_t k = (int64_t)lane * B + Bi;
+        if (k >= hs && k < hs + M) PL::store(st, p, o + k - hs, x[Bi]);
+    });
+}
+
+__global__ void k_zero_ints(int* p, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
 }
 
 // ---------------------------------------------------------------- readout and diagnostics
@@ -861,6 +1026,31 @@ int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegD
     if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 4>(base, hdr, seg, nwin, cf, stream))); }
     if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 8>(base, hdr, seg, nwin, cf, stream))); }
     return (int)hipErrorInvalidValue;
+}
+
+int span_lanes() { return kSpanLD; }
+int span_sites_per_lane() { return kSpanB; }
+int64_t span_edge_copy_bytes(int q, int prec, int hs) { return (int64_t)state_copy_bytes(state_pitch(hs), q, prec); }
+
+int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase,
+                int64_t ecopy, int* flags, int* abort, const Coef& cf, void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    const int h = halo_of(q);
+    const int64_t hs = (int64_t)h * s;
+    const int64_t W = (int64_t)kSpanLD * kSpanB;
+    if (nwg < 2 || s < 1 || steps < 1) return (int)hipErrorInvalidValue;
+    // every owner holds at least H s sites and its window fits
+    const int64_t mmin = n / nwg, mmax = (n + nwg - 1) / nwg;
+    if (mmin < hs || mmax + 2 * hs > W) return (int)hipErrorInvalidValue;
+    k_zero_ints<<<(nwg + 1 + 255) / 256, 256, 0, st>>>(flags, nwg + 1);   // flags then abort word
+    const int per = (nwg + 7) / 8;
+    const unsigned grid = (unsigned)(per * 8);
+    const int64_t epitch = state_pitch(hs);
+    KSLB_DISPATCH_QP(q, prec, (k_span<Q_, P_><<<grid, kSpanLD, 0, st>>>((char*)state, n, state_pitch(n), nwg, steps,
+                                                                        s, ebase, ecopy, epitch, flags, abort, cf)));
+    (void)abort;
+    return (int)hipGetLastError();
 }
 
 int launch_read_rho(int q, int prec, const void* state, int64_t n, double* out, void* stream)

@@ -52,16 +52,16 @@ SIZES = [1, 2, 3, 7, 64, 256, 1000, 1001, 4096, 70001]
 
 @pytest.mark.parametrize("q", [5, 7])
 @pytest.mark.parametrize("n", SIZES)
-@pytest.mark.parametrize("kernel", ["plain", "tiled", "resident", "auto"])
+@pytest.mark.parametrize("kernel", ["plain", "tiled", "resident", "span", "auto"])
 def test_fp64_parity(q, n, kernel):
     dX, dT, tau, steps = 0.2, 1e-4, 1.1, 700
     say("case fp64 parity q=%d n=%d kernel=%s" % (q, n, kernel))
     lat = make(q, n, kernel="plain", dX=dX, dT=dT, tau=tau)
-    if kernel == "resident":
+    if kernel in ("resident", "span"):
         try:
-            lat.set_kernel("resident")
+            lat.set_kernel(kernel)
         except Exception:
-            pytest.skip("n=%d cannot use the resident kernel" % n)
+            pytest.skip("n=%d cannot use the %s kernel" % (n, kernel))
     else:
         lat.set_kernel(kernel)
     coef = oracle.coefficients(q, dX, dT, tau)
@@ -81,7 +81,8 @@ def test_kernel_classes_bitwise_identical(q, n):
     say("case bitwise q=%d n=%d" % (q, n))
     rho0 = ic(n, 0.2, 9)
     outs = []
-    for kernel, spl in (("plain", 0), ("tiled", 0), ("tiled", 7), ("tiled", 1), ("resident", 0)):
+    for kernel, spl in (("plain", 0), ("tiled", 0), ("tiled", 7), ("tiled", 1), ("resident", 0), ("span", 0),
+                        ("span", 5), ("span", 24)):
         lat = make(q, n, kernel="plain")
         try:
             lat.set_kernel(kernel, spl)
@@ -95,7 +96,7 @@ def test_kernel_classes_bitwise_identical(q, n):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "split"])
-@pytest.mark.parametrize("kernel", ["plain", "tiled", "resident"])
+@pytest.mark.parametrize("kernel", ["plain", "tiled", "resident", "span"])
 def test_reduced_precision_kernels_bitwise_identical(prec, kernel):
     say("case bitwise %s %s" % (prec, kernel))
     n = 4096
@@ -134,6 +135,24 @@ def test_resident_config_in_bench_launch():
     assert rel(lat.rho(), rho_ref) < TOL64
     coef = oracle.coefficients(w.q, w.dX, w.dT, tau)
     assert rel(lat.f(), oracle.collide(w.q, coef, tau, f_ref)) < TOL64
+
+
+@pytest.mark.parametrize("spl", [8, 16, 24])
+def test_span_kernel_in_bench_shape(spl):
+    # D1Q7, N = 4096, the multi-workgroup kernel with s steps between edge exchanges
+    w = CFG_RESIDENT_Q7
+    say("case span n=4096 s=%d" % spl)
+    rho0 = w.rho0()
+    lat = Lattice(w.n, w.q, "fp64").set_physical(w.dX, w.dT, 0.0).set_kernel("span", spl)
+    tau = lat.coefficients()["tau"]
+    lat.init_rho(rho0).advance(2001)
+    mass, bad = lat.diagnostics()          # raises if a workgroup timed out
+    assert not bad
+    ref = oracle.solve_periodic(w.q, rho0, w.dX, w.dT, tau, 2001)
+    assert rel(lat.rho(), ref) < TOL64
+    plain = Lattice(w.n, w.q, "fp64").set_physical(w.dX, w.dT, 0.0).set_kernel("plain")
+    plain.init_rho(rho0).advance(2001)
+    assert np.array_equal(lat.f(), plain.f())
 
 
 def test_resident_config_full_length():

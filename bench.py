@@ -50,6 +50,7 @@ WORKLOADS = {
     "d1q7_n16m": ("CFG_LARGE_Q7", "tiled"),
     "ensemble": (None, None),
     "serve": (None, None),
+    "table3": (None, None),
 }
 
 
@@ -200,6 +201,76 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_table3(args):
+    """The Table 3 travelling wave (fixed ends) on the GPU, both schemes.
+
+    For dX in {0.2, 0.1, 0.05} and a sweep of dT: tau = the paper's fit, raised
+    by the stability guard where the fit is linearly unstable; solve to T = 0.5;
+    G of section 3 against the analytic solution; GPU time of the solve.  Then,
+    as in section 3, the D1Q5 plateau accuracy (its best G over the sweep,
+    allowing 10 %) is matched by the largest-dT D1Q7 run at least as accurate,
+    and the costs of the two runs are compared (the paper's Table 4 measured
+    the same ratio on one CPU core)."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03540_amd import inputs
+    from paper_1711_03540_amd.lattice import Lattice, tau_fit
+
+    dev = torch.device("cuda:0")
+    T_end = 0.5
+    lo, hi = inputs.table3_ends()
+    runs = []
+    for dX in (0.2, 0.1, 0.05):
+        n = inputs.table3_sites(dX)
+        X = np.arange(n) * dX
+        rho0 = torch.tensor(inputs.table3_profile(X, 0.0), device=dev)
+        exact = inputs.table3_profile(X, T_end)
+        for q in (5, 7):
+            for dT in (1e-6, 2e-6, 5e-6, 1e-5, 2e-5, 5e-5, 1e-4, 2e-4, 5e-4, 1e-3):
+                steps = int(round(T_end / dT))
+                if steps > 600_000 or steps < 50:
+                    continue
+                try:
+                    lat = Lattice(n, q, "fp64", device=dev).set_physical(dX, dT, 0.0, guard="raise", rho_max=4.5)
+                except Exception as e:
+                    runs.append({"dX": dX, "q": q, "dT": dT, "error": str(e)})
+                    continue
+                lat.set_fixed_ends(lo, hi).init_rho(rho0)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(lat.stream)
+                lat.advance(steps)
+                e1.record(lat.stream)
+                rho = lat.rho()
+                ms = e0.elapsed_time(e1)
+                ok = bool(np.all(np.isfinite(rho)) and np.max(np.abs(rho)) < 1e3)
+                G = float(np.sum(np.abs(rho - exact)) / np.sum(np.abs(exact))) if ok else None
+                runs.append({"dX": dX, "q": q, "dT": dT, "tau": lat.coefficients()["tau"],
+                             "tau_fit": tau_fit(q, dX, dT),
+                             "steps": steps, "G": G, "gpu_ms": ms})
+                print(json.dumps(runs[-1]), file=sys.stderr, flush=True)
+    matched = []
+    for dX in (0.2, 0.1, 0.05):
+        r5 = [r for r in runs if r["dX"] == dX and r["q"] == 5 and r.get("G")]
+        r7 = [r for r in runs if r["dX"] == dX and r["q"] == 7 and r.get("G")]
+        if not r5 or not r7:
+            continue
+        plateau = min(r["G"] for r in r5)
+        a = max((r for r in r5 if r["G"] <= 1.1 * plateau), key=lambda r: r["dT"])
+        cands = [r for r in r7 if r["G"] <= a["G"]]
+        if not cands:
+            continue
+        b = max(cands, key=lambda r: r["dT"])
+        matched.append({"dX": dX, "G_target": a["G"], "d1q5": {"dT": a["dT"], "tau": a["tau"], "G": a["G"],
+                        "steps": a["steps"], "gpu_ms": a["gpu_ms"]},
+                        "d1q7": {"dT": b["dT"], "tau": b["tau"], "G": b["G"], "steps": b["steps"],
+                                 "gpu_ms": b["gpu_ms"]},
+                        "step_ratio": a["steps"] / b["steps"], "gpu_time_ratio": a["gpu_ms"] / b["gpu_ms"],
+                        "saving_pct": 100.0 * (1.0 - b["gpu_ms"] / a["gpu_ms"])})
+    print(json.dumps({"workload": "table3_fixed_ends", "T_end": T_end, "runs": runs, "matched": matched}), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -215,6 +286,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "table3":
+        bench_table3(args)
         return
     import numpy as np
     import torch

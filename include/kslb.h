@@ -164,6 +164,16 @@ kslb_status kslb_get_coefficients(const kslb_lattice* lat, double* E, double* G,
  * that the shape cannot use return EINVAL.                                 */
 kslb_status kslb_set_kernel(kslb_lattice* lat, int kernel, int steps_per_launch);
 
+/* Boundary of the lattice.  KSLB_PERIODIC (default) or KSLB_FIXED_ENDS: the
+ * problem of the paper's Table 3, sites 0 and n_sites-1 held at the
+ * equilibrium of rho_left / rho_right, and a population streamed from beyond
+ * an end taking that end's equilibrium value (the ends and max|c| ghost
+ * sites beyond them are reset after every streaming; the paper gives only
+ * the end values).  Fixed ends run on the PLAIN and SPAN kernels.  Set it
+ * before kslb_init_rho, which then also imposes the end states.           */
+enum { KSLB_PERIODIC = 0, KSLB_FIXED_ENDS = 1 };
+kslb_status kslb_set_boundary(kslb_lattice* lat, int mode, double rho_left, double rho_right);
+
 /* f := feq(rho) at every site, step counter := 0.  rho: n_sites doubles on
  * the device (rho_on_device = 1) or the host.  Host input synchronises.    */
 kslb_status kslb_init_rho(kslb_lattice* lat, const double* rho, int rho_on_device);

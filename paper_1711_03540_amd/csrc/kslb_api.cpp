@@ -138,6 +138,8 @@ struct kslb_lattice {
     double* staging = nullptr;         // Q x n doubles, only for host transfers
     char* span_scratch = nullptr;      // edges + flags of the multi-workgroup kernel
     size_t span_bytes = 0;
+    bool fixed = false;                // fixed-end boundary (Table 3 problem)
+    Ends ends{0.0, 0.0};
     int span_last_nwg = 0;             // geometry of the last multi-workgroup launch
     int64_t span_last_ecopy = 0;
 
@@ -361,6 +363,21 @@ kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
     return KSLB_OK;
 }
 
+kslb_status kslb_set_boundary(kslb_lattice* L, int mode, double rho_left, double rho_right)
+{
+    if (auto s = check_lat(L)) return s;
+    if (mode == KSLB_PERIODIC) {
+        L->fixed = false;
+        return KSLB_OK;
+    }
+    if (mode != KSLB_FIXED_ENDS) return fail(KSLB_EINVAL, "bad boundary mode %d", mode);
+    if (!std::isfinite(rho_left) || !std::isfinite(rho_right)) return fail(KSLB_EINVAL, "non-finite end value");
+    if (L->n < 3) return fail(KSLB_EINVAL, "fixed ends need at least 3 sites");
+    L->fixed = true;
+    L->ends = Ends{rho_left, rho_right};
+    return KSLB_OK;
+}
+
 kslb_status kslb_init_rho(kslb_lattice* L, const double* rho, int rho_on_device)
 {
     if (auto s = check_lat(L)) return s;
@@ -375,7 +392,8 @@ kslb_status kslb_init_rho(kslb_lattice* L, const double* rho, int rho_on_device)
         src = L->staging;
     }
     L->cur = 0;
-    int e = launch_init(L->q, L->prec, L->state(), L->n, src, L->ph.cf, L->stream);
+    int e = L->fixed ? launch_init_fixed(L->q, L->prec, L->state(), L->n, src, L->ph.cf, L->ends, L->stream)
+                     : launch_init(L->q, L->prec, L->state(), L->n, src, L->ph.cf, L->stream);
     if (e) return hip_fail(e, "init kernel");
     if (!rho_on_device) {
         e = hipStreamSynchronize(L->stream);
@@ -398,10 +416,19 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
     int span_s = 0;
     if (kernel == KSLB_KERNEL_AUTO) {
         if (L->n <= kSpanAutoMaxSites && (span_s = span_default_steps(L->n, L->q)) > 0) kernel = KSLB_KERNEL_SPAN;
+        else if (L->fixed) kernel = KSLB_KERNEL_PLAIN;
         else kernel = ringB ? KSLB_KERNEL_RESIDENT : KSLB_KERNEL_TILED;
     }
+    if (L->fixed && kernel != KSLB_KERNEL_PLAIN && kernel != KSLB_KERNEL_SPAN)
+        return fail(KSLB_EINVAL, "fixed ends run on the PLAIN and SPAN kernels only");
     int e = 0;
-    if (kernel == KSLB_KERNEL_PLAIN) {
+    if (kernel == KSLB_KERNEL_PLAIN && L->fixed) {
+        for (int64_t s = 0; s < n_steps; s++) {
+            e = launch_plain_fixed(L->q, L->prec, L->state(), L->other(), L->n, L->ph.cf, L->ends, L->stream);
+            if (e) return hip_fail(e, "plain kernel");
+            L->cur ^= 1;
+        }
+    } else if (kernel == KSLB_KERNEL_PLAIN) {
         for (int64_t s = 0; s < n_steps; s++) {
             e = launch_plain(L->q, L->prec, L->state(), L->other(), L->n, L->ph.cf, L->stream);
             if (e) return hip_fail(e, "plain kernel");
@@ -433,7 +460,7 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
         for (int64_t done = 0; done < n_steps; done += chunk) {
             const int64_t s = std::min(chunk, n_steps - done);
             e = launch_span(L->q, L->prec, L->state(), L->n, nwg, s, sp, L->span_scratch, ecopy, flags,
-                            flags + nwg, L->ph.cf, L->stream);
+                            flags + nwg, L->ph.cf, L->stream, L->fixed ? &L->ends : nullptr);
             if (e) return hip_fail(e, "multi-workgroup kernel");
         }
     } else if (kernel == KSLB_KERNEL_RESIDENT) {

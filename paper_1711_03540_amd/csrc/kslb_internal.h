@@ -64,8 +64,16 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
 int span_lanes();
 int span_sites_per_lane();
 int64_t span_edge_copy_bytes(int q, int prec, int hs);
+// fixed-end boundary values (NULL / absent = periodic)
+struct Ends {
+    double rho_l, rho_r;
+};
 int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase,
-                int64_t ecopy, int* flags, int* abort, const Coef& cf, void* stream);
+                int64_t ecopy, int* flags, int* abort, const Coef& cf, void* stream, const Ends* ends);
+int launch_plain_fixed(int q, int prec, const void* src, void* dst, int64_t n, const Coef& cf, const Ends& ends,
+                       void* stream);
+int launch_init_fixed(int q, int prec, void* state, int64_t n, const double* rho0, const Coef& cf, const Ends& ends,
+                      void* stream);
 int launch_read_rho(int q, int prec, const void* state, int64_t n, double* out, void* stream);
 int launch_read_f(int q, int prec, const void* state, int64_t n, double* out, int pre,
                   const Coef& cf, void* stream);

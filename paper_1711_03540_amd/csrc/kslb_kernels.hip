@@ -441,6 +441,42 @@ __global__ __launch_bounds__(256) void k_plain(const char* __restrict__ src, cha
     PL::store(dst, p, j, y);
 }
 
+// Fixed ends (the Table 3 problem of section 3): sites 0 and n-1 and the
+// ghosts beyond them hold the end-value equilibria; a streamed population
+// from beyond an end is that end's equilibrium value.
+template <int Q, int P>
+__global__ __launch_bounds__(256) void k_plain_fixed(const char* __restrict__ src, char* __restrict__ dst,
+                                                     int64_t n, int64_t p, Coef cf, double rho_l, double rho_r)
+{
+    using PL = Pol<Q, P>;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    if (j == 0 || j == n - 1) {
+        PL::store(dst, p, j, PL::equilibrium(j == 0 ? rho_l : rho_r, cf));
+        return;
+    }
+    const auto eq_l = PL::equilibrium(rho_l, cf), eq_r = PL::equilibrium(rho_r, cf);
+    double g[Q];
+    unroll<Q>([&](auto I) {
+        const int64_t sj = j - vel(I);
+        if (sj < 0) g[I] = PL::template pop<I>(eq_l, cf);
+        else if (sj >= n) g[I] = PL::template pop<I>(eq_r, cf);
+        else g[I] = PL::template pop_g<I>(src, p, sj, cf);
+    });
+    typename PL::Site y;
+    PL::update(g, y, cf);
+    PL::store(dst, p, j, y);
+}
+
+template <int Q, int P>
+__global__ __launch_bounds__(256) void k_init_fixed(char* st, int64_t n, int64_t p, const double* __restrict__ rho0,
+                                                    Coef cf, double rho_l, double rho_r)
+{
+    using PL = Pol<Q, P>;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < n) PL::store(st, p, j, PL::equilibrium(j == 0 ? rho_l : (j == n - 1 ? rho_r : rho0[j]), cf));
+}
+
 // ---------------------------------------------------------------- register-resident step engine
 
 // LD = lanes stride of the exchange area (compile time, so every LDS address
@@ -541,8 +577,15 @@ struct Engine {
 
     // `steps` steps in place on x, lanes `lane` with neighbour lanes left/right;
     // every lane of the workgroup must call this (it holds the barriers).
+    struct NoFix {
+        __device__ __forceinline__ void operator()(Site (&)[B]) const {}
+    };
+
+    // fix(x) runs after every step (the fixed-end boundary of section 3's
+    // Table 3 problem re-imposes its end states there); NoFix for periodic.
+    template <class Fix = NoFix>
     __device__ static __forceinline__ void run(Site (&x)[B], int64_t steps, double* xch, int lane, int left,
-                                               int right, bool active, const Coef& cf)
+                                               int right, bool active, const Coef& cf, const Fix& fix = Fix())
     {
         Site y[B];
         int64_t st = 0;
@@ -551,11 +594,14 @@ struct Engine {
             (void)xch; (void)lane; (void)left; (void)right; (void)active;
             for (; st + 1 < steps; st += 2) {
                 step_dpp(x, y, cf);
+                fix(y);
                 step_dpp(y, x, cf);
+                fix(x);
             }
             if (st < steps) {
                 step_dpp(x, y, cf);
                 unroll<B>([&](auto Bi) { x[Bi] = y[Bi]; });
+                fix(x);
             }
             return;
         }
@@ -727,11 +773,11 @@ __device__ __forceinline__ bool span_wait(const int* fa, const int* fb, int targ
 // final state is written in place: a workgroup stores only after both
 // neighbours finished every chunk, so no initial load can see it.  Each wait
 // is bounded; on timeout a workgroup raises `abort` and every workgroup stops.
-template <int Q, int P>
+template <int Q, int P, bool FIX>
 __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t n, int64_t p, int nwg,
                                                   int64_t steps, int s, char* __restrict__ ebase, int64_t ecopy,
                                                   int64_t epitch, int* __restrict__ flags, int* __restrict__ abort,
-                                                  Coef cf)
+                                                  Coef cf, double rho_l, double rho_r)
 {
     using E = Engine<Q, P, kSpanB, kSpanLD>;
     using PL = typename E::PL;
@@ -756,11 +802,28 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
         const int64_t k = (int64_t)lane * B + Bi;
         x[Bi] = PL::load(st, p, wrap_site(o - hs + k, n));
     });
+    // fixed ends: sites <= 0 and >= n-1 (boundary sites and the ghosts
+    // beyond them) hold the end-value equilibria after every step; only the
+    // owners whose window reaches an end apply it
+    const int64_t j0 = o - hs + (int64_t)lane * B;
+    const bool touches = FIX && (o - hs <= 0 || o + M + hs >= n - 1);
+    const typename E::Site eq_l = PL::equilibrium(rho_l, cf), eq_r = PL::equilibrium(rho_r, cf);
+    auto fix = [&](typename E::Site (&y)[B]) {
+        if (touches) {
+            unroll<B>([&](auto Bi) {
+                const int64_t j = j0 + Bi;
+                if (j <= 0) y[Bi] = eq_l;
+                else if (j >= n - 1) y[Bi] = eq_r;
+            });
+        }
+    };
+    if constexpr (FIX) fix(x);
     bool ok = true;
     int64_t done = 0;
     for (int64_t c = 0; done < steps; c++) {
         const int sc = (int)(steps - done < s ? steps - done : s);
-        E::run(x, sc, xch, lane, left, right, true, cf);
+        if constexpr (FIX) E::run(x, sc, xch, lane, left, right, true, cf, fix);
+        else E::run(x, sc, xch, lane, left, right, true, cf);
         done += sc;
         if (done >= steps) break;
         // publish own edges
@@ -778,6 +841,7 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
             if (k < hs) x[Bi] = PL::load(edge(c, left_w, 1), epitch, k);
             else if (k >= hs + M && k < 2 * hs + M) x[Bi] = PL::load(edge(c, right_w, 0), epitch, k - hs - M);
         });
+        if constexpr (FIX) fix(x);
     }
     if (!ok) return;
     // final state: only after both neighbours have finished every chunk
@@ -1033,7 +1097,7 @@ int span_sites_per_lane() { return kSpanB; }
 int64_t span_edge_copy_bytes(int q, int prec, int hs) { return (int64_t)state_copy_bytes(state_pitch(hs), q, prec); }
 
 int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase,
-                int64_t ecopy, int* flags, int* abort, const Coef& cf, void* stream)
+                int64_t ecopy, int* flags, int* abort, const Coef& cf, void* stream, const Ends* ends)
 {
     hipStream_t st = (hipStream_t)stream;
     const int h = halo_of(q);
@@ -1047,9 +1111,31 @@ int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps,
     const int per = (nwg + 7) / 8;
     const unsigned grid = (unsigned)(per * 8);
     const int64_t epitch = state_pitch(hs);
-    KSLB_DISPATCH_QP(q, prec, (k_span<Q_, P_><<<grid, kSpanLD, 0, st>>>((char*)state, n, state_pitch(n), nwg, steps,
-                                                                        s, ebase, ecopy, epitch, flags, abort, cf)));
-    (void)abort;
+    if (ends) {
+        KSLB_DISPATCH_QP(q, prec, (k_span<Q_, P_, true><<<grid, kSpanLD, 0, st>>>(
+                                      (char*)state, n, state_pitch(n), nwg, steps, s, ebase, ecopy, epitch, flags,
+                                      abort, cf, ends->rho_l, ends->rho_r)));
+    } else {
+        KSLB_DISPATCH_QP(q, prec, (k_span<Q_, P_, false><<<grid, kSpanLD, 0, st>>>(
+                                      (char*)state, n, state_pitch(n), nwg, steps, s, ebase, ecopy, epitch, flags,
+                                      abort, cf, 0.0, 0.0)));
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_plain_fixed(int q, int prec, const void* src, void* dst, int64_t n, const Coef& cf, const Ends& ends,
+                       void* stream)
+{
+    KSLB_DISPATCH_QP(q, prec, (k_plain_fixed<Q_, P_><<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(
+                                  (const char*)src, (char*)dst, n, state_pitch(n), cf, ends.rho_l, ends.rho_r)));
+    return (int)hipGetLastError();
+}
+
+int launch_init_fixed(int q, int prec, void* state, int64_t n, const double* rho0, const Coef& cf, const Ends& ends,
+                      void* stream)
+{
+    KSLB_DISPATCH_QP(q, prec, (k_init_fixed<Q_, P_><<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(
+                                  (char*)state, n, state_pitch(n), rho0, cf, ends.rho_l, ends.rho_r)));
     return (int)hipGetLastError();
 }
 

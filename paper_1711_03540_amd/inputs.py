@@ -107,6 +107,31 @@ CFG_RESIDENT_Q7 = Workload("d1q7_n4096_modes", 7, 4096, 256 * _PI, 1e-4, 100_000
 CFG_LARGE_Q7 = Workload("d1q7_n16m_modes", 7, 1 << 24, 32 * _PI * 4096, 2e-8, 1_000, ic_seed=4)
 
 
+# The travelling wave of the paper's Table 3 (section 3): b = 3, X0 = 20 on
+# [X_m, X_M] = [0, 60], k = sqrt(11/19)/2, with end values b -+ (30/19) sqrt(11/19).
+TABLE3_B = 3.0
+TABLE3_XM = 60.0
+
+
+def table3_profile(X, t: float = 0.0) -> np.ndarray:
+    """rho(X, t) of the Table 3 solution (its initial condition at t = 0)."""
+    X = np.asarray(X, dtype=np.float64)
+    k = 0.5 * math.sqrt(11.0 / 19.0)
+    a = (15.0 / 19.0) * math.sqrt(11.0 / 19.0)
+    th = np.tanh(k * (X - TABLE3_B * t - TABLE3_XM / 3.0))
+    return TABLE3_B + a * (-9.0 * th + 11.0 * th ** 3)
+
+
+def table3_ends():
+    left = TABLE3_B - (30.0 / 19.0) * math.sqrt(11.0 / 19.0)
+    return left, 2.0 * TABLE3_B - left
+
+
+def table3_sites(dX: float) -> int:
+    """Sites X_j = j dX, j = 0 .. 60/dX."""
+    return int(round(TABLE3_XM / dX)) + 1
+
+
 def ensemble_shapes(count: int = 4096, seed: int = 2, n_lo: int = 512, n_hi: int = 8192) -> np.ndarray:
     """N_i = min(n_hi, floor(n_lo * (n_hi/n_lo)^u)), log-uniform on [n_lo, n_hi]."""
     sm = SplitMix64(seed)

@@ -95,6 +95,15 @@ class Lattice:
         call("kslb_set_kernel", self._h, k, steps_per_launch)
         return self
 
+    def set_fixed_ends(self, rho_left: float, rho_right: float) -> "Lattice":
+        """Fixed-end boundary of the paper's Table 3 problem (set before init_rho)."""
+        call("kslb_set_boundary", self._h, 1, float(rho_left), float(rho_right))
+        return self
+
+    def set_periodic(self) -> "Lattice":
+        call("kslb_set_boundary", self._h, 0, 0.0, 0.0)
+        return self
+
     # -- state ------------------------------------------------------------
     def init_rho(self, rho) -> "Lattice":
         import torch

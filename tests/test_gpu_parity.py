@@ -298,6 +298,33 @@ def test_served_results_equal_solo_solves():
         assert torch.equal(stats.results[i].rho, lat.read_rho()), i
 
 
+@pytest.mark.parametrize("q", [5, 7])
+@pytest.mark.parametrize("dX", [0.2, 0.1])
+def test_fixed_ends_table3_parity(q, dX):
+    # the Table 3 travelling wave with fixed ends: GPU (plain and
+    # multi-workgroup kernels) against the oracle's fixed-end solve
+    from paper_1711_03540_amd.inputs import table3_ends, table3_profile, table3_sites
+    say("case fixed ends q=%d dX=%g" % (q, dX))
+    dT = dX ** 4 / 100
+    tau = 1.0 if q == 5 else 1.3
+    steps = 3000
+    n = table3_sites(dX)
+    X = np.arange(n) * dX
+    lo, hi = table3_ends()
+    ref = oracle.solve_tanh_fixed(q, dX, dT, tau, steps)
+    outs = []
+    for kernel in ("plain", "span"):
+        lat = Lattice(n, q, "fp64").set_physical(dX, dT, tau).set_kernel(kernel).set_fixed_ends(lo, hi)
+        lat.init_rho(table3_profile(X, 0.0)).advance(steps)
+        rho = lat.rho()
+        assert rel(rho, ref) < TOL64, kernel
+        assert rho[0] == pytest.approx(lo, abs=1e-14) and rho[-1] == pytest.approx(hi, abs=1e-14)
+        outs.append(lat.f())
+    assert np.array_equal(outs[0], outs[1])
+    G = oracle.global_error(ref, oracle.tanh_solution(X, steps * dT))
+    assert G < 1e-3
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split"])
 def test_checkpoint_resume_bitwise(prec):
     say("case resume %s" % prec)

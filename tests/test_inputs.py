@@ -54,3 +54,14 @@ def test_request_stream():
     assert {r.precision for r in reqs} == {"fp32", "fp64"}
     assert min(r.n for r in reqs) >= 256 and max(r.n for r in reqs) <= 65536
     assert min(r.steps for r in reqs) >= 1000 and max(r.steps for r in reqs) <= 100000
+
+
+def test_table3_profile_matches_the_oracle():
+    # two independent codings of the Table 3 formula
+    import oracle
+    from paper_1711_03540_amd.inputs import table3_ends, table3_profile, table3_sites
+    X = np.linspace(-10, 70, 161)
+    for t in (0.0, 0.7):
+        assert np.allclose(table3_profile(X, t), oracle.tanh_solution(X, t), rtol=0, atol=1e-14)
+    assert np.allclose(table3_ends(), oracle.tanh_ends(), atol=1e-15)
+    assert table3_sites(0.05) == 1201 and table3_sites(0.2) == 301

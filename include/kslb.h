@@ -66,8 +66,12 @@ enum { KSLB_D1Q5 = 5, KSLB_D1Q7 = 7 };
  *           term of the equilibrium in double, the relaxation in single.
  *   SPLIT : rho stored in double and the non-equilibrium part
  *           f_i - feq_i(rho) in single; arithmetic in double.  Exact change
- *           of variables of the FP64 scheme (rounding aside).             */
-enum { KSLB_FP64 = 0, KSLB_FP32 = 1, KSLB_SPLIT = 2 };
+ *           of variables of the FP64 scheme (rounding aside).
+ *   RHO   : tau = 1 only.  With omega = 1 the collision of Eq. (2) leaves
+ *           f_i = feq_i(rho), so the state is rho alone (one double per
+ *           site); densities are bitwise those of FP64 at tau = 1.  Setting
+ *           any other tau returns EINVAL.                                  */
+enum { KSLB_FP64 = 0, KSLB_FP32 = 1, KSLB_SPLIT = 2, KSLB_RHO = 3 };
 
 /* Reading of the bracket of Eq. (delta_M).  DERIVED uses (T3+1)/(T2+1), the
  * ratio in the fourth-derivative term of Eq. (KS_trunc2) that dM cancels;

@@ -14,8 +14,8 @@ LIB_PATH = os.path.join(HERE, "libkslb.so")
 
 KSLB_OK, KSLB_EINVAL, KSLB_ENOMEM, KSLB_EDEVICE, KSLB_ESTATE, KSLB_EUNSTABLE, KSLB_ENONFINITE = \
     0, -1, -2, -3, -4, -5, -6
-FP64, FP32, SPLIT = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "split": SPLIT}
+FP64, FP32, SPLIT, RHO = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "split": SPLIT, "rho": RHO}
 DM_DERIVED, DM_LITERAL = 0, 1
 GUARD_REFUSE, GUARD_RAISE_TAU, GUARD_OFF = 0, 1, 2
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_RESIDENT, KERNEL_TILED, KERNEL_SPAN = 0, 1, 2, 3, 4

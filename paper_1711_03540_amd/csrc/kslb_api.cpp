@@ -56,7 +56,7 @@ constexpr size_t kDiagBytes = 4096;   // 256 partial sums + mass + flag
 
 bool valid_shape(int64_t n, int q, int prec)
 {
-    return n > 0 && n < (int64_t(1) << 40) && (q == 5 || q == 7) && prec >= 0 && prec <= 2;
+    return n > 0 && n < (int64_t(1) << 40) && (q == 5 || q == 7) && prec >= 0 && prec <= 3;
 }
 
 int halo(int q) { return q == 5 ? 2 : 3; }
@@ -114,6 +114,13 @@ kslb_status set_physics(Physics& ph, int q, double dX, double dT, double tau, in
     ph.tau = tau;
     ph.omega = 1.0 / tau;
     fold(ph.cf, E, G, ph.omega, q);
+    return KSLB_OK;
+}
+
+kslb_status rho_mode_check(int prec, const Physics& ph)
+{
+    if (prec == kRHO && ph.omega != 1.0)
+        return fail(KSLB_EINVAL, "the rho-only storage needs tau = 1 exactly (got tau = %.17g)", ph.tau);
     return KSLB_OK;
 }
 
@@ -298,6 +305,7 @@ kslb_status kslb_set_physical(kslb_lattice* L, double dX, double dT, double tau,
     Physics ph;
     kslb_status st = set_physics(ph, L->q, dX, dT, tau, dm_variant, guard_policy, rho_max);
     if (st) return st;
+    if ((st = rho_mode_check(L->prec, ph))) return st;
     L->ph = ph;
     return KSLB_OK;
 }
@@ -318,6 +326,7 @@ kslb_status kslb_set_coefficients(kslb_lattice* L, const double* E, const double
     ph.omega = omega;
     ph.tau = 1.0 / omega;
     fold(ph.cf, ph.E, ph.G, omega, L->q);
+    if (auto st = rho_mode_check(L->prec, ph)) return st;
     L->ph = ph;
     return KSLB_OK;
 }
@@ -926,6 +935,7 @@ kslb_status kslb_ensemble_set_physical(kslb_ensemble* E, double dX, double dT, d
     Physics ph;
     kslb_status st = set_physics(ph, E->q, dX, dT, tau, dm_variant, guard_policy, rho_max);
     if (st) return st;
+    if ((st = rho_mode_check(E->prec, ph))) return st;
     E->ph = ph;
     return KSLB_OK;
 }

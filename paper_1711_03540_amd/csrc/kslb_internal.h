@@ -11,7 +11,7 @@ namespace kslb {
 // (tau = (3 + sqrt 6)/6 ~ 0.908).
 constexpr double kTauMin = 0.92;
 
-enum Precision { kFP64 = 0, kFP32 = 1, kSPLIT = 2 };
+enum Precision { kFP64 = 0, kFP32 = 1, kSPLIT = 2, kRHO = 3 };
 
 // Coefficients handed to every kernel by value.
 //   feq_i(rho) = E_i rho + G_i rho^2        (equilibrium, section 2.3)

@@ -410,6 +410,77 @@ struct Pol<Q, kSPLIT> {
     }
 };
 
+// tau = 1 only (omega = 1): the collision leaves S_i = feq_i(rho), so the
+// state is rho alone, one row of p doubles.  A population is rebuilt as
+// feq_i(rho) by the same expression the FP64 policy evaluates with
+// A_i = 1 * E_i and B_i = 1 * G_i, so densities are bitwise those of FP64.
+template <int Q>
+struct Pol<Q, kRHO> {
+    struct Site { double rho; };
+
+    template <int I>
+    __device__ static __forceinline__ double eq_of(double rho, const Coef& cf)
+    {
+        if constexpr (has_g(I)) return __builtin_fma(cf.A[I], rho, cf.B[I] * (rho * rho));
+        else return cf.A[I] * rho;
+    }
+
+    template <int I>
+    __device__ static __forceinline__ double pop(const Site& x, const Coef& cf) { return eq_of<I>(x.rho, cf); }
+
+    template <int I>
+    __device__ static __forceinline__ double pop_g(const char* st, int64_t, int64_t j, const Coef& cf)
+    {
+        return eq_of<I>(reinterpret_cast<const double*>(st)[j], cf);
+    }
+
+    __device__ static __forceinline__ void update(const double (&g)[Q], Site& y, const Coef&)
+    {
+        y.rho = dsum<Q>(g);
+    }
+
+    __device__ static __forceinline__ Site load(const char* st, int64_t, int64_t j)
+    {
+        return Site{reinterpret_cast<const double*>(st)[j]};
+    }
+
+    __device__ static __forceinline__ void store(char* st, int64_t, int64_t j, const Site& x)
+    {
+        reinterpret_cast<double*>(st)[j] = x.rho;
+    }
+
+    template <int B>
+    __device__ static __forceinline__ void load_vec(const char* st, int64_t, int64_t j0, Site (&x)[B])
+    {
+        const d2v* r = reinterpret_cast<const d2v*>(reinterpret_cast<const double*>(st) + j0);
+        unroll<B / 2>([&](auto K) {
+            const d2v v = r[K];
+            x[2 * K].rho = v.x;
+            x[2 * K + 1].rho = v.y;
+        });
+    }
+
+    template <int B>
+    __device__ static __forceinline__ void store_vec(char* st, int64_t, int64_t j0, const Site (&x)[B])
+    {
+        d2v* r = reinterpret_cast<d2v*>(reinterpret_cast<double*>(st) + j0);
+        unroll<B / 2>([&](auto K) {
+            d2v v;
+            v.x = x[2 * K].rho;
+            v.y = x[2 * K + 1].rho;
+            r[K] = v;
+        });
+    }
+
+    __device__ static __forceinline__ Site equilibrium(double rho, const Coef&) { return Site{rho}; }
+
+    __device__ static __forceinline__ Site from_f(const double (&f)[Q], const Coef&) { return Site{dsum<Q>(f)}; }
+
+    __device__ static __forceinline__ double density(const Site& x) { return x.rho; }
+
+    __device__ static __forceinline__ bool finite(const Site& x) { return __builtin_isfinite(x.rho); }
+};
+
 // ---------------------------------------------------------------- per-site kernels
 
 template <int Q, int P>
@@ -631,7 +702,7 @@ constexpr int kRingLD = 512;
 // rho/n site record of SPLIT and the 28-byte FP32 record the compiler keeps
 // part of the register block in scratch memory).
 template <int P>
-constexpr bool kVecIO = (P == kFP64);
+constexpr bool kVecIO = (P == kFP64 || P == kRHO);
 constexpr int kTileLD = 256;
 
 // Whole periodic lattice of n = B * L sites in one workgroup of L lanes,
@@ -944,11 +1015,13 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256
         if ((q) == 5) {                                                  \
             if ((prec) == kFP64) { constexpr int Q_ = 5, P_ = kFP64; CALL; } \
             else if ((prec) == kFP32) { constexpr int Q_ = 5, P_ = kFP32; CALL; } \
-            else { constexpr int Q_ = 5, P_ = kSPLIT; CALL; }             \
+            else if ((prec) == kSPLIT) { constexpr int Q_ = 5, P_ = kSPLIT; CALL; } \
+            else { constexpr int Q_ = 5, P_ = kRHO; CALL; }               \
         } else {                                                         \
             if ((prec) == kFP64) { constexpr int Q_ = 7, P_ = kFP64; CALL; } \
             else if ((prec) == kFP32) { constexpr int Q_ = 7, P_ = kFP32; CALL; } \
-            else { constexpr int Q_ = 7, P_ = kSPLIT; CALL; }             \
+            else if ((prec) == kSPLIT) { constexpr int Q_ = 7, P_ = kSPLIT; CALL; } \
+            else { constexpr int Q_ = 7, P_ = kRHO; CALL; }               \
         }                                                                \
     } while (0)
 
@@ -960,7 +1033,8 @@ size_t state_copy_bytes(int64_t n, int q, int prec)
     size_t b;
     if (prec == kFP64) b = (size_t)q * p * 8;
     else if (prec == kFP32) b = (size_t)q * p * 4;
-    else b = p * 8 + (size_t)q * p * 4;
+    else if (prec == kSPLIT) b = p * 8 + (size_t)q * p * 4;
+    else b = p * 8;
     return (b + 255) & ~(size_t)255;
 }
 

@@ -55,7 +55,8 @@ def test_state_bytes_and_bad_shapes():
     assert f(1000, 7, 0) == 2 * 1024 * 7 * 8 + 4096
     assert f(0, 7, 0) == 0
     assert f(16, 6, 0) == 0
-    assert f(16, 7, 3) == 0
+    assert f(16, 7, 3) == 2 * 64 * 8 + 4096          # rho only: one row
+    assert f(16, 7, 4) == 0
 
 
 def test_errors_are_reported_without_device_work():

@@ -325,6 +325,32 @@ def test_fixed_ends_table3_parity(q, dX):
     assert G < 1e-3
 
 
+@pytest.mark.parametrize("q", [5, 7])
+@pytest.mark.parametrize("n", [3, 256, 1000, 4096, 70001])
+def test_rho_only_mode_at_tau1(q, n):
+    # tau = 1: the rho-only storage evolves exactly as FP64 on every kernel
+    # class: its populations feq(rho) are FP64's post-collision state bit for
+    # bit.  The density readouts differ by rounding only: FP64 sums its stored
+    # populations, the rho-only state holds rho itself.
+    say("case rho-only q=%d n=%d" % (q, n))
+    dX, dT = 0.3, 2e-4
+    rho0 = ic(n, dX, 31)
+    ref = make(q, n, "fp64", "plain", dX, dT, 1.0).init_rho(rho0).advance(500)
+    rr = ref.rho()
+    assert rel(rr, oracle.solve_periodic(q, rho0, dX, dT, 1.0, 500)) < TOL64
+    for kernel in ("plain", "tiled", "resident", "span"):
+        lat = Lattice(n, q, "rho").set_physical(dX, dT, 1.0)
+        try:
+            lat.set_kernel(kernel)
+        except Exception:
+            continue
+        lat.init_rho(rho0).advance(500)
+        assert np.array_equal(lat.f(), ref.f()), kernel
+        assert rel(lat.rho(), rr) < 1e-15, kernel
+    with pytest.raises(Exception):
+        Lattice(n, q, "rho").set_physical(dX, dT, 1.1)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split"])
 def test_checkpoint_resume_bitwise(prec):
     say("case resume %s" % prec)

@@ -51,6 +51,7 @@ WORKLOADS = {
     "ensemble": (None, None),
     "serve": (None, None),
     "table3": (None, None),
+    "stats": (None, None),
 }
 
 
@@ -70,6 +71,7 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0, help="ensemble/serve: steps per launch (0 = default)")
     ap.add_argument("--segments", type=int, default=0, help="ensemble: instance tiles per window (0 = default)")
     ap.add_argument("--requests", type=int, default=2000, help="serve workload: requests")
+    ap.add_argument("--stats-t", type=int, default=1000, help="stats workload: final time T")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -271,6 +273,71 @@ def bench_table3(args):
     print(json.dumps({"workload": "table3_fixed_ends", "T_end": T_end, "runs": runs, "matched": matched}), flush=True)
 
 
+def bench_stats(args):
+    """Reduced-precision error on long-time statistics: the D1Q7 N = 4096 lattice
+    (L = 256 pi, dT = 1e-4, fitted tau, 16 random modes) run to T = 1000 in FP64,
+    FP32 and split storage; time averages over T in [200, 1000] (one sample per
+    unit time) of the energy spectrum E_m = <|rho_m|^2> (rho_m the discrete
+    Fourier coefficient / N) and of <rho^2>, with standard errors from 8 blocks;
+    plus the norm-wise error against FP64 at fixed times."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03540_amd import inputs
+    from paper_1711_03540_amd.lattice import Lattice
+
+    dev = torch.device("cuda:0")
+    w = inputs.CFG_RESIDENT_Q7
+    rho0 = torch.tensor(w.rho0(), device=dev)
+    per_unit = int(round(1.0 / w.dT))
+    t_lo, t_hi = 200, args.stats_t
+    res = {}
+    fixed = {}
+    for prec in ("fp64", "fp32", "split"):
+        lat = Lattice(w.n, 7, prec, device=dev).set_physical(w.dX, w.dT, 0.0).init_rho(rho0)
+        out = torch.empty(w.n, dtype=torch.float64, device=dev)
+        spec, r2 = [], []
+        snaps = {}
+        t0 = time.perf_counter()
+        for t in range(1, t_hi + 1):
+            lat.advance(per_unit)
+            if t in (1, 10, 100):
+                snaps[t] = lat.read_rho(out).clone()
+            if t >= t_lo:
+                lat.read_rho(out)
+                f = torch.fft.rfft(out) / w.n
+                spec.append((f.real ** 2 + f.imag ** 2).cpu().numpy())
+                r2.append(float(torch.mean(out * out)))
+        torch.cuda.synchronize()
+        spec = np.array(spec)
+        r2 = np.array(r2)
+        nb = 8
+        blocks = np.array_split(np.arange(len(r2)), nb)
+        bm_s = np.array([spec[b].mean(axis=0) for b in blocks])
+        bm_r = np.array([r2[b].mean() for b in blocks])
+        res[prec] = {"E_m": spec.mean(axis=0), "E_m_se": bm_s.std(axis=0, ddof=1) / math.sqrt(nb),
+                     "rho2": float(r2.mean()), "rho2_se": float(bm_r.std(ddof=1) / math.sqrt(nb)),
+                     "seconds": time.perf_counter() - t0}
+        fixed[prec] = snaps
+        print("stats %s done in %.1f s" % (prec, res[prec]["seconds"]), file=sys.stderr, flush=True)
+    ref = res["fp64"]
+    kband = slice(1, 160)     # kappa = m / 128 < 1.25: the active band
+    out = {"workload": "stats_d1q7_n4096", "T": [t_lo, t_hi], "samples": t_hi - t_lo + 1,
+           "fp64": {"rho2": ref["rho2"], "rho2_se": ref["rho2_se"], "seconds": ref["seconds"]}}
+    for prec in ("fp32", "split"):
+        r = res[prec]
+        z = (r["E_m"][kband] - ref["E_m"][kband]) / np.sqrt(r["E_m_se"][kband] ** 2 + ref["E_m_se"][kband] ** 2)
+        out[prec] = {"rho2": r["rho2"], "rho2_se": r["rho2_se"],
+                     "rho2_diff_in_se": (r["rho2"] - ref["rho2"]) / math.hypot(r["rho2_se"], ref["rho2_se"]),
+                     "spectrum_max_abs_z": float(np.max(np.abs(z))), "spectrum_rms_z": float(np.sqrt(np.mean(z ** 2))),
+                     "spectrum_max_rel_diff": float(np.max(np.abs(r["E_m"][kband] / ref["E_m"][kband] - 1))),
+                     "fixed_time_rel_err_vs_fp64": {
+                         "T=%d" % t: float(torch.max(torch.abs(fixed[prec][t] - fixed["fp64"][t])) /
+                                           torch.max(torch.abs(fixed["fp64"][t]))) for t in (1, 10, 100)},
+                     "seconds": r["seconds"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -289,6 +356,9 @@ def main():
         return
     if args.workload == "table3":
         bench_table3(args)
+        return
+    if args.workload == "stats":
+        bench_stats(args)
         return
     import numpy as np
     import torch

@@ -41,7 +41,7 @@ def flops_per_site_update(q: int) -> int:
 # Algorithmic HBM bytes of one s = 1 step per site: read Q populations and
 # write Q populations of the storage format.
 def bytes_per_site_update(q: int, precision: str) -> int:
-    return {"fp64": 2 * q * 8, "fp32": 2 * q * 4, "split": 2 * (8 + q * 4)}[precision]
+    return {"fp64": 2 * q * 8, "fp32": 2 * q * 4, "split": 2 * (8 + q * 4), "rho": 2 * 8}[precision]
 
 
 WORKLOADS = {
@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10, help="timed solves")
     ap.add_argument("--warmup", type=int, default=2, help="untimed solves")
     ap.add_argument("--workload", default="d1q7_n4096", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "split"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "split", "rho"])
     ap.add_argument("--kernel", default=None, choices=["span", "resident", "tiled", "plain"])
     ap.add_argument("--tile-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -475,7 +475,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "split": "f64+f32"}[args.precision],
+        "dtype": {"fp64": "f64", "fp32": "f32", "split": "f64+f32", "rho": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": w.name, "scheme": "D1Q%d" % w.q, "n_sites": w.n, "lb_steps_per_solve": w.steps,
                    "dX": w.dX, "dT": w.dT, "tau": tau, "precision": args.precision, "kernel": kernel,

@@ -184,6 +184,7 @@ int ring_sites_per_lane(int64_t n, int q)
 }
 
 constexpr int kTileB = 8;
+int tile_sites_per_lane(int prec) { return prec == kRHO ? 16 : kTileB; }
 // Default steps between edge exchanges of the SPAN kernel: the largest s
 // whose owners still hold H s sites (256 >= 3 H s), or less when the lattice
 // is too small for that.
@@ -218,9 +219,9 @@ constexpr int64_t kSpanAutoMaxSites = 65536;
 
 // Steps per tiled launch: halo overhead 2 H s <= W / 8, rounded down to a
 // multiple of 8 so that every window starts on an 8-site boundary.
-int default_tile_steps(int q)
+int default_tile_steps(int q, int prec)
 {
-    const int W = tile_lanes() * kTileB;
+    const int W = tile_lanes() * tile_sites_per_lane(prec);
     int s = W / (16 * halo(q));
     s -= s % 8;
     return std::max(8, s);
@@ -364,7 +365,7 @@ kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
                         (long long)L->n, sp);
     }
     if (kernel == KSLB_KERNEL_TILED && steps_per_launch > 0) {
-        if (tile_lanes() * kTileB - 2 * halo(L->q) * steps_per_launch <= 0)
+        if (tile_lanes() * tile_sites_per_lane(L->prec) - 2 * halo(L->q) * steps_per_launch <= 0)
             return fail(KSLB_EINVAL, "steps_per_launch %d leaves no valid sites in a tile", steps_per_launch);
     }
     L->kernel = kernel;
@@ -482,10 +483,11 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
             L->cur ^= 1;
         }
     } else {
-        int s_max = L->tile_steps > 0 ? L->tile_steps : default_tile_steps(L->q);
+        int s_max = L->tile_steps > 0 ? L->tile_steps : default_tile_steps(L->q, L->prec);
         for (int64_t done = 0; done < n_steps;) {
             const int s = (int)std::min<int64_t>(s_max, n_steps - done);
-            e = launch_tile(L->q, L->prec, kTileB, L->state(), L->other(), L->n, s, L->ph.cf, L->stream);
+            e = launch_tile(L->q, L->prec, tile_sites_per_lane(L->prec), L->state(), L->other(), L->n, s, L->ph.cf,
+                            L->stream);
             if (e) return hip_fail(e, "tiled kernel");
             L->cur ^= 1;
             done += s;
@@ -954,7 +956,8 @@ kslb_status kslb_ensemble_set_tiling(kslb_ensemble* E, int sites_per_lane, int m
     int B = sites_per_lane ? sites_per_lane : E->B;
     int m = max_segments ? max_segments : E->max_seg;
     int c = steps_per_chunk ? steps_per_chunk : E->chunk;
-    if (B != 4 && B != 8) return fail(KSLB_EINVAL, "sites_per_lane must be 4 or 8");
+    if (B != 4 && B != 8 && !(B == 16 && E->prec == kRHO))
+        return fail(KSLB_EINVAL, "sites_per_lane must be 4 or 8 (or 16 with the rho-only storage)");
     if (m < 1 || m > tile_lanes()) return fail(KSLB_EINVAL, "max_segments must lie in [1, %d]", tile_lanes());
     const int64_t W = (int64_t)tile_lanes() * B;
     if (c < 1 || W - 2 * halo(E->q) * (int64_t)c < B)

@@ -557,13 +557,23 @@ struct Engine {
     using PL = Pol<Q, P>;
     using Site = typename PL::Site;
     static constexpr int H = halo_of(Q);
-    static constexpr int NX = nx_of(Q);
+    // rho-only state: the neighbours need the densities of the H edge sites
+    // on each side, not the 12 (6) populations
+    static constexpr bool kR = (P == kRHO);
+    static constexpr int NX = kR ? 2 * H : nx_of(Q);
     static constexpr int SLOT = NX * LD;     // doubles per exchange buffer
     static_assert(B >= H, "a lane must hold at least max|c| sites");
 
-    // write the populations the neighbours pull (column `lane` of slot)
+    // write the values the neighbours pull (column `lane` of slot)
     __device__ static __forceinline__ void publish(const Site (&x)[B], double* slot, const Coef& cf)
     {
+        if constexpr (kR) {
+            unroll<H>([&](auto T) {
+                slot[T * LD] = x[B - H + T].rho;           // for the right neighbour
+                slot[(H + T) * LD] = x[T].rho;             // for the left neighbour
+            });
+            return;
+        }
         unroll<Q - 1>([&](auto I1) {
             constexpr int i = I1 + 1;
             constexpr int c = vel(i);
@@ -589,6 +599,7 @@ struct Engine {
                 constexpr int c = vel(i);
                 constexpr int sb = b - c;
                 if constexpr (sb >= 0 && sb < B) g[i] = PL::template pop<i>(x[sb], cf);
+                else if constexpr (kR) g[i] = PL::template pop<i>(Site{hv[sb < 0 ? H + sb : H + sb - B]}, cf);
                 else if constexpr (c > 0) g[i] = hv[koff(i) + b];
                 else g[i] = hv[koff(i) + sb - B];
             });
@@ -601,15 +612,22 @@ struct Engine {
                                                 const double* right, const Coef& cf)
     {
         double hv[NX];
-        unroll<Q - 1>([&](auto I1) {
-            constexpr int i = I1 + 1;
-            constexpr int c = vel(i);
-            constexpr int k0 = koff(i);
-            unroll<iabs(c)>([&](auto T) {
-                constexpr int t = T;
-                hv[k0 + t] = (c > 0 ? left : right)[(k0 + t) * LD];
+        if constexpr (kR) {
+            unroll<H>([&](auto T) {
+                hv[T] = left[T * LD];
+                hv[H + T] = right[(H + T) * LD];
             });
-        });
+        } else {
+            unroll<Q - 1>([&](auto I1) {
+                constexpr int i = I1 + 1;
+                constexpr int c = vel(i);
+                constexpr int k0 = koff(i);
+                unroll<iabs(c)>([&](auto T) {
+                    constexpr int t = T;
+                    hv[k0 + t] = (c > 0 ? left : right)[(k0 + t) * LD];
+                });
+            });
+        }
         step_hv(x, y, hv, cf);
     }
 
@@ -633,6 +651,14 @@ struct Engine {
     __device__ static __forceinline__ void step_dpp(const Site (&x)[B], Site (&y)[B], const Coef& cf)
     {
         double hv[NX];
+        if constexpr (kR) {
+            unroll<H>([&](auto T) {
+                hv[T] = from_lane(x[B - H + T].rho, true);
+                hv[H + T] = from_lane(x[T].rho, false);
+            });
+            step_hv(x, y, hv, cf);
+            return;
+        }
         unroll<Q - 1>([&](auto I1) {
             constexpr int i = I1 + 1;
             constexpr int c = vel(i);
@@ -1056,6 +1082,7 @@ int ring_max_lanes() { return kRingLD; }
 int tile_lanes() { return kTileLD; }
 int ring_lds_bytes(int q) { return 2 * nx_of(q) * kRingLD * (int)sizeof(double); }
 int tile_lds_bytes(int q) { return 2 * nx_of(q) * kTileLD * (int)sizeof(double); }
+// (the rho-only engine exchanges fewer values and uses a prefix of these areas)
 
 // Raise a kernel's dynamic LDS limit above 64 KiB, once per kernel and size
 // (the attribute is per function).
@@ -1144,6 +1171,10 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
 {
     if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (tile_one<Q_, P_, 4>(src, dst, n, s, cf, stream))); }
     if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (tile_one<Q_, P_, 8>(src, dst, n, s, cf, stream))); }
+    if (B == 16 && prec == kRHO) {   // 16 sites per lane: rho-only state only
+        if (q == 5) return tile_one<5, kRHO, 16>(src, dst, n, s, cf, stream);
+        return tile_one<7, kRHO, 16>(src, dst, n, s, cf, stream);
+    }
     return (int)hipErrorInvalidValue;
 }
 
@@ -1163,6 +1194,10 @@ int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegD
     if (nwin <= 0) return 0;
     if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 4>(base, hdr, seg, nwin, cf, stream))); }
     if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 8>(base, hdr, seg, nwin, cf, stream))); }
+    if (B == 16 && prec == kRHO) {
+        if (q == 5) return ens_one<5, kRHO, 16>(base, hdr, seg, nwin, cf, stream);
+        return ens_one<7, kRHO, 16>(base, hdr, seg, nwin, cf, stream);
+    }
     return (int)hipErrorInvalidValue;
 }
 

@@ -241,6 +241,12 @@ kslb_status kslb_ensemble_set_physical(kslb_ensemble* ens, double dX, double dT,
 kslb_status kslb_ensemble_set_tiling(kslb_ensemble* ens, int sites_per_lane, int max_segments,
                                      int steps_per_chunk);
 
+/* Steady-state graphs (default on): when every instance still to advance
+ * has at least four more full chunks, the two alternating chunk launches are
+ * captured once as a HIP graph (kernel nodes only) and replayed.  Results
+ * are bitwise those of the launch-per-chunk path.                          */
+kslb_status kslb_ensemble_set_graphs(kslb_ensemble* ens, int enable);
+
 /* The tau in use (after the fit and the guard). */
 kslb_status kslb_ensemble_get_tau(const kslb_ensemble* ens, double* tau);
 

@@ -683,6 +683,12 @@ struct kslb_ensemble {
     size_t h_cap[2] = {0, 0};
     hipEvent_t up_ev[2] = {nullptr, nullptr};
     bool up_pending[2] = {false, false};
+    uint64_t slot_gen[2] = {0, 0};          // bumped whenever a slot is rewritten
+    // steady state: the two alternating chunk launches captured as one graph
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;       // private stream the graph is recorded on
+    hipGraphExec_t gexec = nullptr;
+    uint64_t gkey[5] = {0, 0, 0, 0, 0};
     double* staging = nullptr;
     int64_t staging_n = 0;
 };
@@ -739,7 +745,7 @@ struct Tile {
 // instance; best-fit-decreasing packs tiles with equal step counts into
 // windows of tile_lanes() lanes and at most max_seg segments.
 kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, const WinHdr** hdr, const SegDesc** seg,
-                     int* nwin)
+                     int* nwin, int* slot_out = nullptr, int avoid = -1)
 {
     std::vector<uint64_t> key;
     key.reserve(3 * (size_t)E->count + 3);
@@ -756,6 +762,7 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, const WinHdr
             *hdr = reinterpret_cast<const WinHdr*>(E->d_tab[k]);
             *seg = reinterpret_cast<const SegDesc*>(E->d_tab[k] + sizeof(WinHdr) * (size_t)E->nwin[k]);
             *nwin = E->nwin[k];
+            if (slot_out) *slot_out = k;
             return KSLB_OK;
         }
     }
@@ -837,8 +844,10 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, const WinHdr
         }
     }
     const size_t bytes = sizeof(WinHdr) * hv.size() + sizeof(SegDesc) * sv.size();
-    const int k = E->next_slot;
-    E->next_slot ^= 1;
+    int k = E->next_slot;
+    if (k == avoid) k ^= 1;
+    E->next_slot = k ^ 1;
+    E->slot_gen[k]++;
     if (E->d_cap[k] < bytes) {
         if (E->d_tab[k]) {
             (void)hipStreamSynchronize(E->stream);
@@ -880,6 +889,64 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, const WinHdr
     *hdr = reinterpret_cast<const WinHdr*>(E->d_tab[k]);
     *seg = reinterpret_cast<const SegDesc*>(E->d_tab[k] + sizeof(WinHdr) * hv.size());
     *nwin = (int)hv.size();
+    if (slot_out) *slot_out = k;
+    return KSLB_OK;
+}
+
+// Steady state: every active instance has at least `pairs` * 2 more full
+// chunks.  The chunk with the current parities and the one after it (all
+// parities flipped) are planned into the two descriptor slots and captured
+// once as a graph of two kernel launches, replayed `pairs` times.  The graph
+// holds kernels only (no memset or copy nodes); it is rebuilt whenever either
+// slot is rewritten.
+kslb_status ens_replay_pairs(kslb_ensemble* E, const std::vector<int>& adv, int64_t pairs)
+{
+    const WinHdr *ha, *hb;
+    const SegDesc *sa, *sb;
+    int na, nb, ka, kb;
+    if (auto s = ens_plan(E, adv, &ha, &sa, &na, &ka)) return s;
+    for (int i = 0; i < E->count; i++)
+        if (adv[i] > 0) E->cur[i] ^= 1;
+    kslb_status st = ens_plan(E, adv, &hb, &sb, &nb, &kb, ka);
+    for (int i = 0; i < E->count; i++)
+        if (adv[i] > 0) E->cur[i] ^= 1;
+    if (st) return st;
+    const uint64_t key[5] = {(uint64_t)ka, E->slot_gen[ka], (uint64_t)kb, E->slot_gen[kb],
+                             ((uint64_t)E->B << 32) | (uint64_t)(na + nb)};
+    if (!E->gexec || std::memcmp(key, E->gkey, sizeof key) != 0) {
+        if (E->gexec) {
+            (void)hipStreamSynchronize(E->stream);
+            (void)hipGraphExecDestroy(E->gexec);
+            E->gexec = nullptr;
+        }
+        // record on a private stream (the caller's may be the null stream,
+        // which cannot be captured); replay on the caller's stream
+        if (!E->cap_stream) {
+            int e = hipStreamCreateWithFlags(&E->cap_stream, hipStreamNonBlocking);
+            if (e) return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+        hipGraph_t graph = nullptr;
+        int e = hipStreamBeginCapture(E->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e) return hip_fail(e, "hipStreamBeginCapture");
+        int e1 = launch_ens(E->q, E->prec, E->B, E->buf, ha, sa, na, E->ph.cf, E->cap_stream);
+        int e2 = launch_ens(E->q, E->prec, E->B, E->buf, hb, sb, nb, E->ph.cf, E->cap_stream);
+        e = hipStreamEndCapture(E->cap_stream, &graph);
+        if (e1 || e2 || e) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(e1 ? e1 : (e2 ? e2 : e), "ensemble graph capture");
+        }
+        e = hipGraphInstantiate(&E->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e) {
+            E->gexec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        std::memcpy(E->gkey, key, sizeof key);
+    }
+    for (int64_t r = 0; r < pairs; r++) {
+        int e = hipGraphLaunch(E->gexec, E->stream);
+        if (e) return hip_fail(e, "hipGraphLaunch");
+    }
     return KSLB_OK;
 }
 
@@ -968,6 +1035,13 @@ kslb_status kslb_ensemble_set_tiling(kslb_ensemble* E, int sites_per_lane, int m
     return KSLB_OK;
 }
 
+kslb_status kslb_ensemble_set_graphs(kslb_ensemble* E, int enable)
+{
+    if (!E) return fail(KSLB_EINVAL, "null ensemble");
+    E->use_graphs = enable != 0;
+    return KSLB_OK;
+}
+
 kslb_status kslb_ensemble_resize(kslb_ensemble* E, int idx, int64_t n_sites)
 {
     if (auto s = check_ens(E, idx)) return s;
@@ -1023,6 +1097,23 @@ kslb_status kslb_ensemble_advance(kslb_ensemble* E, const int64_t* steps)
             any = any || adv[i] > 0;
         }
         if (!any) break;
+        if (E->use_graphs) {
+            int64_t full = INT64_MAX;
+            for (int i = 0; i < E->count; i++) {
+                if (left[i] <= 0) continue;
+                full = std::min<int64_t>(full, left[i] / E->chunk);
+            }
+            const int64_t pairs = full / 2;
+            if (full != INT64_MAX && pairs >= 2) {
+                if (auto s = ens_replay_pairs(E, adv, pairs)) return s;
+                for (int i = 0; i < E->count; i++) {
+                    if (left[i] <= 0) continue;
+                    left[i] -= 2 * pairs * E->chunk;
+                    E->step[i] += 2 * pairs * E->chunk;
+                }
+                continue;
+            }
+        }
         const WinHdr* hdr = nullptr;
         const SegDesc* seg = nullptr;
         int nwin = 0;
@@ -1085,6 +1176,8 @@ kslb_status kslb_ensemble_destroy(kslb_ensemble* E)
     if (!E) return KSLB_OK;
     DeviceGuard g(E->device);
     (void)hipStreamSynchronize(E->stream);
+    if (E->gexec) (void)hipGraphExecDestroy(E->gexec);
+    if (E->cap_stream) (void)hipStreamDestroy(E->cap_stream);
     for (int k = 0; k < 2; k++) {
         if (E->d_tab[k]) (void)hipFree(E->d_tab[k]);
         if (E->h_pin[k]) (void)hipHostFree(E->h_pin[k]);

@@ -492,6 +492,16 @@ __global__ __launch_bounds__(256) void k_init(char* st, int64_t n, int64_t p, co
     if (j < n) PL::store(st, p, j, PL::equilibrium(rho0[j], cf));
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Renumber them so that XCD x runs a contiguous run of logical blocks: the
+// halo lines two neighbouring blocks share then sit in one L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
+{
+    const int64_t per = nb / 8;
+    if (b < per * 8) return (b % 8) * per + b / 8;
+    return b;   // the ragged remainder keeps its index
+}
+
 // One fused pull-stream + density + equilibrium + BGK step per launch (s = 1).
 template <int Q, int P>
 __global__ __launch_bounds__(256) void k_plain(const char* __restrict__ src, char* __restrict__ dst,
@@ -499,7 +509,7 @@ __global__ __launch_bounds__(256) void k_plain(const char* __restrict__ src, cha
 {
     using PL = Pol<Q, P>;
     constexpr int H = halo_of(Q);
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (j >= n) return;
     double g[Q];
     if (j >= H && j + H < n) {
@@ -801,7 +811,7 @@ __global__ __launch_bounds__(kTileLD) void k_tile(const char* __restrict__ src, 
 {
     extern __shared__ double xch[];
     constexpr int H = halo_of(Q);
-    const int64_t ws = (int64_t)blockIdx.x * T - (int64_t)H * s;
+    const int64_t ws = xcd_block(blockIdx.x, gridDim.x) * T - (int64_t)H * s;
     const int64_t kl0 = (int64_t)threadIdx.x * B;
     window_lane<Q, P, B>(src, dst, n, p, ws + kl0, kl0, (int64_t)H * s, T, s, xch, cf);
 }

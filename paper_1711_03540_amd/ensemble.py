@@ -58,6 +58,11 @@ class Ensemble:
         self.chunk = steps_per_chunk or getattr(self, "chunk", 32)
         return self
 
+    def set_graphs(self, enable: bool = True) -> "Ensemble":
+        """Replay steady-state chunk pairs from a captured HIP graph (default on)."""
+        call("kslb_ensemble_set_graphs", self._h, int(bool(enable)))
+        return self
+
     def resize(self, idx: int, n: int) -> "Ensemble":
         call("kslb_ensemble_resize", self._h, int(idx), int(n))
         self.n[idx] = n

@@ -40,6 +40,7 @@ class Result:
     completed: float = math.nan
     rho: Optional[object] = None        # device tensor (float64)
     event: Optional[object] = None
+    finite: Optional[bool] = None       # False: the solve produced NaN/inf (retired alone)
 
     @property
     def latency(self) -> float:
@@ -172,5 +173,8 @@ class SolveServer:
                         time.sleep(min(dt, 1e-3))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        for res in results:
+            if res.rho is not None:
+                res.finite = bool(torch.isfinite(res.rho).all().item())
         su = float(sum(r.n * r.steps for r in requests))
         return ServeStats(results, wall, su)

@@ -250,6 +250,30 @@ def test_ensemble_matches_oracle_and_single_lattices():
         assert ens.status(i) == (steps[i], False)
 
 
+def test_ensemble_graph_replays_match_eager_launches():
+    # steady-state chunk pairs replayed from a captured graph, several advance
+    # calls with host synchronisation and eager work in between, each checked
+    # against the launch-per-chunk path
+    import torch
+    say("case ensemble graphs")
+    sizes = [700, 2500, 5000, 9000, 64]
+    dX, dT = 0.2, 1e-4
+    rho0s = [ic(n, dX, 70 + i) for i, n in enumerate(sizes)]
+    a = Ensemble(sizes, 7, "fp64").set_physical(dX, dT, 1.1).set_tiling(8, 16, 16).set_graphs(True)
+    b = Ensemble(sizes, 7, "fp64").set_physical(dX, dT, 1.1).set_tiling(8, 16, 16).set_graphs(False)
+    for e in (a, b):
+        for i, r in enumerate(rho0s):
+            e.init_rho(i, r)
+    for rnd, steps in enumerate(([200] * 5, [160, 96, 300, 0, 64], [128] * 5)):
+        a.advance(steps)
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()      # eager work between replays
+        b.advance(steps)
+        for i in range(len(sizes)):
+            assert np.array_equal(a.rho(i), b.rho(i)), (rnd, i)
+            assert a.status(i)[0] == b.status(i)[0]
+
+
 @pytest.mark.parametrize("q,prec", [(7, "fp64"), (5, "fp64"), (7, "split"), (5, "fp32")])
 def test_ensemble_packing_and_chunking_bitwise(q, prec):
     # packed windows (several instance tiles per workgroup), one tile per
@@ -286,13 +310,21 @@ def test_served_results_equal_solo_solves():
     reqs = request_stream(40, seed=17, rate=20000.0, n_lo=64, n_hi=6000, steps_lo=50, steps_hi=1500)
     init = [torch.tensor(random_modes_ic(r.n, r.n * dX, seed=r.seed % 1000003, n_modes=min(16, r.n // 2)),
                          device="cuda") for r in reqs]
+    # one request blows up (density ~1e300 overflows): it must be flagged and
+    # must not disturb the requests sharing its launches
+    bad = 7
+    init[bad] = init[bad] * 1e300
     srv = SolveServer(dX, dT, slots=6, capacity=6000, chunk=24, round_steps=100)
     stats = srv.serve(reqs, init, realtime=True)
     summ = stats.summary()
     say("serve summary", summ)
     assert summ["completed"] == len(reqs)
     assert summ["p99_ms"] >= summ["p50_ms"] > 0
+    assert stats.results[bad].finite is False
     for i, r in enumerate(reqs):
+        if i == bad:
+            continue
+        assert stats.results[i].finite
         lat = Lattice(r.n, r.q, SERVE_PRECISION[r.precision]).set_physical(dX, dT, 0.0).set_kernel("plain")
         lat.init_rho(init[i]).advance(r.steps)
         assert torch.equal(stats.results[i].rho, lat.read_rho()), i

@@ -30,11 +30,16 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 N_CU = 256
 
-# Algorithmic FP64 flops of one site update (an FMA counts 2): density
-# Q-1 adds, rho^2 1 mul, then per population with G != 0 (c = +-1, +-2) one
-# mul + two FMA, and per population without G one mul + one FMA.
-def flops_per_site_update(q: int) -> int:
+# Algorithmic flops of one site update (an FMA counts 2).  Population
+# storage: density Q-1 adds, rho^2 1 mul, then per population with G != 0
+# (c = +-1, +-2) one mul + two FMA, and per population without G one mul +
+# one FMA.  Rho-only storage (tau = 1, post-collision populations feq(rho)):
+# rho^2 1 mul, then the new density sum_i A_i rho(j - c_i) + B_i rho^2(j - c_i)
+# as 1 mul + (Q + 4 - 1) FMA.
+def flops_per_site_update(q: int, precision: str = "fp64") -> int:
     with_g, without_g = 4, q - 4
+    if precision == "rho":
+        return 1 + 1 + 2 * (q + with_g - 1)
     return (q - 1) + 1 + with_g * (1 + 2 * 2) + without_g * (1 + 2)
 
 
@@ -416,27 +421,20 @@ def main():
     if bad:
         raise SystemExit("bench: non-finite state")
 
-    # launches per advance and the dominant kernel's average duration
-    if kernel in ("resident", "span"):
-        launches = max(1, math.ceil(w.steps / (1 << 20)))
-        units = w.n * w.steps / launches
-        kname = "k_ring" if kernel == "resident" else "k_span"
-    elif kernel == "tiled":
-        s = args.tile_steps or (256 * 8) // (16 * (2 if w.q == 5 else 3))
-        launches = math.ceil(w.steps / s)
-        units = w.n * w.steps / launches
-        kname = "k_tile"
-    else:
-        launches = w.steps
-        units = w.n
-        kname = "k_plain"
+    # launches per advance and the dominant kernel's average duration, from
+    # the launch shape the library resolved for this lattice
+    shape = lat.kernel()
+    assert shape["kernel"] == kernel, shape
+    launches = math.ceil(w.steps / shape["steps_per_launch"])
+    units = w.n * w.steps / launches
+    kname = {"resident": "k_ring", "span": "k_span", "tiled": "k_tile", "plain": "k_plain"}[kernel]
     kernel_ms = float(np.mean(adv_ms)) / launches
     if kernel == "plain":
         ach = bytes_per_site_update(w.q, args.precision) * units / (kernel_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS, "traffic": None}
     else:
-        ach = flops_per_site_update(w.q) * units / (kernel_ms * 1e-3) / 1e12
+        ach = flops_per_site_update(w.q, args.precision) * units / (kernel_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": None}
         if kernel in ("resident", "span"):
@@ -446,21 +444,18 @@ def main():
             if kernel == "resident":
                 simds = 4
             else:
-                h = 2 if w.q == 5 else 3
-                s_ex = args.tile_steps or next(s for s in range(256 // (3 * h), 0, -1)
-                                               if w.n // math.ceil(w.n / (256 - 2 * h * s)) >= h * s)
-                simds = math.ceil(w.n / (256 - 2 * h * s_ex))
-                roof["steps_between_exchanges"] = s_ex
+                simds = shape["workgroups"]
+                roof["steps_between_exchanges"] = shape["exchange_steps"]
                 roof["workgroups"] = simds
             roof["simds_used"] = simds
             roof["frac_of_used_simds"] = ach / (PEAK_FP64_VECTOR_TFLOPS * simds / (4 * N_CU))
     roof["traffic"] = measured_traffic(kname, w.name, args.precision)
     roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
-    roof["traffic_algorithmic"] = (bytes_per_site_update(w.q, args.precision) * w.n if kernel != "resident"
-                                   else bytes_per_site_update(w.q, args.precision) * w.n)
+    roof["traffic_algorithmic"] = bytes_per_site_update(w.q, args.precision) * w.n
     roof["kernel"] = kname
+    roof["launch_shape"] = shape
     roof["kernel_ms_avg"] = kernel_ms
-    roof["algorithmic_per_site_update"] = (flops_per_site_update(w.q) if kernel != "plain"
+    roof["algorithmic_per_site_update"] = (flops_per_site_update(w.q, args.precision) if kernel != "plain"
                                            else bytes_per_site_update(w.q, args.precision))
     roof["units_per_launch"] = units
 

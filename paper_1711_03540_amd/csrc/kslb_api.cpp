@@ -233,6 +233,33 @@ kslb_status check_lat(const kslb_lattice* L)
     return KSLB_OK;
 }
 
+// Longest advance one launch of the RESIDENT or SPAN kernel covers.
+constexpr int64_t kMaxStepsPerLaunch = int64_t(1) << 20;
+
+// The kernel class an advance of this lattice runs (AUTO resolved) and its
+// step parameter: steps per launch for TILED, steps between edge exchanges
+// for SPAN, 0 otherwise.  kernel = AUTO on return means no class fits.
+struct KernelChoice {
+    int kernel;
+    int steps;
+};
+
+KernelChoice resolve_kernel(const kslb_lattice* L)
+{
+    int kernel = L->kernel;
+    if (kernel == KSLB_KERNEL_AUTO) {
+        if (L->n <= kSpanAutoMaxSites && span_default_steps(L->n, L->q) > 0) kernel = KSLB_KERNEL_SPAN;
+        else if (L->fixed) kernel = KSLB_KERNEL_PLAIN;
+        else kernel = ring_sites_per_lane(L->n, L->q) ? KSLB_KERNEL_RESIDENT : KSLB_KERNEL_TILED;
+    }
+    int steps = 0;
+    if (kernel == KSLB_KERNEL_SPAN)
+        steps = (L->kernel == KSLB_KERNEL_SPAN && L->tile_steps > 0) ? L->tile_steps : span_default_steps(L->n, L->q);
+    else if (kernel == KSLB_KERNEL_TILED)
+        steps = L->tile_steps > 0 ? L->tile_steps : default_tile_steps(L->q, L->prec);
+    return KernelChoice{kernel, steps};
+}
+
 }  // namespace
 
 extern "C" {
@@ -373,6 +400,39 @@ kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
     return KSLB_OK;
 }
 
+kslb_status kslb_get_kernel(const kslb_lattice* L, int* kernel, int* steps_per_launch, int* exchange_steps,
+                            int64_t* workgroups)
+{
+    if (auto s = check_lat(L)) return s;
+    const KernelChoice kc = resolve_kernel(L);
+    int per_launch = 1, exch = 0;
+    int64_t wg = (L->n + 255) / 256;
+    switch (kc.kernel) {
+    case KSLB_KERNEL_RESIDENT:
+        per_launch = (int)kMaxStepsPerLaunch;
+        wg = 1;
+        break;
+    case KSLB_KERNEL_SPAN:
+        per_launch = (int)kMaxStepsPerLaunch;
+        exch = kc.steps;
+        wg = kc.steps ? span_plan(L->n, L->q, kc.steps) : 0;
+        break;
+    case KSLB_KERNEL_TILED: {
+        per_launch = kc.steps;
+        const int64_t T = (int64_t)tile_lanes() * tile_sites_per_lane(L->prec) - 2 * (int64_t)halo(L->q) * kc.steps;
+        wg = T > 0 ? (L->n + T - 1) / T : 0;
+        break;
+    }
+    default:
+        break;
+    }
+    if (kernel) *kernel = kc.kernel;
+    if (steps_per_launch) *steps_per_launch = per_launch;
+    if (exchange_steps) *exchange_steps = exch;
+    if (workgroups) *workgroups = wg;
+    return KSLB_OK;
+}
+
 kslb_status kslb_set_boundary(kslb_lattice* L, int mode, double rho_left, double rho_right)
 {
     if (auto s = check_lat(L)) return s;
@@ -421,14 +481,9 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
     if (!L->have_state) return fail(KSLB_ESTATE, "advance before init_rho/write_f");
     if (n_steps == 0) return KSLB_OK;
     DeviceGuard g(L->device);
-    int kernel = L->kernel;
+    const KernelChoice kc = resolve_kernel(L);
+    const int kernel = kc.kernel;
     const int ringB = ring_sites_per_lane(L->n, L->q);
-    int span_s = 0;
-    if (kernel == KSLB_KERNEL_AUTO) {
-        if (L->n <= kSpanAutoMaxSites && (span_s = span_default_steps(L->n, L->q)) > 0) kernel = KSLB_KERNEL_SPAN;
-        else if (L->fixed) kernel = KSLB_KERNEL_PLAIN;
-        else kernel = ringB ? KSLB_KERNEL_RESIDENT : KSLB_KERNEL_TILED;
-    }
     if (L->fixed && kernel != KSLB_KERNEL_PLAIN && kernel != KSLB_KERNEL_SPAN)
         return fail(KSLB_EINVAL, "fixed ends run on the PLAIN and SPAN kernels only");
     int e = 0;
@@ -445,8 +500,7 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
             L->cur ^= 1;
         }
     } else if (kernel == KSLB_KERNEL_SPAN) {
-        const int sp = (L->kernel == KSLB_KERNEL_SPAN && L->tile_steps > 0) ? L->tile_steps
-                                                                             : span_default_steps(L->n, L->q);
+        const int sp = kc.steps;
         const int nwg = sp ? span_plan(L->n, L->q, sp) : 0;
         if (!nwg) return fail(KSLB_EINVAL, "shape cannot use the multi-workgroup kernel");
         L->span_last_nwg = nwg;
@@ -466,7 +520,7 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
             L->span_bytes = need;
         }
         int* flags = reinterpret_cast<int*>(L->span_scratch + (size_t)(4 * nwg) * (size_t)ecopy);
-        const int64_t chunk = int64_t(1) << 20;
+        const int64_t chunk = kMaxStepsPerLaunch;
         for (int64_t done = 0; done < n_steps; done += chunk) {
             const int64_t s = std::min(chunk, n_steps - done);
             e = launch_span(L->q, L->prec, L->state(), L->n, nwg, s, sp, L->span_scratch, ecopy, flags,
@@ -475,7 +529,7 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
         }
     } else if (kernel == KSLB_KERNEL_RESIDENT) {
         if (!ringB) return fail(KSLB_EINVAL, "shape cannot use the resident kernel");
-        const int64_t chunk = int64_t(1) << 20;   // bound a single launch
+        const int64_t chunk = kMaxStepsPerLaunch;
         for (int64_t done = 0; done < n_steps; done += chunk) {
             const int64_t s = std::min(chunk, n_steps - done);
             e = launch_ring(L->q, L->prec, ringB, L->state(), L->other(), L->n, s, L->ph.cf, L->stream);
@@ -483,7 +537,7 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
             L->cur ^= 1;
         }
     } else {
-        int s_max = L->tile_steps > 0 ? L->tile_steps : default_tile_steps(L->q, L->prec);
+        const int s_max = kc.steps;
         for (int64_t done = 0; done < n_steps;) {
             const int s = (int)std::min<int64_t>(s_max, n_steps - done);
             e = launch_tile(L->q, L->prec, tile_sites_per_lane(L->prec), L->state(), L->other(), L->n, s, L->ph.cf,

@@ -494,7 +494,11 @@ __global__ __launch_bounds__(256) void k_init(char* st, int64_t n, int64_t p, co
 
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
 // Renumber them so that XCD x runs a contiguous run of logical blocks: the
-// halo lines two neighbouring blocks share then sit in one L2.
+// halo lines two neighbouring tiles share then sit in one L2.  Used by the
+// tiled kernel only: the one-step streaming kernel reads each line once and
+// runs faster in hardware order (49.8 against 47.6 GLUPS at N = 2^24, D1Q7,
+// FP64, measured back to back), where all eight XCDs stream neighbouring
+// addresses at the same time.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
 {
     const int64_t per = nb / 8;
@@ -509,7 +513,7 @@ __global__ __launch_bounds__(256) void k_plain(const char* __restrict__ src, cha
 {
     using PL = Pol<Q, P>;
     constexpr int H = halo_of(Q);
-    const int64_t j = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     double g[Q];
     if (j >= H && j + H < n) {

@@ -95,6 +95,14 @@ class Lattice:
         call("kslb_set_kernel", self._h, k, steps_per_launch)
         return self
 
+    def kernel(self) -> dict:
+        """The kernel an advance runs now (AUTO resolved) and its launch shape."""
+        k, spl, ex, wg = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        call("kslb_get_kernel", self._h, ctypes.byref(k), ctypes.byref(spl), ctypes.byref(ex), ctypes.byref(wg))
+        name = {v: n for n, v in _lib.KERNELS.items()}[k.value]
+        return {"kernel": name, "steps_per_launch": spl.value, "exchange_steps": ex.value,
+                "workgroups": wg.value}
+
     def set_fixed_ends(self, rho_left: float, rho_right: float) -> "Lattice":
         """Fixed-end boundary of the paper's Table 3 problem (set before init_rho)."""
         call("kslb_set_boundary", self._h, 1, float(rho_left), float(rho_right))

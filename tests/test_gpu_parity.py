@@ -444,3 +444,33 @@ def test_zero_steps_and_errors():
         lat.set_kernel("tiled", 100000)
     with pytest.raises(KslbError):
         Lattice(100, 7).set_physical(0.2, 1e-3, 1.0)   # refused by the stability guard
+
+
+def test_resolved_kernel_and_launch_shape():
+    say("case resolved kernel")
+    # AUTO: a few thousand sites run on SPAN, larger periodic lattices on TILED
+    k = make(7, 4096).kernel()
+    assert k["kernel"] == "span" and k["steps_per_launch"] == 1 << 20
+    assert k["exchange_steps"] >= 1 and k["workgroups"] >= 2
+    n = 100_000
+    for prec, sites in (("fp64", 8), ("rho", 16)):
+        lat = Lattice(n, 7, prec).set_physical(0.3, 2e-4, 1.0)
+        k = lat.kernel()
+        s = k["steps_per_launch"]
+        assert k["kernel"] == "tiled" and s % 8 == 0 and 2 * 3 * s <= 256 * sites // 8
+        assert k["workgroups"] == -(-n // (256 * sites - 2 * 3 * s))
+        # a tiled advance of s + 1 steps is two launches: same result as s + 1 plain steps
+        lat.init_rho(ic(n, 0.3, 5)).advance(s + 1)
+        ref = Lattice(n, 7, prec).set_physical(0.3, 2e-4, 1.0).set_kernel("plain")
+        ref.init_rho(ic(n, 0.3, 5)).advance(s + 1)
+        assert np.array_equal(lat.f(), ref.f())
+    k = make(5, 1000, kernel="plain").kernel()
+    assert k == {"kernel": "plain", "steps_per_launch": 1, "exchange_steps": 0, "workgroups": 4}
+    k = make(7, 4096, kernel="resident").kernel()
+    assert k["kernel"] == "resident" and k["workgroups"] == 1
+    k = make(7, 4096, kernel="tiled", steps_per_launch=24).kernel()
+    assert k["steps_per_launch"] == 24 and k["workgroups"] == -(-4096 // (2048 - 144))
+    # fixed ends beyond the SPAN size run on PLAIN
+    lat = make(7, 70001)
+    lat.set_fixed_ends(1.0, 2.0)
+    assert lat.kernel()["kernel"] == "plain"

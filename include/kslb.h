@@ -168,16 +168,25 @@ kslb_status kslb_get_coefficients(const kslb_lattice* lat, double* E, double* G,
  * that the shape cannot use return EINVAL.                                 */
 kslb_status kslb_set_kernel(kslb_lattice* lat, int kernel, int steps_per_launch);
 
+/* Width of the SPAN kernel's workgroups: 64 lanes (one wave; lanes trade
+ * values by DPP), 128 or 256 (two or four waves trading through LDS with one
+ * barrier per step; a window of lanes x 4 sites, so edge exchanges between
+ * workgroups come 2 or 4 times less often).  0 = the library's default for
+ * the shape.  If SPAN is the chosen kernel, a width that cannot split the
+ * lattice with its steps between exchanges returns EINVAL.  Every width runs
+ * the same step, Eq. (2), with bitwise identical results.                  */
+kslb_status kslb_set_span_lanes(kslb_lattice* lat, int lanes);
+
 /* The kernel an advance runs now, with AUTO resolved for this shape and
  * boundary: its class, the most steps one launch advances (1 for PLAIN, the
  * tile's steps for TILED, 2^20 for RESIDENT and SPAN, whose longer advances
  * are split into launches of at most that many steps), the steps between
- * edge exchanges (SPAN; 0 otherwise) and the workgroups of one launch.  Any
- * output may be NULL.  Host only; enqueues nothing.  Every class runs the
- * same step, Eq. (2); the class changes how steps are scheduled, not what
- * they compute.                                                            */
+ * edge exchanges (SPAN; 0 otherwise), the workgroups of one launch and the
+ * lanes of each.  Any output may be NULL.  Host only; enqueues nothing.
+ * Every class runs the same step, Eq. (2); the class changes how steps are
+ * scheduled, not what they compute.                                        */
 kslb_status kslb_get_kernel(const kslb_lattice* lat, int* kernel, int* steps_per_launch,
-                            int* exchange_steps, int64_t* workgroups);
+                            int* exchange_steps, int64_t* workgroups, int* lanes_per_workgroup);
 
 /* Boundary of the lattice.  KSLB_PERIODIC (default) or KSLB_FIXED_ENDS: the
  * problem of the paper's Table 3, sites 0 and n_sites-1 held at the

@@ -141,6 +141,7 @@ struct kslb_lattice {
     Physics ph;
     int kernel = KSLB_KERNEL_AUTO;
     int tile_steps = 0;
+    int span_lanes = 0;                // lanes per SPAN workgroup, 0 = default
     int64_t step = 0;
     double* staging = nullptr;         // Q x n doubles, only for host transfers
     char* span_scratch = nullptr;      // edges + flags of the multi-workgroup kernel
@@ -188,14 +189,14 @@ int tile_sites_per_lane(int prec) { return prec == kRHO ? 16 : kTileB; }
 // Default steps between edge exchanges of the SPAN kernel: the largest s
 // whose owners still hold H s sites (256 >= 3 H s), or less when the lattice
 // is too small for that.
-int span_default_steps(int64_t n, int q);
+int span_default_steps(int64_t n, int q, int lanes);
 
 // Multi-workgroup plan: nwg owners of about n / nwg sites each, every window
-// (own sites + 2 H s halo) within span_lanes() x span_sites_per_lane() slots,
-// every owner at least H s sites.  Returns nwg, or 0 when the shape cannot use it.
-int span_plan(int64_t n, int q, int s)
+// (own sites + 2 H s halo) within lanes x span_sites_per_lane() slots, every
+// owner at least H s sites.  Returns nwg, or 0 when the shape cannot use it.
+int span_plan(int64_t n, int q, int s, int lanes)
 {
-    const int64_t W = (int64_t)span_lanes() * span_sites_per_lane();
+    const int64_t W = (int64_t)lanes * span_sites_per_lane();
     const int64_t hs = (int64_t)halo(q) * s;
     const int64_t own = W - 2 * hs;
     if (s < 1 || own < hs) return 0;
@@ -205,12 +206,28 @@ int span_plan(int64_t n, int q, int s)
     return (int)nwg;
 }
 
-int span_default_steps(int64_t n, int q)
+// Default steps between edge exchanges: the largest s whose owners still hold
+// H s sites (W >= 3 H s), or less when the lattice is too small for that.
+int span_default_steps(int64_t n, int q, int lanes)
 {
-    const int64_t W = (int64_t)span_lanes() * span_sites_per_lane();
+    const int64_t W = (int64_t)lanes * span_sites_per_lane();
     for (int s = (int)(W / (3 * halo(q))); s >= 1; s--)
-        if (span_plan(n, q, s)) return s;
+        if (span_plan(n, q, s, lanes)) return s;
     return 0;
+}
+
+// Default SPAN width: the widest workgroup (fewest exchanges per step) that
+// still splits the lattice over at least kSpanMinOwners owners.
+constexpr int kSpanMinOwners = 8;
+constexpr int kSpanDefaultMaxLanes = 64;
+int span_default_lanes(int64_t n, int q)
+{
+    for (int lanes : {256, 128, 64}) {
+        if (lanes > kSpanDefaultMaxLanes) continue;
+        const int s = span_default_steps(n, q, lanes);
+        if (s && (lanes == 64 || span_plan(n, q, s, lanes) >= kSpanMinOwners)) return lanes;
+    }
+    return 64;
 }
 
 // AUTO: one lattice small enough for a few hundred single-wave owners runs
@@ -242,22 +259,25 @@ constexpr int64_t kMaxStepsPerLaunch = int64_t(1) << 20;
 struct KernelChoice {
     int kernel;
     int steps;
+    int lanes;   // SPAN workgroup width
 };
 
 KernelChoice resolve_kernel(const kslb_lattice* L)
 {
     int kernel = L->kernel;
+    const int lanes = L->span_lanes > 0 ? L->span_lanes : span_default_lanes(L->n, L->q);
     if (kernel == KSLB_KERNEL_AUTO) {
-        if (L->n <= kSpanAutoMaxSites && span_default_steps(L->n, L->q) > 0) kernel = KSLB_KERNEL_SPAN;
+        if (L->n <= kSpanAutoMaxSites && span_default_steps(L->n, L->q, lanes) > 0) kernel = KSLB_KERNEL_SPAN;
         else if (L->fixed) kernel = KSLB_KERNEL_PLAIN;
         else kernel = ring_sites_per_lane(L->n, L->q) ? KSLB_KERNEL_RESIDENT : KSLB_KERNEL_TILED;
     }
     int steps = 0;
     if (kernel == KSLB_KERNEL_SPAN)
-        steps = (L->kernel == KSLB_KERNEL_SPAN && L->tile_steps > 0) ? L->tile_steps : span_default_steps(L->n, L->q);
+        steps = (L->kernel == KSLB_KERNEL_SPAN && L->tile_steps > 0) ? L->tile_steps
+                                                                     : span_default_steps(L->n, L->q, lanes);
     else if (kernel == KSLB_KERNEL_TILED)
         steps = L->tile_steps > 0 ? L->tile_steps : default_tile_steps(L->q, L->prec);
-    return KernelChoice{kernel, steps};
+    return KernelChoice{kernel, steps, lanes};
 }
 
 }  // namespace
@@ -386,10 +406,11 @@ kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
                         (long long)L->n);
     }
     if (kernel == KSLB_KERNEL_SPAN) {
-        const int sp = steps_per_launch > 0 ? steps_per_launch : span_default_steps(L->n, L->q);
-        if (!sp || !span_plan(L->n, L->q, sp))
-            return fail(KSLB_EINVAL, "n=%lld cannot be split over workgroups with %d steps between exchanges",
-                        (long long)L->n, sp);
+        const int lanes = L->span_lanes > 0 ? L->span_lanes : span_default_lanes(L->n, L->q);
+        const int sp = steps_per_launch > 0 ? steps_per_launch : span_default_steps(L->n, L->q, lanes);
+        if (!sp || !span_plan(L->n, L->q, sp, lanes))
+            return fail(KSLB_EINVAL, "n=%lld cannot be split over workgroups of %d lanes with %d steps between "
+                        "exchanges", (long long)L->n, lanes, sp);
     }
     if (kernel == KSLB_KERNEL_TILED && steps_per_launch > 0) {
         if (tile_lanes() * tile_sites_per_lane(L->prec) - 2 * halo(L->q) * steps_per_launch <= 0)
@@ -401,21 +422,25 @@ kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
 }
 
 kslb_status kslb_get_kernel(const kslb_lattice* L, int* kernel, int* steps_per_launch, int* exchange_steps,
-                            int64_t* workgroups)
+                            int64_t* workgroups, int* lanes_per_workgroup)
 {
     if (auto s = check_lat(L)) return s;
     const KernelChoice kc = resolve_kernel(L);
-    int per_launch = 1, exch = 0;
+    int per_launch = 1, exch = 0, lanes = 256;
     int64_t wg = (L->n + 255) / 256;
     switch (kc.kernel) {
-    case KSLB_KERNEL_RESIDENT:
+    case KSLB_KERNEL_RESIDENT: {
+        const int rb = ring_sites_per_lane(L->n, L->q);
         per_launch = (int)kMaxStepsPerLaunch;
         wg = 1;
+        lanes = rb ? (int)(L->n / rb) : 0;
         break;
+    }
     case KSLB_KERNEL_SPAN:
         per_launch = (int)kMaxStepsPerLaunch;
         exch = kc.steps;
-        wg = kc.steps ? span_plan(L->n, L->q, kc.steps) : 0;
+        wg = kc.steps ? span_plan(L->n, L->q, kc.steps, kc.lanes) : 0;
+        lanes = kc.lanes;
         break;
     case KSLB_KERNEL_TILED: {
         per_launch = kc.steps;
@@ -430,6 +455,22 @@ kslb_status kslb_get_kernel(const kslb_lattice* L, int* kernel, int* steps_per_l
     if (steps_per_launch) *steps_per_launch = per_launch;
     if (exchange_steps) *exchange_steps = exch;
     if (workgroups) *workgroups = wg;
+    if (lanes_per_workgroup) *lanes_per_workgroup = lanes;
+    return KSLB_OK;
+}
+
+kslb_status kslb_set_span_lanes(kslb_lattice* L, int lanes)
+{
+    if (auto s = check_lat(L)) return s;
+    if (lanes != 0 && !span_lanes_valid(lanes)) return fail(KSLB_EINVAL, "SPAN lanes must be 0, 64, 128 or 256");
+    if (L->kernel == KSLB_KERNEL_SPAN) {
+        const int w = lanes > 0 ? lanes : span_default_lanes(L->n, L->q);
+        const int sp = L->tile_steps > 0 ? L->tile_steps : span_default_steps(L->n, L->q, w);
+        if (!sp || !span_plan(L->n, L->q, sp, w))
+            return fail(KSLB_EINVAL, "n=%lld cannot be split over workgroups of %d lanes with %d steps between "
+                        "exchanges", (long long)L->n, w, sp);
+    }
+    L->span_lanes = lanes;
     return KSLB_OK;
 }
 
@@ -501,7 +542,7 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
         }
     } else if (kernel == KSLB_KERNEL_SPAN) {
         const int sp = kc.steps;
-        const int nwg = sp ? span_plan(L->n, L->q, sp) : 0;
+        const int nwg = sp ? span_plan(L->n, L->q, sp, kc.lanes) : 0;
         if (!nwg) return fail(KSLB_EINVAL, "shape cannot use the multi-workgroup kernel");
         L->span_last_nwg = nwg;
         L->span_last_ecopy = span_edge_copy_bytes(L->q, L->prec, halo(L->q) * sp);
@@ -523,7 +564,7 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
         const int64_t chunk = kMaxStepsPerLaunch;
         for (int64_t done = 0; done < n_steps; done += chunk) {
             const int64_t s = std::min(chunk, n_steps - done);
-            e = launch_span(L->q, L->prec, L->state(), L->n, nwg, s, sp, L->span_scratch, ecopy, flags,
+            e = launch_span(L->q, L->prec, kc.lanes, L->state(), L->n, nwg, s, sp, L->span_scratch, ecopy, flags,
                             flags + nwg, L->ph.cf, L->stream, L->fixed ? &L->ends : nullptr);
             if (e) return hip_fail(e, "multi-workgroup kernel");
         }

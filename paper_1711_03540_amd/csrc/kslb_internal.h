@@ -59,16 +59,17 @@ int launch_ring(int q, int prec, int B, const void* src, void* dst, int64_t n, i
                 const Coef& cf, void* stream);
 int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, int s,
                 const Coef& cf, void* stream);
-// one small lattice over nwg single-wave workgroups exchanging edges every s
-// steps; flags has nwg + 1 ints (the last is the abort word), in place on state
-int span_lanes();
+// one small lattice over nwg workgroups of `lanes` lanes (64, 128 or 256)
+// exchanging edges every s steps; flags has nwg + 1 ints (the last is the
+// abort word), in place on state
 int span_sites_per_lane();
+bool span_lanes_valid(int lanes);
 int64_t span_edge_copy_bytes(int q, int prec, int hs);
 // fixed-end boundary values (NULL / absent = periodic)
 struct Ends {
     double rho_l, rho_r;
 };
-int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase,
+int launch_span(int q, int prec, int lanes, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase,
                 int64_t ecopy, int* flags, int* abort, const Coef& cf, void* stream, const Ends* ends);
 int launch_plain_fixed(int q, int prec, const void* src, void* dst, int64_t n, const Coef& cf, const Ends& ends,
                        void* stream);

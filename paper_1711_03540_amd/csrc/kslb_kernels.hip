@@ -586,18 +586,18 @@ struct Engine {
                 slot[T * LD] = x[B - H + T].rho;           // for the right neighbour
                 slot[(H + T) * LD] = x[T].rho;             // for the left neighbour
             });
-            return;
-        }
-        unroll<Q - 1>([&](auto I1) {
-            constexpr int i = I1 + 1;
-            constexpr int c = vel(i);
-            constexpr int k0 = koff(i);
-            unroll<iabs(c)>([&](auto T) {
-                constexpr int t = T;
-                constexpr int src = (c > 0) ? (B - c + t) : t;
-                slot[(k0 + t) * LD] = PL::template pop<i>(x[src], cf);
+        } else {
+            unroll<Q - 1>([&](auto I1) {
+                constexpr int i = I1 + 1;
+                constexpr int c = vel(i);
+                constexpr int k0 = koff(i);
+                unroll<iabs(c)>([&](auto T) {
+                    constexpr int t = T;
+                    constexpr int src = (c > 0) ? (B - c + t) : t;
+                    slot[(k0 + t) * LD] = PL::template pop<i>(x[src], cf);
+                });
             });
-        });
+        }
     }
 
     // one step x -> y from registers plus hv, the values pulled from the
@@ -648,16 +648,18 @@ struct Engine {
     // Single-wave windows: the neighbour values move between lanes with DPP
     // wave rotations (lane l reads lane l-1 for c > 0, lane l+1 for c < 0),
     // with no LDS round trip and no barrier.
+    // A whole-wave rotation gives every lane a valid source lane, so the
+    // destination's previous value is never kept and need not be set first.
     __device__ static __forceinline__ double from_lane(double v, bool from_left)
     {
         const int lo = __double2loint(v), hi = __double2hiint(v);
         int rlo, rhi;
         if (from_left) {
-            rlo = __builtin_amdgcn_update_dpp(0, lo, 0x13C, 0xF, 0xF, false);   // wave_ror:1
-            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x13C, 0xF, 0xF, false);
+            rlo = __builtin_amdgcn_mov_dpp(lo, 0x13C, 0xF, 0xF, true);   // wave_ror:1
+            rhi = __builtin_amdgcn_mov_dpp(hi, 0x13C, 0xF, 0xF, true);
         } else {
-            rlo = __builtin_amdgcn_update_dpp(0, lo, 0x134, 0xF, 0xF, false);   // wave_rol:1
-            rhi = __builtin_amdgcn_update_dpp(0, hi, 0x134, 0xF, 0xF, false);
+            rlo = __builtin_amdgcn_mov_dpp(lo, 0x134, 0xF, 0xF, true);   // wave_rol:1
+            rhi = __builtin_amdgcn_mov_dpp(hi, 0x134, 0xF, 0xF, true);
         }
         return __hiloint2double(rhi, rlo);
     }
@@ -670,19 +672,18 @@ struct Engine {
                 hv[T] = from_lane(x[B - H + T].rho, true);
                 hv[H + T] = from_lane(x[T].rho, false);
             });
-            step_hv(x, y, hv, cf);
-            return;
-        }
-        unroll<Q - 1>([&](auto I1) {
-            constexpr int i = I1 + 1;
-            constexpr int c = vel(i);
-            constexpr int k0 = koff(i);
-            unroll<iabs(c)>([&](auto T) {
-                constexpr int t = T;
-                constexpr int src = (c > 0) ? (B - c + t) : t;
-                hv[k0 + t] = from_lane(PL::template pop<i>(x[src], cf), c > 0);
+        } else {
+            unroll<Q - 1>([&](auto I1) {
+                constexpr int i = I1 + 1;
+                constexpr int c = vel(i);
+                constexpr int k0 = koff(i);
+                unroll<iabs(c)>([&](auto T) {
+                    constexpr int t = T;
+                    constexpr int src = (c > 0) ? (B - c + t) : t;
+                    hv[k0 + t] = from_lane(PL::template pop<i>(x[src], cf), c > 0);
+                });
             });
-        });
+        }
         step_hv(x, y, hv, cf);
     }
 
@@ -719,10 +720,16 @@ struct Engine {
         for (; st + 1 < steps; st += 2) {
             if (active) publish(x, xch + lane, cf);
             __syncthreads();
-            if (active) step(x, y, xch + left, xch + right, cf);
-            if (active) publish(y, xch + SLOT + lane, cf);
+            if (active) {
+                step(x, y, xch + left, xch + right, cf);
+                fix(y);
+                publish(y, xch + SLOT + lane, cf);
+            }
             __syncthreads();
-            if (active) step(y, x, xch + SLOT + left, xch + SLOT + right, cf);
+            if (active) {
+                step(y, x, xch + SLOT + left, xch + SLOT + right, cf);
+                fix(x);
+            }
         }
         if (st < steps) {
             if (active) publish(x, xch + lane, cf);
@@ -730,6 +737,7 @@ struct Engine {
             if (active) {
                 step(x, y, xch + left, xch + right, cf);
                 unroll<B>([&](auto Bi) { x[Bi] = y[Bi]; });
+                fix(x);
             }
             __syncthreads();   // the next call writes slot 0 again
         }
@@ -843,8 +851,7 @@ __global__ __launch_bounds__(kTileLD) void k_ens(char* base, const WinHdr* __res
 
 // ---------------------------------------------------------------- one lattice over many workgroups
 
-constexpr int kSpanLD = 64;      // one wave per workgroup: no s_barrier stalls
-constexpr int kSpanB = 4;
+constexpr int kSpanB = 4;        // sites per lane of a SPAN window
 constexpr int kSpinLimit = 1 << 21;
 
 // Flag handshake of the multi-workgroup kernel.  Signal: a release fence
@@ -861,13 +868,14 @@ __device__ __forceinline__ void span_signal(int* flag, int value, int lane)
 __device__ __forceinline__ bool span_wait(const int* fa, const int* fb, int target, int* abort, int lane)
 {
     for (int spin = 0;; spin++) {
+        // the abort word is read with the flags: one memory round trip per poll
         const int a = __hip_atomic_load(fa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int b = __hip_atomic_load(fb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int ab = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (__builtin_amdgcn_readfirstlane(a) >= target && __builtin_amdgcn_readfirstlane(b) >= target) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             return true;
         }
-        const int ab = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (__builtin_amdgcn_readfirstlane(ab) || spin >= kSpinLimit) {
             if (lane == 0) __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
@@ -884,16 +892,26 @@ __device__ __forceinline__ bool span_wait(const int* fa, const int* fb, int targ
 // final state is written in place: a workgroup stores only after both
 // neighbours finished every chunk, so no initial load can see it.  Each wait
 // is bounded; on timeout a workgroup raises `abort` and every workgroup stops.
-template <int Q, int P, bool FIX>
-__global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t n, int64_t p, int nwg,
-                                                  int64_t steps, int s, char* __restrict__ ebase, int64_t ecopy,
-                                                  int64_t epitch, int* __restrict__ flags, int* __restrict__ abort,
-                                                  Coef cf, double rho_l, double rho_r)
+//
+// LD lanes per workgroup: one wave (LD = 64) moves values between lanes by
+// DPP; several waves exchange through LDS with one barrier per step and make
+// the window LD * B sites wide, so edge exchanges are rarer.  With several
+// waves every wave fences its own edge stores before a barrier, wave 0 alone
+// raises the flag and polls, and the outcome reaches the other waves through
+// LDS, so every wave takes the same path (abort included).
+template <int Q, int P, bool FIX, int LD>
+__global__ __launch_bounds__(LD) void k_span(char* __restrict__ st, int64_t n, int64_t p, int nwg,
+                                             int64_t steps, int s, char* __restrict__ ebase, int64_t ecopy,
+                                             int64_t epitch, int* __restrict__ flags, int* __restrict__ abort,
+                                             Coef cf, double rho_l, double rho_r)
 {
-    using E = Engine<Q, P, kSpanB, kSpanLD>;
+    using E = Engine<Q, P, kSpanB, LD>;
     using PL = typename E::PL;
     constexpr int B = kSpanB;
-    double* xch = nullptr;   // single wave: the engine exchanges by DPP
+    constexpr bool kOneWave = (LD == 64);
+    extern __shared__ double span_lds[];
+    double* xch = kOneWave ? nullptr : span_lds;   // exchange area, then one int for the wait outcome
+    int* wait_ok = kOneWave ? nullptr : reinterpret_cast<int*>(span_lds + 2 * E::SLOT);
     // consecutive owners share an XCD (workgroups are dealt round-robin to 8 XCDs)
     const int per = (nwg + 7) / 8;
     const int w = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -904,9 +922,29 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
     const int64_t M = n * (w + 1) / nwg - o;
     const int hs = E::H * s;
     const int lane = threadIdx.x;
-    const int left = lane == 0 ? kSpanLD - 1 : lane - 1;
-    const int right = lane + 1 == kSpanLD ? 0 : lane + 1;
+    const int left = lane == 0 ? LD - 1 : lane - 1;
+    const int right = lane + 1 == LD ? 0 : lane + 1;
     auto edge = [&](int64_t chunk, int who, int side) { return ebase + (((chunk & 1) * nwg + who) * 2 + side) * ecopy; };
+    // signal `value` and wait until both neighbours reached it (uniform over the workgroup)
+    auto handshake = [&](int value) -> bool {
+        if constexpr (kOneWave) {
+            span_signal(flags + w, value, lane);
+            return span_wait(flags + left_w, flags + right_w, value, abort, lane);
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this wave's edge stores
+            __syncthreads();
+            if (lane < 64) {
+                span_signal(flags + w, value, lane);
+                const bool ok = span_wait(flags + left_w, flags + right_w, value, abort, lane);
+                if (lane == 0) *wait_ok = ok ? 1 : 0;
+            }
+            __syncthreads();
+            const bool ok = *wait_ok != 0;
+            __syncthreads();   // every wave has read wait_ok before the next handshake writes it
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return ok;
+        }
+    };
 
     typename E::Site x[B];
     unroll<B>([&](auto Bi) {
@@ -943,8 +981,7 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
             if (k >= hs && k < 2 * hs) PL::store(edge(c, w, 0), epitch, k - hs, x[Bi]);
             if (k >= M && k < M + hs) PL::store(edge(c, w, 1), epitch, k - M, x[Bi]);
         });
-        span_signal(flags + w, (int)(c + 1), lane);
-        ok = span_wait(flags + left_w, flags + right_w, (int)(c + 1), abort, lane);
+        ok = handshake((int)(c + 1));
         if (!ok) break;
         // refresh the halo slots from the neighbours' edges
         unroll<B>([&](auto Bi) {
@@ -957,8 +994,7 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
     if (!ok) return;
     // final state: only after both neighbours have finished every chunk
     const int total = (int)((steps + s - 1) / s);
-    span_signal(flags + w, total, lane);
-    if (!span_wait(flags + left_w, flags + right_w, total, abort, lane)) return;
+    if (!handshake(total)) return;
     unroll<B>([&](auto Bi) {
         const int64_t k = (int64_t)lane * B + Bi;
         if (k >= hs && k < hs + M) PL::store(st, p, o + k - hs, x[Bi]);
@@ -1215,17 +1251,39 @@ int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegD
     return (int)hipErrorInvalidValue;
 }
 
-int span_lanes() { return kSpanLD; }
 int span_sites_per_lane() { return kSpanB; }
+bool span_lanes_valid(int lanes) { return lanes == 64 || lanes == 128 || lanes == 256; }
 int64_t span_edge_copy_bytes(int q, int prec, int hs) { return (int64_t)state_copy_bytes(state_pitch(hs), q, prec); }
 
-int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase,
+template <int Q, int P, bool FIX, int LD>
+static void span_one(hipStream_t st, unsigned grid, void* state, int64_t n, int nwg, int64_t steps, int s,
+                     char* ebase, int64_t ecopy, int64_t epitch, int* flags, int* abort, const Coef& cf, double rl,
+                     double rr)
+{
+    using E = Engine<Q, P, kSpanB, LD>;
+    const size_t lds = LD == 64 ? 0 : sizeof(double) * (2 * E::SLOT + 1);
+    k_span<Q, P, FIX, LD><<<grid, LD, lds, st>>>((char*)state, n, state_pitch(n), nwg, steps, s, ebase, ecopy, epitch,
+                                                 flags, abort, cf, rl, rr);
+}
+
+template <int Q, int P, bool FIX>
+static void span_lanes_dispatch(int lanes, hipStream_t st, unsigned grid, void* state, int64_t n, int nwg,
+                                int64_t steps, int s, char* ebase, int64_t ecopy, int64_t epitch, int* flags,
+                                int* abort, const Coef& cf, double rl, double rr)
+{
+    if (lanes == 64) span_one<Q, P, FIX, 64>(st, grid, state, n, nwg, steps, s, ebase, ecopy, epitch, flags, abort, cf, rl, rr);
+    else if (lanes == 128) span_one<Q, P, FIX, 128>(st, grid, state, n, nwg, steps, s, ebase, ecopy, epitch, flags, abort, cf, rl, rr);
+    else span_one<Q, P, FIX, 256>(st, grid, state, n, nwg, steps, s, ebase, ecopy, epitch, flags, abort, cf, rl, rr);
+}
+
+int launch_span(int q, int prec, int lanes, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase,
                 int64_t ecopy, int* flags, int* abort, const Coef& cf, void* stream, const Ends* ends)
 {
     hipStream_t st = (hipStream_t)stream;
     const int h = halo_of(q);
     const int64_t hs = (int64_t)h * s;
-    const int64_t W = (int64_t)kSpanLD * kSpanB;
+    if (!span_lanes_valid(lanes)) return (int)hipErrorInvalidValue;
+    const int64_t W = (int64_t)lanes * kSpanB;
     if (nwg < 2 || s < 1 || steps < 1) return (int)hipErrorInvalidValue;
     // every owner holds at least H s sites and its window fits
     const int64_t mmin = n / nwg, mmax = (n + nwg - 1) / nwg;
@@ -1235,13 +1293,12 @@ int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps,
     const unsigned grid = (unsigned)(per * 8);
     const int64_t epitch = state_pitch(hs);
     if (ends) {
-        KSLB_DISPATCH_QP(q, prec, (k_span<Q_, P_, true><<<grid, kSpanLD, 0, st>>>(
-                                      (char*)state, n, state_pitch(n), nwg, steps, s, ebase, ecopy, epitch, flags,
-                                      abort, cf, ends->rho_l, ends->rho_r)));
+        KSLB_DISPATCH_QP(q, prec, (span_lanes_dispatch<Q_, P_, true>(lanes, st, grid, state, n, nwg, steps, s, ebase,
+                                                                     ecopy, epitch, flags, abort, cf, ends->rho_l,
+                                                                     ends->rho_r)));
     } else {
-        KSLB_DISPATCH_QP(q, prec, (k_span<Q_, P_, false><<<grid, kSpanLD, 0, st>>>(
-                                      (char*)state, n, state_pitch(n), nwg, steps, s, ebase, ecopy, epitch, flags,
-                                      abort, cf, 0.0, 0.0)));
+        KSLB_DISPATCH_QP(q, prec, (span_lanes_dispatch<Q_, P_, false>(lanes, st, grid, state, n, nwg, steps, s, ebase,
+                                                                      ecopy, epitch, flags, abort, cf, 0.0, 0.0)));
     }
     return (int)hipGetLastError();
 }

@@ -90,18 +90,27 @@ class Lattice:
         return {"E": E, "G": G, "omega": om.value, "tau": tau.value, "J": jkm[0], "K": jkm[1],
                 "M": jkm[2], "dM": jkm[3], "C6": jkm[4]}
 
-    def set_kernel(self, kind="auto", steps_per_launch: int = 0) -> "Lattice":
+    def set_kernel(self, kind="auto", steps_per_launch: int = 0, span_lanes: Optional[int] = None) -> "Lattice":
+        """Kernel class and its step parameter; ``span_lanes`` (0, 64, 128, 256)
+        sets the SPAN workgroup width first when given."""
+        if span_lanes is not None:
+            call("kslb_set_span_lanes", self._h, int(span_lanes))
         k = _lib.KERNELS[kind] if isinstance(kind, str) else int(kind)
         call("kslb_set_kernel", self._h, k, steps_per_launch)
         return self
 
+    def set_span_lanes(self, lanes: int) -> "Lattice":
+        call("kslb_set_span_lanes", self._h, int(lanes))
+        return self
+
     def kernel(self) -> dict:
         """The kernel an advance runs now (AUTO resolved) and its launch shape."""
-        k, spl, ex, wg = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
-        call("kslb_get_kernel", self._h, ctypes.byref(k), ctypes.byref(spl), ctypes.byref(ex), ctypes.byref(wg))
+        k, spl, ex, wg, ln = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64(), ctypes.c_int()
+        call("kslb_get_kernel", self._h, ctypes.byref(k), ctypes.byref(spl), ctypes.byref(ex), ctypes.byref(wg),
+             ctypes.byref(ln))
         name = {v: n for n, v in _lib.KERNELS.items()}[k.value]
         return {"kernel": name, "steps_per_launch": spl.value, "exchange_steps": ex.value,
-                "workgroups": wg.value}
+                "workgroups": wg.value, "lanes": ln.value}
 
     def set_fixed_ends(self, rho_left: float, rho_right: float) -> "Lattice":
         """Fixed-end boundary of the paper's Table 3 problem (set before init_rho)."""

@@ -155,6 +155,47 @@ def test_span_kernel_in_bench_shape(spl):
     assert np.array_equal(lat.f(), plain.f())
 
 
+@pytest.mark.parametrize("q", [5, 7])
+@pytest.mark.parametrize("lanes", [128, 256])
+@pytest.mark.parametrize("n,spl", [(1000, 0), (4096, 0), (4096, 17), (12345, 0), (70001, 0)])
+def test_span_multiwave_bitwise(q, lanes, n, spl):
+    # SPAN workgroups of 2 or 4 waves (LDS exchange inside, flags between
+    # workgroups): bitwise equal to the one-step kernel, and to the oracle
+    dX, dT, tau, steps = 0.2, 1e-4, 1.1, 700
+    rho0 = ic(n, dX, 17)
+    lat = make(q, n, dX=dX, dT=dT, tau=tau)
+    lat.set_kernel("span", spl, span_lanes=lanes)
+    k = lat.kernel()
+    say("case span multiwave q=%d n=%d lanes=%d s=%d: %s" % (q, n, lanes, spl, k))
+    assert k["kernel"] == "span" and k["lanes"] == lanes and k["workgroups"] >= 2
+    assert spl == 0 or k["exchange_steps"] == spl
+    lat.init_rho(rho0).advance(steps)
+    mass, bad = lat.diagnostics()          # raises if a workgroup timed out
+    assert not bad
+    ref = make(q, n, kernel="plain", dX=dX, dT=dT, tau=tau).init_rho(rho0).advance(steps)
+    assert np.array_equal(lat.f(), ref.f())
+    if n <= 4096:
+        assert rel(lat.rho(), oracle_run(q, n, dX, dT, tau, steps, 17)[0]) < TOL64
+    # a second advance on the same lattice reuses the exchange area
+    lat.advance(steps // 3)
+    ref.advance(steps // 3)
+    assert np.array_equal(lat.f(), ref.f())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split", "rho"])
+def test_span_multiwave_reduced_storage(prec):
+    n, dX, dT = 4096, 0.3, 2e-4
+    tau = 1.0
+    rho0 = ic(n, dX, 23)
+    say("case span multiwave %s" % prec)
+    outs = []
+    for kernel, lanes in (("plain", None), ("span", 64), ("span", 256)):
+        lat = Lattice(n, 7, prec).set_physical(dX, dT, tau).set_kernel(kernel, 0, span_lanes=lanes)
+        lat.init_rho(rho0).advance(900)
+        outs.append(lat.f())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
 def test_resident_config_full_length():
     w = CFG_RESIDENT_Q7
     say("case %s full %d steps" % (w.name, w.steps))
@@ -344,15 +385,25 @@ def test_fixed_ends_table3_parity(q, dX):
     X = np.arange(n) * dX
     lo, hi = table3_ends()
     ref = oracle.solve_tanh_fixed(q, dX, dT, tau, steps)
+    from paper_1711_03540_amd import KslbError
     outs = []
-    for kernel in ("plain", "span"):
-        lat = Lattice(n, q, "fp64").set_physical(dX, dT, tau).set_kernel(kernel).set_fixed_ends(lo, hi)
+    for kernel, lanes in (("plain", None), ("span", 64), ("span", 128), ("span", 256)):
+        lat = Lattice(n, q, "fp64").set_physical(dX, dT, tau)
+        try:
+            lat.set_kernel(kernel, 0, span_lanes=lanes)
+        except KslbError:
+            assert lanes == 256      # too wide for a few hundred sites
+            continue
+        lat.set_fixed_ends(lo, hi)
+        say("  kernel %s lanes %s: %s" % (kernel, lanes, lat.kernel()))
         lat.init_rho(table3_profile(X, 0.0)).advance(steps)
         rho = lat.rho()
-        assert rel(rho, ref) < TOL64, kernel
+        assert rel(rho, ref) < TOL64, (kernel, lanes)
         assert rho[0] == pytest.approx(lo, abs=1e-14) and rho[-1] == pytest.approx(hi, abs=1e-14)
         outs.append(lat.f())
-    assert np.array_equal(outs[0], outs[1])
+    assert len(outs) >= 3
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
     G = oracle.global_error(ref, oracle.tanh_solution(X, steps * dT))
     assert G < 1e-3
 
@@ -465,7 +516,7 @@ def test_resolved_kernel_and_launch_shape():
         ref.init_rho(ic(n, 0.3, 5)).advance(s + 1)
         assert np.array_equal(lat.f(), ref.f())
     k = make(5, 1000, kernel="plain").kernel()
-    assert k == {"kernel": "plain", "steps_per_launch": 1, "exchange_steps": 0, "workgroups": 4}
+    assert k == {"kernel": "plain", "steps_per_launch": 1, "exchange_steps": 0, "workgroups": 4, "lanes": 256}
     k = make(7, 4096, kernel="resident").kernel()
     assert k["kernel"] == "resident" and k["workgroups"] == 1
     k = make(7, 4096, kernel="tiled", steps_per_launch=24).kernel()

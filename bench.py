@@ -31,16 +31,17 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 N_CU = 256
 
 # Algorithmic flops of one site update (an FMA counts 2).  Population
-# storage: density Q-1 adds, rho^2 1 mul, then per population with G != 0
-# (c = +-1, +-2) one mul + two FMA, and per population without G one mul +
-# one FMA.  Rho-only storage (tau = 1, post-collision populations feq(rho)):
-# rho^2 1 mul, then the new density sum_i A_i rho(j - c_i) + B_i rho^2(j - c_i)
-# as 1 mul + (Q + 4 - 1) FMA.
+# storage: density Q-1 adds; rho^2 1 mul; A_i rho 1 mul for c = 0 and one per
+# +-c pair (A is even in c); one FMA per population with G != 0 (c = +-1, +-2)
+# for G_i rho^2 + A_i rho; one FMA per population for (1 - omega) g_i + feq_i.
+# D1Q7: 6 + 5 + 2 * 11 = 33, D1Q5: 4 + 4 + 2 * 9 = 26.  Rho-only storage
+# (tau = 1, post-collision populations feq(rho)): rho^2 1 mul, then the new
+# density sum_i A_i rho(j - c_i) + B_i rho^2(j - c_i) as 1 mul + (Q + 4 - 1) FMA.
 def flops_per_site_update(q: int, precision: str = "fp64") -> int:
-    with_g, without_g = 4, q - 4
+    with_g = 4
     if precision == "rho":
         return 1 + 1 + 2 * (q + with_g - 1)
-    return (q - 1) + 1 + with_g * (1 + 2 * 2) + without_g * (1 + 2)
+    return (q - 1) + (2 + (q - 1) // 2) + 2 * (with_g + q)
 
 
 # Algorithmic HBM bytes of one s = 1 step per site: read Q populations and

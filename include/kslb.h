@@ -154,7 +154,9 @@ kslb_status kslb_set_physical(kslb_lattice* lat, double dX, double dT, double ta
                               int dm_variant, int guard_policy, double rho_max);
 
 /* Raw override: E[q], G[q] and omega in (0, 2).  G_i must be 0 for c_i in
- * {0, +-3} (EINVAL otherwise).  No guard.                                  */
+ * {0, +-3}, and E must be even and G odd in c exactly (E at +c equals E at
+ * -c, G at +c equals minus G at -c), the symmetry of Eq. (feq)'s weights,
+ * which the kernels use; EINVAL otherwise.  No guard.                      */
 kslb_status kslb_set_coefficients(kslb_lattice* lat, const double* E, const double* G,
                                   double omega);
 

@@ -368,6 +368,10 @@ kslb_status kslb_set_coefficients(kslb_lattice* L, const double* E, const double
         const bool g_allowed = (i >= 1 && i <= 4);
         if (!g_allowed && G[i] != 0.0) return fail(KSLB_EINVAL, "G_%d must be 0 (c = 0 or +-3)", i);
     }
+    for (int k = 1; 2 * k < L->q; k++)
+        if (E[2 * k] != E[2 * k - 1] || G[2 * k] != -G[2 * k - 1])
+            return fail(KSLB_EINVAL, "E must be even and G odd in c (E_%d = E_%d, G_%d = -G_%d)", 2 * k, 2 * k - 1,
+                        2 * k, 2 * k - 1);
     Physics ph;
     ph.set = true;
     for (int i = 0; i < L->q; i++) { ph.E[i] = E[i]; ph.G[i] = G[i]; }

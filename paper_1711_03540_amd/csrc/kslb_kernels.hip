@@ -71,6 +71,37 @@ __device__ __forceinline__ double dsum(const double (&g)[Q])
     else return ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + g[6]);
 }
 
+// Equilibrium feq_i(rho) = e_i rho + g_i rho^2 with (e, g) = (E, G) or, with
+// omega folded in, (A, B) = omega (E, G).  The equilibrium of Eq. (feq) is
+// built from the even-moment weights w(0), w(2), w(4) (and w(6) for D1Q7),
+// which take equal values at +c and -c, and from the first-moment weight w(1),
+// which changes sign; so e_{+c} = e_{-c} and g_{+c} = -g_{-c} exactly, and a
+// +-c pair shares its product e rho.  eq_one and eq_all round identically.
+template <int I>
+__device__ __forceinline__ double eq_one(double rho, const double* e, const double* g)
+{
+    if constexpr (has_g(I)) return __builtin_fma(g[I], rho * rho, e[I] * rho);
+    else return e[I] * rho;
+}
+
+template <int Q>
+__device__ __forceinline__ void eq_all(double rho, const double* e, const double* g, double (&eq)[Q])
+{
+    const double r2 = rho * rho;
+    eq[0] = e[0] * rho;
+    unroll<(Q - 1) / 2>([&](auto K) {
+        constexpr int ip = 2 * K + 1, im = 2 * K + 2;   // velocities +c, -c
+        const double a = e[ip] * rho;
+        if constexpr (has_g(ip)) {
+            eq[ip] = __builtin_fma(g[ip], r2, a);
+            eq[im] = __builtin_fma(g[im], r2, a);
+        } else {
+            eq[ip] = a;
+            eq[im] = a;
+        }
+    });
+}
+
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -96,15 +127,9 @@ struct Pol<Q, kFP64> {
 
     __device__ static __forceinline__ void update(const double (&g)[Q], Site& y, const Coef& cf)
     {
-        const double rho = dsum<Q>(g);
-        const double r2 = rho * rho;
-        unroll<Q>([&](auto I) {
-            constexpr int i = I;
-            double eq;
-            if constexpr (has_g(i)) eq = __builtin_fma(cf.A[i], rho, cf.B[i] * r2);
-            else eq = cf.A[i] * rho;
-            y.s[i] = __builtin_fma(cf.a1mw, g[i], eq);
-        });
+        double eq[Q];
+        eq_all<Q>(dsum<Q>(g), cf.A, cf.B, eq);
+        unroll<Q>([&](auto I) { y.s[I] = __builtin_fma(cf.a1mw, g[I], eq[I]); });
     }
 
     __device__ static __forceinline__ Site load(const char* st, int64_t p, int64_t j)
@@ -150,12 +175,7 @@ struct Pol<Q, kFP64> {
     __device__ static __forceinline__ Site equilibrium(double rho, const Coef& cf)
     {
         Site x;
-        const double r2 = rho * rho;
-        unroll<Q>([&](auto I) {
-            constexpr int i = I;
-            if constexpr (has_g(i)) x.s[i] = __builtin_fma(cf.E[i], rho, cf.G[i] * r2);
-            else x.s[i] = cf.E[i] * rho;
-        });
+        eq_all<Q>(rho, cf.E, cf.G, x.s);
         return x;
     }
 
@@ -192,15 +212,9 @@ struct Pol<Q, kFP32> {
     // density sum and rho^2 term in double, relaxation in single
     __device__ static __forceinline__ void update(const double (&g)[Q], Site& y, const Coef& cf)
     {
-        const double rho = dsum<Q>(g);
-        const double r2 = rho * rho;
-        unroll<Q>([&](auto I) {
-            constexpr int i = I;
-            double eq;
-            if constexpr (has_g(i)) eq = __builtin_fma(cf.A[i], rho, cf.B[i] * r2);
-            else eq = cf.A[i] * rho;
-            y.s[i] = __builtin_fmaf(cf.a1mw_f, (float)g[i], (float)eq);
-        });
+        double eq[Q];
+        eq_all<Q>(dsum<Q>(g), cf.A, cf.B, eq);
+        unroll<Q>([&](auto I) { y.s[I] = __builtin_fmaf(cf.a1mw_f, (float)g[I], (float)eq[I]); });
     }
 
     __device__ static __forceinline__ Site load(const char* st, int64_t p, int64_t j)
@@ -250,12 +264,9 @@ struct Pol<Q, kFP32> {
     __device__ static __forceinline__ Site equilibrium(double rho, const Coef& cf)
     {
         Site x;
-        const double r2 = rho * rho;
-        unroll<Q>([&](auto I) {
-            constexpr int i = I;
-            if constexpr (has_g(i)) x.s[i] = (float)__builtin_fma(cf.E[i], rho, cf.G[i] * r2);
-            else x.s[i] = (float)(cf.E[i] * rho);
-        });
+        double eq[Q];
+        eq_all<Q>(rho, cf.E, cf.G, eq);
+        unroll<Q>([&](auto I) { x.s[I] = (float)eq[I]; });
         return x;
     }
 
@@ -295,8 +306,7 @@ struct Pol<Q, kSPLIT> {
     template <int I>
     __device__ static __forceinline__ double eq_of(double rho, const Coef& cf)
     {
-        if constexpr (has_g(I)) return __builtin_fma(cf.E[I], rho, cf.G[I] * (rho * rho));
-        else return cf.E[I] * rho;
+        return eq_one<I>(rho, cf.E, cf.G);
     }
 
     template <int I>
@@ -316,10 +326,9 @@ struct Pol<Q, kSPLIT> {
     {
         const double rho = dsum<Q>(g);
         y.rho = rho;
-        unroll<Q>([&](auto I) {
-            constexpr int i = I;
-            y.n[i] = (float)(cf.a1mw * (g[i] - eq_of<i>(rho, cf)));
-        });
+        double eq[Q];
+        eq_all<Q>(rho, cf.E, cf.G, eq);
+        unroll<Q>([&](auto I) { y.n[I] = (float)(cf.a1mw * (g[I] - eq[I])); });
     }
 
     __device__ static __forceinline__ Site load(const char* st, int64_t p, int64_t j)
@@ -421,8 +430,7 @@ struct Pol<Q, kRHO> {
     template <int I>
     __device__ static __forceinline__ double eq_of(double rho, const Coef& cf)
     {
-        if constexpr (has_g(I)) return __builtin_fma(cf.A[I], rho, cf.B[I] * (rho * rho));
-        else return cf.A[I] * rho;
+        return eq_one<I>(rho, cf.A, cf.B);
     }
 
     template <int I>

@@ -87,6 +87,13 @@ int scheme_coefficients(int q, double dX, double dT, double tau, int dm_variant,
         if (E) E[i] = e;
         if (G) G[i] = J * w[1][i];
     }
+    // Eq. (feq): the even-moment weights take equal values at +c and -c and
+    // w(1) changes sign; state that symmetry exactly (the kernels share the
+    // product E rho within a +-c pair)
+    for (int k = 1; 2 * k < q; k++) {
+        if (E) E[2 * k] = E[2 * k - 1];
+        if (G) G[2 * k] = -G[2 * k - 1];
+    }
     return 0;
 }
 

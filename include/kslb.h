@@ -26,9 +26,11 @@
  *     is rho_j = sum_i f_i(j) of the paper's f at time n.
  *   - Device memory and HIP streams belong to the caller.  The library never
  *     frees a caller buffer.  It allocates only small descriptor tables, the
- *     exchange area of the SPAN kernel (four edges of H s sites per
- *     workgroup) and, when a host pointer is passed to a transfer call, one
- *     device staging buffer of Q * n_sites doubles; all live until destroy.
+ *     exchange area of the SPAN kernel (two edges of H s sites per workgroup
+ *     and exchange, for the exchanges of one launch, at most 256 MiB; a
+ *     longer advance is split into several launches) and, when a host
+ *     pointer is passed to a transfer call, one device staging buffer of
+ *     Q * n_sites doubles; all live until destroy.
  *   - Every function returns a kslb_status (0 = OK, < 0 = error) and never
  *     aborts or throws; kslb_last_error() describes the last failure of the
  *     calling thread.  Work enqueued on the stream is asynchronous; a device
@@ -89,12 +91,12 @@ enum { KSLB_GUARD_REFUSE = 0, KSLB_GUARD_RAISE_TAU = 1, KSLB_GUARD_OFF = 2 };
  *   RESIDENT : one workgroup holds the whole lattice in registers for all
  *              steps; needs n_sites = B * L with B in {4, 8}, L <= 512.
  *   TILED    : halo-widened tiles, several steps per launch in registers.
- *   SPAN     : one launch for all steps; single-wave workgroups each own a
- *              slice in registers and swap edge sites with their two
+ *   SPAN     : thousands of steps per launch; single-wave workgroups each
+ *              own a slice in registers and swap edge sites with their two
  *              neighbours every steps_per_launch steps (default: the
- *              largest s with 3 max|c| s <= 256, 28 for D1Q7) through
- *              a small library-owned exchange area; for lattices of about
- *              2 to 2000 slices of (256 - 2 H s) sites.
+ *              largest s with 3 max|c| s <= 256, 28 for D1Q7) through a
+ *              library-owned exchange area; for lattices of about 2 to 2048
+ *              slices of (256 - 2 H s) sites.
  * All classes give bitwise identical results.                              */
 enum { KSLB_KERNEL_AUTO = 0, KSLB_KERNEL_PLAIN = 1, KSLB_KERNEL_RESIDENT = 2,
        KSLB_KERNEL_TILED = 3, KSLB_KERNEL_SPAN = 4 };
@@ -170,21 +172,12 @@ kslb_status kslb_get_coefficients(const kslb_lattice* lat, double* E, double* G,
  * that the shape cannot use return EINVAL.                                 */
 kslb_status kslb_set_kernel(kslb_lattice* lat, int kernel, int steps_per_launch);
 
-/* Width of the SPAN kernel's workgroups: 64 lanes (one wave; lanes trade
- * values by DPP), 128 or 256 (two or four waves trading through LDS with one
- * barrier per step; a window of lanes x 4 sites, so edge exchanges between
- * workgroups come 2 or 4 times less often).  0 = the library's default for
- * the shape.  If SPAN is the chosen kernel, a width that cannot split the
- * lattice with its steps between exchanges returns EINVAL.  Every width runs
- * the same step, Eq. (2), with bitwise identical results.                  */
-kslb_status kslb_set_span_lanes(kslb_lattice* lat, int lanes);
-
 /* The kernel an advance runs now, with AUTO resolved for this shape and
  * boundary: its class, the most steps one launch advances (1 for PLAIN, the
- * tile's steps for TILED, 2^20 for RESIDENT and SPAN, whose longer advances
- * are split into launches of at most that many steps), the steps between
- * edge exchanges (SPAN; 0 otherwise), the workgroups of one launch and the
- * lanes of each.  Any output may be NULL.  Host only; enqueues nothing.
+ * tile's steps for TILED, 2^20 for RESIDENT, as many as the exchange area
+ * holds for SPAN; longer advances are split into launches of at most that
+ * many steps), the steps between edge exchanges (SPAN; 0 otherwise), the
+ * workgroups of one launch and the lanes of each.  Any output may be NULL.  Host only; enqueues nothing.
  * Every class runs the same step, Eq. (2); the class changes how steps are
  * scheduled, not what they compute.                                        */
 kslb_status kslb_get_kernel(const kslb_lattice* lat, int* kernel, int* steps_per_launch,

@@ -51,7 +51,6 @@ SIGNATURES = {
     "kslb_set_coefficients": (_st, [_vp, _vp, _vp, _d]),
     "kslb_get_coefficients": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "kslb_set_kernel": (_st, [_vp, _i, _i]),
-    "kslb_set_span_lanes": (_st, [_vp, _i]),
     "kslb_get_kernel": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "kslb_set_boundary": (_st, [_vp, _i, _d, _d]),
     "kslb_init_rho": (_st, [_vp, _vp, _i]),

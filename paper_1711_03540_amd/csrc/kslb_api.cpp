@@ -141,15 +141,12 @@ struct kslb_lattice {
     Physics ph;
     int kernel = KSLB_KERNEL_AUTO;
     int tile_steps = 0;
-    int span_lanes = 0;                // lanes per SPAN workgroup, 0 = default
     int64_t step = 0;
     double* staging = nullptr;         // Q x n doubles, only for host transfers
     char* span_scratch = nullptr;      // edges + flags of the multi-workgroup kernel
     size_t span_bytes = 0;
     bool fixed = false;                // fixed-end boundary (Table 3 problem)
     Ends ends{0.0, 0.0};
-    int span_last_nwg = 0;             // geometry of the last multi-workgroup launch
-    int64_t span_last_ecopy = 0;
 
     char* state() { return buf + (size_t)cur * copy; }
     char* other() { return buf + (size_t)(1 - cur) * copy; }
@@ -185,50 +182,39 @@ int ring_sites_per_lane(int64_t n, int q)
 }
 
 constexpr int kTileB = 8;
+constexpr int kSpanMaxOwners = 2048;
 int tile_sites_per_lane(int prec) { return prec == kRHO ? 16 : kTileB; }
-// Default steps between edge exchanges of the SPAN kernel: the largest s
-// whose owners still hold H s sites (256 >= 3 H s), or less when the lattice
-// is too small for that.
-int span_default_steps(int64_t n, int q, int lanes);
-
-// Multi-workgroup plan: nwg owners of about n / nwg sites each, every window
-// (own sites + 2 H s halo) within lanes x span_sites_per_lane() slots, every
-// owner at least H s sites.  Returns nwg, or 0 when the shape cannot use it.
-int span_plan(int64_t n, int q, int s, int lanes)
+// Multi-workgroup plan: nwg single-wave owners of about n / nwg sites each,
+// every window (own sites + 2 H s halo) within span_lanes() x
+// span_sites_per_lane(q) slots, every owner at least H s sites.  Returns nwg,
+// or 0 when the shape cannot use it.
+int span_plan(int64_t n, int q, int s)
 {
-    const int64_t W = (int64_t)lanes * span_sites_per_lane();
+    const int64_t W = (int64_t)span_lanes() * span_sites_per_lane(q);
     const int64_t hs = (int64_t)halo(q) * s;
     const int64_t own = W - 2 * hs;
     if (s < 1 || own < hs) return 0;
     const int64_t nwg = (n + own - 1) / own;
-    if (nwg < 2 || nwg > 2048) return 0;
+    if (nwg < 2 || nwg > kSpanMaxOwners) return 0;
     if (n / nwg < hs) return 0;
     return (int)nwg;
 }
 
 // Default steps between edge exchanges: the largest s whose owners still hold
 // H s sites (W >= 3 H s), or less when the lattice is too small for that.
-int span_default_steps(int64_t n, int q, int lanes)
+int span_default_steps(int64_t n, int q)
 {
-    const int64_t W = (int64_t)lanes * span_sites_per_lane();
+    const int64_t W = (int64_t)span_lanes() * span_sites_per_lane(q);
     for (int s = (int)(W / (3 * halo(q))); s >= 1; s--)
-        if (span_plan(n, q, s, lanes)) return s;
+        if (span_plan(n, q, s)) return s;
     return 0;
 }
 
-// Default SPAN width: the widest workgroup (fewest exchanges per step) that
-// still splits the lattice over at least kSpanMinOwners owners.
-constexpr int kSpanMinOwners = 8;
-constexpr int kSpanDefaultMaxLanes = 64;
-int span_default_lanes(int64_t n, int q)
-{
-    for (int lanes : {256, 128, 64}) {
-        if (lanes > kSpanDefaultMaxLanes) continue;
-        const int s = span_default_steps(n, q, lanes);
-        if (s && (lanes == 64 || span_plan(n, q, s, lanes) >= kSpanMinOwners)) return lanes;
-    }
-    return 64;
-}
+// Device scratch of the SPAN kernel: a control block sized for the most
+// owners, then the edge slots of one launch, at most kSpanSlotBytes of them
+// (a longer advance is split into launches of (slots + 1) s steps).
+constexpr size_t kSpanCtlBytes = (size_t)(kSpanMaxOwners + 64) * sizeof(int);
+constexpr size_t kSpanSlotBytes = size_t(256) << 20;
 
 // AUTO: one lattice small enough for a few hundred single-wave owners runs
 // on SPAN; otherwise RESIDENT when it fits one workgroup, else TILED.
@@ -259,28 +245,88 @@ constexpr int64_t kMaxStepsPerLaunch = int64_t(1) << 20;
 struct KernelChoice {
     int kernel;
     int steps;
-    int lanes;   // SPAN workgroup width
 };
 
 KernelChoice resolve_kernel(const kslb_lattice* L)
 {
     int kernel = L->kernel;
-    const int lanes = L->span_lanes > 0 ? L->span_lanes : span_default_lanes(L->n, L->q);
     if (kernel == KSLB_KERNEL_AUTO) {
-        if (L->n <= kSpanAutoMaxSites && span_default_steps(L->n, L->q, lanes) > 0) kernel = KSLB_KERNEL_SPAN;
+        if (L->n <= kSpanAutoMaxSites && span_default_steps(L->n, L->q) > 0) kernel = KSLB_KERNEL_SPAN;
         else if (L->fixed) kernel = KSLB_KERNEL_PLAIN;
         else kernel = ring_sites_per_lane(L->n, L->q) ? KSLB_KERNEL_RESIDENT : KSLB_KERNEL_TILED;
     }
     int steps = 0;
     if (kernel == KSLB_KERNEL_SPAN)
-        steps = (L->kernel == KSLB_KERNEL_SPAN && L->tile_steps > 0) ? L->tile_steps
-                                                                     : span_default_steps(L->n, L->q, lanes);
+        steps = (L->kernel == KSLB_KERNEL_SPAN && L->tile_steps > 0) ? L->tile_steps : span_default_steps(L->n, L->q);
     else if (kernel == KSLB_KERNEL_TILED)
         steps = L->tile_steps > 0 ? L->tile_steps : default_tile_steps(L->q, L->prec);
-    return KernelChoice{kernel, steps, lanes};
+    return KernelChoice{kernel, steps};
 }
 
 }  // namespace
+
+// Bytes of one SPAN edge copy: ceil(n / nwg) sites in state format.
+int64_t span_copy_bytes(const kslb_lattice* L, int nwg)
+{
+    return span_edge_copy_bytes(L->q, L->prec, (L->n + nwg - 1) / nwg);
+}
+
+// Edge slots one SPAN launch can use, and the steps such a launch covers.
+int64_t span_slot_capacity(const kslb_lattice* L, int nwg, int s)
+{
+    const int64_t per = (int64_t)nwg * span_copy_bytes(L, nwg);
+    return std::max<int64_t>(1, std::min<int64_t>((int64_t)kSpanSlotBytes / per, kMaxStepsPerLaunch / s));
+}
+
+int64_t span_steps_per_launch(const kslb_lattice* L, int nwg, int s)
+{
+    return std::min<int64_t>(kMaxStepsPerLaunch, (span_slot_capacity(L, nwg, s) + 1) * s);
+}
+
+// Scratch for a SPAN advance of n_steps: the control block and the edge
+// slots of (up to) one launch; *slots_out is every slot the area holds in
+// this geometry.  Each launch refills the slots it uses with the sentinel.
+kslb_status span_prepare(kslb_lattice* L, int nwg, int s, int64_t n_steps, int64_t* slots_out)
+{
+    const int64_t per = (int64_t)nwg * span_copy_bytes(L, nwg);
+    const int64_t exchanges = (std::min(n_steps, span_steps_per_launch(L, nwg, s)) + s - 1) / s - 1;
+    const int64_t want = std::max<int64_t>(1, std::min(span_slot_capacity(L, nwg, s), exchanges));
+    int64_t have = L->span_scratch ? (int64_t)(L->span_bytes - kSpanCtlBytes) / per : 0;
+    if (have < want) {
+        const size_t need = kSpanCtlBytes + (size_t)want * (size_t)per;
+        int sticky = 0;
+        int e = 0;
+        if (L->span_scratch) {
+            // keep the error word across the reallocation
+            e = hipMemcpyAsync(&sticky, reinterpret_cast<int*>(L->span_scratch) + span_ctl_error_index(), sizeof sticky,
+                               hipMemcpyDeviceToHost, L->stream);
+            if (!e) e = hipStreamSynchronize(L->stream);
+            if (e) return hip_fail(e, "SPAN control copy");
+            (void)hipFree(L->span_scratch);
+            L->span_scratch = nullptr;
+            L->span_bytes = 0;
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, need)) return fail(KSLB_ENOMEM, "exchange area of %zu bytes failed", need);
+        L->span_scratch = (char*)p;
+        L->span_bytes = need;
+        int* ctl = reinterpret_cast<int*>(L->span_scratch);
+        e = launch_span_ctl_init(ctl, (int)(kSpanCtlBytes / sizeof(int)), L->stream);
+        if (!e && sticky) e = launch_span_set_ctl(ctl, span_ctl_error_index(), 1, L->stream);
+        if (e) return hip_fail(e, "SPAN control init");
+        have = want;
+    }
+    *slots_out = have;
+    return KSLB_OK;
+}
+
+// A new state: forget SPAN timeouts of the previous one.
+kslb_status span_clear_error(kslb_lattice* L)
+{
+    if (!L->span_scratch) return KSLB_OK;
+    int e = launch_span_set_ctl(reinterpret_cast<int*>(L->span_scratch), span_ctl_error_index(), 0, L->stream);
+    return e ? hip_fail(e, "SPAN control") : KSLB_OK;
+}
 
 extern "C" {
 
@@ -410,11 +456,10 @@ kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
                         (long long)L->n);
     }
     if (kernel == KSLB_KERNEL_SPAN) {
-        const int lanes = L->span_lanes > 0 ? L->span_lanes : span_default_lanes(L->n, L->q);
-        const int sp = steps_per_launch > 0 ? steps_per_launch : span_default_steps(L->n, L->q, lanes);
-        if (!sp || !span_plan(L->n, L->q, sp, lanes))
-            return fail(KSLB_EINVAL, "n=%lld cannot be split over workgroups of %d lanes with %d steps between "
-                        "exchanges", (long long)L->n, lanes, sp);
+        const int sp = steps_per_launch > 0 ? steps_per_launch : span_default_steps(L->n, L->q);
+        if (!sp || !span_plan(L->n, L->q, sp))
+            return fail(KSLB_EINVAL, "n=%lld cannot be split over workgroups with %d steps between exchanges",
+                        (long long)L->n, sp);
     }
     if (kernel == KSLB_KERNEL_TILED && steps_per_launch > 0) {
         if (tile_lanes() * tile_sites_per_lane(L->prec) - 2 * halo(L->q) * steps_per_launch <= 0)
@@ -441,10 +486,10 @@ kslb_status kslb_get_kernel(const kslb_lattice* L, int* kernel, int* steps_per_l
         break;
     }
     case KSLB_KERNEL_SPAN:
-        per_launch = (int)kMaxStepsPerLaunch;
         exch = kc.steps;
-        wg = kc.steps ? span_plan(L->n, L->q, kc.steps, kc.lanes) : 0;
-        lanes = kc.lanes;
+        wg = kc.steps ? span_plan(L->n, L->q, kc.steps) : 0;
+        per_launch = wg ? (int)span_steps_per_launch(L, (int)wg, kc.steps) : 0;
+        lanes = span_lanes();
         break;
     case KSLB_KERNEL_TILED: {
         per_launch = kc.steps;
@@ -460,21 +505,6 @@ kslb_status kslb_get_kernel(const kslb_lattice* L, int* kernel, int* steps_per_l
     if (exchange_steps) *exchange_steps = exch;
     if (workgroups) *workgroups = wg;
     if (lanes_per_workgroup) *lanes_per_workgroup = lanes;
-    return KSLB_OK;
-}
-
-kslb_status kslb_set_span_lanes(kslb_lattice* L, int lanes)
-{
-    if (auto s = check_lat(L)) return s;
-    if (lanes != 0 && !span_lanes_valid(lanes)) return fail(KSLB_EINVAL, "SPAN lanes must be 0, 64, 128 or 256");
-    if (L->kernel == KSLB_KERNEL_SPAN) {
-        const int w = lanes > 0 ? lanes : span_default_lanes(L->n, L->q);
-        const int sp = L->tile_steps > 0 ? L->tile_steps : span_default_steps(L->n, L->q, w);
-        if (!sp || !span_plan(L->n, L->q, sp, w))
-            return fail(KSLB_EINVAL, "n=%lld cannot be split over workgroups of %d lanes with %d steps between "
-                        "exchanges", (long long)L->n, w, sp);
-    }
-    L->span_lanes = lanes;
     return KSLB_OK;
 }
 
@@ -515,6 +545,7 @@ kslb_status kslb_init_rho(kslb_lattice* L, const double* rho, int rho_on_device)
         if (e) return hip_fail(e, "hipStreamSynchronize");
     }
     L->have_state = true;
+    if (auto st = span_clear_error(L)) return st;
     L->step = 0;
     return KSLB_OK;
 }
@@ -546,30 +577,18 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
         }
     } else if (kernel == KSLB_KERNEL_SPAN) {
         const int sp = kc.steps;
-        const int nwg = sp ? span_plan(L->n, L->q, sp, kc.lanes) : 0;
+        const int nwg = sp ? span_plan(L->n, L->q, sp) : 0;
         if (!nwg) return fail(KSLB_EINVAL, "shape cannot use the multi-workgroup kernel");
-        L->span_last_nwg = nwg;
-        L->span_last_ecopy = span_edge_copy_bytes(L->q, L->prec, halo(L->q) * sp);
-        const int64_t ecopy = span_edge_copy_bytes(L->q, L->prec, halo(L->q) * sp);
-        const size_t need = (size_t)(4 * nwg) * (size_t)ecopy + 256 + sizeof(int) * (size_t)(nwg + 1);
-        if (L->span_bytes < need) {
-            if (L->span_scratch) {
-                (void)hipStreamSynchronize(L->stream);
-                (void)hipFree(L->span_scratch);
-                L->span_scratch = nullptr;
-                L->span_bytes = 0;
-            }
-            void* p = nullptr;
-            if (hipMalloc(&p, need)) return fail(KSLB_ENOMEM, "exchange area of %zu bytes failed", need);
-            L->span_scratch = (char*)p;
-            L->span_bytes = need;
-        }
-        int* flags = reinterpret_cast<int*>(L->span_scratch + (size_t)(4 * nwg) * (size_t)ecopy);
-        const int64_t chunk = kMaxStepsPerLaunch;
+        int64_t slots = 0;
+        if (auto st = span_prepare(L, nwg, sp, n_steps, &slots)) return st;
+        const int64_t ecopy = span_copy_bytes(L, nwg);
+        int* ctl = reinterpret_cast<int*>(L->span_scratch);
+        char* ebase = L->span_scratch + kSpanCtlBytes;
+        const int64_t chunk = std::min<int64_t>(kMaxStepsPerLaunch, (slots + 1) * sp);
         for (int64_t done = 0; done < n_steps; done += chunk) {
             const int64_t s = std::min(chunk, n_steps - done);
-            e = launch_span(L->q, L->prec, kc.lanes, L->state(), L->n, nwg, s, sp, L->span_scratch, ecopy, flags,
-                            flags + nwg, L->ph.cf, L->stream, L->fixed ? &L->ends : nullptr);
+            e = launch_span(L->q, L->prec, L->state(), L->n, nwg, s, sp, ebase, ecopy, slots, ctl, L->ph.cf,
+                            L->stream, L->fixed ? &L->ends : nullptr);
             if (e) return hip_fail(e, "multi-workgroup kernel");
         }
     } else if (kernel == KSLB_KERNEL_RESIDENT) {
@@ -665,6 +684,7 @@ kslb_status kslb_write_f(kslb_lattice* L, const double* in, int in_on_device, in
         if (e) return hip_fail(e, "hipStreamSynchronize");
     }
     L->have_state = true;
+    if (auto st = span_clear_error(L)) return st;
     L->step = step;
     return KSLB_OK;
 }
@@ -692,6 +712,7 @@ kslb_status kslb_load_state(kslb_lattice* L, const void* dev_src, int64_t step)
     int e = hipMemcpyAsync(L->state(), dev_src, L->copy, hipMemcpyDeviceToDevice, L->stream);
     if (e) return hip_fail(e, "hipMemcpyAsync(load)");
     L->have_state = true;
+    if (auto st = span_clear_error(L)) return st;
     L->step = step;
     return KSLB_OK;
 }
@@ -723,16 +744,12 @@ kslb_status kslb_diagnostics(kslb_lattice* L, double* mass, int* nonfinite)
     if (mass) *mass = m;
     if (nonfinite) *nonfinite = f;
     if (L->span_scratch) {
-        // the abort word follows the flags of the last multi-workgroup launch
-        int ab = 0;
-        const int nwg = L->span_last_nwg;
-        if (nwg) {
-            const int64_t ecopy = L->span_last_ecopy;
-            const int* abort_d = reinterpret_cast<const int*>(L->span_scratch + (size_t)(4 * nwg) * (size_t)ecopy) + nwg;
-            e = hipMemcpy(&ab, abort_d, sizeof ab, hipMemcpyDeviceToHost);
-            if (e) return hip_fail(e, "abort word copy");
-            if (ab) return fail(KSLB_EDEVICE, "a multi-workgroup launch timed out waiting for a neighbour");
-        }
+        int err = 0;
+        e = hipMemcpyAsync(&err, reinterpret_cast<const int*>(L->span_scratch) + span_ctl_error_index(), sizeof err,
+                           hipMemcpyDeviceToHost, L->stream);
+        if (!e) e = hipStreamSynchronize(L->stream);
+        if (e) return hip_fail(e, "SPAN control copy");
+        if (err) return fail(KSLB_EDEVICE, "a multi-workgroup launch timed out waiting for a neighbour");
     }
     return KSLB_OK;
 }

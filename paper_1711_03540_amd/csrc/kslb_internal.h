@@ -59,18 +59,25 @@ int launch_ring(int q, int prec, int B, const void* src, void* dst, int64_t n, i
                 const Coef& cf, void* stream);
 int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, int s,
                 const Coef& cf, void* stream);
-// one small lattice over nwg workgroups of `lanes` lanes (64, 128 or 256)
-// exchanging edges every s steps; flags has nwg + 1 ints (the last is the
-// abort word), in place on state
-int span_sites_per_lane();
-bool span_lanes_valid(int lanes);
-int64_t span_edge_copy_bytes(int q, int prec, int hs);
+// One small lattice over nwg single-wave workgroups exchanging edges every s
+// steps through `slots` edge slots per launch (slots * nwg copies of ecopy
+// bytes from ebase, each holding ceil(n / nwg) sites in state format; see
+// span_edge_copy_bytes).  ctl holds span_ctl_ints(nwg) ints (abort, sticky
+// error, then the handshake flags), set up by launch_span_ctl_init.  The
+// state is advanced in place.
+int span_lanes();
+int span_sites_per_lane(int q);
+int span_ctl_ints(int nwg);
+int span_ctl_error_index();   // sticky: a launch timed out since the state was set
+int64_t span_edge_copy_bytes(int q, int prec, int64_t sites);
+int launch_span_ctl_init(int* ctl, int count, void* stream);
+int launch_span_set_ctl(int* ctl, int index, int value, void* stream);
 // fixed-end boundary values (NULL / absent = periodic)
 struct Ends {
     double rho_l, rho_r;
 };
-int launch_span(int q, int prec, int lanes, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase,
-                int64_t ecopy, int* flags, int* abort, const Coef& cf, void* stream, const Ends* ends);
+int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase, int64_t ecopy,
+                int64_t slots, int* ctl, const Coef& cf, void* stream, const Ends* ends);
 int launch_plain_fixed(int q, int prec, const void* src, void* dst, int64_t n, const Coef& cf, const Ends& ends,
                        void* stream);
 int launch_init_fixed(int q, int prec, void* state, int64_t n, const double* rho0, const Coef& cf, const Ends& ends,

@@ -23,6 +23,7 @@
 // from registers plus the neighbours' values.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <utility>
 
 #include "kslb_internal.h"
@@ -859,67 +860,188 @@ __global__ __launch_bounds__(kTileLD) void k_ens(char* base, const WinHdr* __res
 
 // ---------------------------------------------------------------- one lattice over many workgroups
 
-constexpr int kSpanB = 4;        // sites per lane of a SPAN window
+constexpr int kSpanLD = 64;      // one wave per workgroup: lanes trade values by DPP, no barrier
+// Sites per lane of a SPAN window: the fewest a lane can hold (max|c|), so
+// that a step's dependency chain is short; a narrower window exchanges more
+// often, which measures as the better trade for the lattices SPAN serves.
+__host__ __device__ constexpr int span_b_of(int q) { return halo_of(q); }
 constexpr int kSpinLimit = 1 << 21;
+constexpr int kFirstPollDelay = 6;   // units of 64 clocks before the first poll of an exchange
 
-// Flag handshake of the multi-workgroup kernel.  Signal: a release fence
-// (this wave's edge stores become visible at device scope) and a relaxed
-// store of the chunk count.  Wait: relaxed polls of both neighbours' flags,
-// then one acquire fence; a bounded number of polls, after which the abort
-// word is raised and every waiter gives up.
+// Control words of the multi-workgroup kernel (device memory, kept by the
+// lattice across launches): the abort word of the current launch, a sticky
+// error word (set with it, cleared only when the state is replaced), then the
+// nwg flags of the final handshake.
+constexpr int kCtlAbort = 0, kCtlSticky = 1, kCtlFlags = 4;
+
+// Edge slots.  At exchange c owner w stores its own sites, once, into slot
+// (c, w); its left neighbour reads the first H s of them, its right
+// neighbour the last H s.  Within one launch every slot word is written once;
+// before the launch the whole area holds a sentinel no arithmetic produces (a
+// signalling NaN with a fixed payload).  Writer and readers use relaxed
+// device-scope atomic accesses per word, so a reader needs no flag and no
+// fence: a word that no longer holds the sentinel holds its one value of this
+// launch.
+// s_waitcnt vmcnt(0) with expcnt and lgkmcnt left at their maximum (gfx9
+// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+constexpr unsigned long long kSent64 = 0x7FF4A5A5A5A5A5A5ull;
+constexpr unsigned int kSent32 = 0x7FA5A5A5u;
+
+__device__ __forceinline__ void st_sync(double* a, double v)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(a), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_sync(float* a, float v)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned int*>(a), __float_as_uint(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool ld_sync(const double* a, double& v)
+{
+    const unsigned long long u = __hip_atomic_load(reinterpret_cast<unsigned long long*>(const_cast<double*>(a)),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v = __longlong_as_double((long long)u);
+    return u != kSent64;
+}
+__device__ __forceinline__ bool ld_sync(const float* a, float& v)
+{
+    const unsigned int u = __hip_atomic_load(reinterpret_cast<unsigned int*>(const_cast<float*>(a)),
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v = __uint_as_float(u);
+    return u != kSent32;
+}
+__device__ __forceinline__ void st_sent(double* a)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(a), kSent64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_sent(float* a)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned int*>(a), kSent32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Word-wise access to one site of a state-format copy (pitch p): every word
+// of the site through fn(pointer, member).
+template <int Q, int P>
+struct SiteWords;
+
+template <int Q>
+struct SiteWords<Q, kFP64> {
+    template <class S, class F>
+    __device__ static __forceinline__ void each(char* st, int64_t p, int64_t j, S& x, F&& fn)
+    {
+        unroll<Q>([&](auto I) { fn(reinterpret_cast<double*>(st) + I * p + j, x.s[I]); });
+    }
+};
+template <int Q>
+struct SiteWords<Q, kFP32> {
+    template <class S, class F>
+    __device__ static __forceinline__ void each(char* st, int64_t p, int64_t j, S& x, F&& fn)
+    {
+        unroll<Q>([&](auto I) { fn(reinterpret_cast<float*>(st) + I * p + j, x.s[I]); });
+    }
+};
+template <int Q>
+struct SiteWords<Q, kSPLIT> {
+    template <class S, class F>
+    __device__ static __forceinline__ void each(char* st, int64_t p, int64_t j, S& x, F&& fn)
+    {
+        fn(reinterpret_cast<double*>(st) + j, x.rho);
+        float* nb = reinterpret_cast<float*>(st + p * (int64_t)sizeof(double));
+        unroll<Q>([&](auto I) { fn(nb + I * p + j, x.n[I]); });
+    }
+};
+template <int Q>
+struct SiteWords<Q, kRHO> {
+    template <class S, class F>
+    __device__ static __forceinline__ void each(char* st, int64_t, int64_t j, S& x, F&& fn)
+    {
+        fn(reinterpret_cast<double*>(st) + j, x.rho);
+    }
+};
+
+template <int Q, int P>
+__device__ __forceinline__ void site_store_sync(char* st, int64_t p, int64_t j, const typename Pol<Q, P>::Site& x)
+{
+    typename Pol<Q, P>::Site y = x;
+    SiteWords<Q, P>::each(st, p, j, y, [](auto* a, auto v) { st_sync(a, v); });
+}
+
+// true when no word of the site holds the sentinel (all loads are issued
+// before any result is tested)
+template <int Q, int P>
+__device__ __forceinline__ bool site_load_sync(char* st, int64_t p, int64_t j, typename Pol<Q, P>::Site& x)
+{
+    int missing = 0;
+    SiteWords<Q, P>::each(st, p, j, x, [&](auto* a, auto& v) { missing |= ld_sync(a, v) ? 0 : 1; });
+    return missing == 0;
+}
+
+template <int Q, int P>
+__device__ __forceinline__ void site_store_sentinel(char* st, int64_t p, int64_t j)
+{
+    typename Pol<Q, P>::Site y{};
+    SiteWords<Q, P>::each(st, p, j, y, [](auto* a, auto) { st_sent(a); });
+}
+
+// Final handshake of a launch: a release fence and a relaxed store of the
+// flag; relaxed polls of both neighbours' flags (with the abort word, one
+// memory round trip per poll), then one acquire fence.  Bounded: on timeout
+// the abort and sticky words are raised and every waiter gives up.
+__device__ __forceinline__ void span_raise_abort(int* ctl, int lane)
+{
+    if (lane == 0) {
+        __hip_atomic_store(ctl + kCtlAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(ctl + kCtlSticky, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 __device__ __forceinline__ void span_signal(int* flag, int value, int lane)
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (lane == 0) __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ bool span_wait(const int* fa, const int* fb, int target, int* abort, int lane)
+__device__ __forceinline__ bool span_wait(const int* fa, const int* fb, int target, int* ctl, int lane)
 {
     for (int spin = 0;; spin++) {
-        // the abort word is read with the flags: one memory round trip per poll
         const int a = __hip_atomic_load(fa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int b = __hip_atomic_load(fb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int ab = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int ab = __hip_atomic_load(ctl + kCtlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (__builtin_amdgcn_readfirstlane(a) >= target && __builtin_amdgcn_readfirstlane(b) >= target) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             return true;
         }
         if (__builtin_amdgcn_readfirstlane(ab) || spin >= kSpinLimit) {
-            if (lane == 0) __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            span_raise_abort(ctl, lane);
             return false;
         }
         __builtin_amdgcn_s_sleep(1);
     }
 }
 
-// Workgroup w owns sites [o_w, o_w + M_w) of a periodic lattice and holds
-// them, plus H s halo sites on each side, in its registers (slot k <-> site
-// o_w - H s + k).  Every s steps it publishes its first and last H s own sites
-// to a double-buffered edge area, raises its flag to the chunk count, waits for
-// both neighbours' flags, and refreshes its halo slots from their edges.  The
-// final state is written in place: a workgroup stores only after both
-// neighbours finished every chunk, so no initial load can see it.  Each wait
-// is bounded; on timeout a workgroup raises `abort` and every workgroup stops.
-//
-// LD lanes per workgroup: one wave (LD = 64) moves values between lanes by
-// DPP; several waves exchange through LDS with one barrier per step and make
-// the window LD * B sites wide, so edge exchanges are rarer.  With several
-// waves every wave fences its own edge stores before a barrier, wave 0 alone
-// raises the flag and polls, and the outcome reaches the other waves through
-// LDS, so every wave takes the same path (abort included).
-template <int Q, int P, bool FIX, int LD>
-__global__ __launch_bounds__(LD) void k_span(char* __restrict__ st, int64_t n, int64_t p, int nwg,
-                                             int64_t steps, int s, char* __restrict__ ebase, int64_t ecopy,
-                                             int64_t epitch, int* __restrict__ flags, int* __restrict__ abort,
-                                             Coef cf, double rho_l, double rho_r)
+// Workgroup w owns sites [o_w, o_w + M_w) of the lattice and holds them, plus
+// H s halo sites on each side, in its registers (window slot k <-> site
+// o_w - H s + k).  Every s steps it stores its own sites to its edge slot of
+// this exchange and loads its halo from the neighbours' slots, polling until
+// no word holds the sentinel.  The final state is written in place after a
+// flag handshake with both neighbours, so no initial load can see it.  Every
+// wait is bounded; on timeout a workgroup raises the abort word and every
+// workgroup stops.
+template <int Q, int P, bool FIX>
+__global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t n, int64_t p, int nwg,
+                                                  int64_t steps, int s, char* __restrict__ ebase, int64_t ecopy,
+                                                  int64_t epitch, int64_t slots, int* __restrict__ ctl, Coef cf,
+                                                  double rho_l, double rho_r)
 {
-    using E = Engine<Q, P, kSpanB, LD>;
+    using E = Engine<Q, P, span_b_of(Q), kSpanLD>;
     using PL = typename E::PL;
-    constexpr int B = kSpanB;
-    constexpr bool kOneWave = (LD == 64);
-    extern __shared__ double span_lds[];
-    double* xch = kOneWave ? nullptr : span_lds;   // exchange area, then one int for the wait outcome
-    int* wait_ok = kOneWave ? nullptr : reinterpret_cast<int*>(span_lds + 2 * E::SLOT);
+    using Site = typename E::Site;
+    constexpr int B = span_b_of(Q);
+    double* xch = nullptr;   // single wave: the engine exchanges by DPP
+    int* flags = ctl + kCtlFlags;
     // consecutive owners share an XCD (workgroups are dealt round-robin to 8 XCDs)
     const int per = (nwg + 7) / 8;
     const int w = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -930,31 +1052,12 @@ __global__ __launch_bounds__(LD) void k_span(char* __restrict__ st, int64_t n, i
     const int64_t M = n * (w + 1) / nwg - o;
     const int hs = E::H * s;
     const int lane = threadIdx.x;
-    const int left = lane == 0 ? LD - 1 : lane - 1;
-    const int right = lane + 1 == LD ? 0 : lane + 1;
-    auto edge = [&](int64_t chunk, int who, int side) { return ebase + (((chunk & 1) * nwg + who) * 2 + side) * ecopy; };
-    // signal `value` and wait until both neighbours reached it (uniform over the workgroup)
-    auto handshake = [&](int value) -> bool {
-        if constexpr (kOneWave) {
-            span_signal(flags + w, value, lane);
-            return span_wait(flags + left_w, flags + right_w, value, abort, lane);
-        } else {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this wave's edge stores
-            __syncthreads();
-            if (lane < 64) {
-                span_signal(flags + w, value, lane);
-                const bool ok = span_wait(flags + left_w, flags + right_w, value, abort, lane);
-                if (lane == 0) *wait_ok = ok ? 1 : 0;
-            }
-            __syncthreads();
-            const bool ok = *wait_ok != 0;
-            __syncthreads();   // every wave has read wait_ok before the next handshake writes it
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            return ok;
-        }
-    };
+    const int left = lane == 0 ? kSpanLD - 1 : lane - 1;
+    const int right = lane + 1 == kSpanLD ? 0 : lane + 1;
+    auto slot = [&](int64_t chunk, int who) { return ebase + (chunk * nwg + who) * ecopy; };
+    const int64_t M_left = n * (left_w + 1) / nwg - n * left_w / nwg;   // own sites of the left neighbour
 
-    typename E::Site x[B];
+    Site x[B];
     unroll<B>([&](auto Bi) {
         const int64_t k = (int64_t)lane * B + Bi;
         x[Bi] = PL::load(st, p, wrap_site(o - hs + k, n));
@@ -964,8 +1067,8 @@ __global__ __launch_bounds__(LD) void k_span(char* __restrict__ st, int64_t n, i
     // owners whose window reaches an end apply it
     const int64_t j0 = o - hs + (int64_t)lane * B;
     const bool touches = FIX && (o - hs <= 0 || o + M + hs >= n - 1);
-    const typename E::Site eq_l = PL::equilibrium(rho_l, cf), eq_r = PL::equilibrium(rho_r, cf);
-    auto fix = [&](typename E::Site (&y)[B]) {
+    const Site eq_l = PL::equilibrium(rho_l, cf), eq_r = PL::equilibrium(rho_r, cf);
+    auto fix = [&](Site (&y)[B]) {
         if (touches) {
             unroll<B>([&](auto Bi) {
                 const int64_t j = j0 + Bi;
@@ -983,36 +1086,97 @@ __global__ __launch_bounds__(LD) void k_span(char* __restrict__ st, int64_t n, i
         else E::run(x, sc, xch, lane, left, right, true, cf);
         done += sc;
         if (done >= steps) break;
-        // publish own edges
+        if (c >= slots) {   // the host sizes launches to their slots; stop rather than overrun
+            span_raise_abort(ctl, lane);
+            ok = false;
+            break;
+        }
+        // Publish own sites (one store per word).  No memory access of this
+        // wave is outstanding here (the halo loads were consumed by the last
+        // chunk); saying so keeps the compiler from waiting for them between
+        // these stores, which the counter it waits on also counts.
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         unroll<B>([&](auto Bi) {
             const int64_t k = (int64_t)lane * B + Bi;
-            if (k >= hs && k < 2 * hs) PL::store(edge(c, w, 0), epitch, k - hs, x[Bi]);
-            if (k >= M && k < M + hs) PL::store(edge(c, w, 1), epitch, k - M, x[Bi]);
+            if (k >= hs && k < hs + M) site_store_sync<Q, P>(slot(c, w), epitch, k - hs, x[Bi]);
         });
-        ok = handshake((int)(c + 1));
+        // receive the halo: poll the neighbours' slots until every word is
+        // written.  Every slot of the lane loads (slots outside the halo read
+        // a valid word and ignore it), so all loads of a poll are in flight
+        // together: one memory round trip per poll.
+        char* src[B];
+        int64_t idx[B];
+        bool want[B];
+        // the neighbours' stores leave at the same time as ours: a first poll
+        // issued at once mostly reaches memory before them, so wait a little
+        __builtin_amdgcn_s_sleep(kFirstPollDelay);
+        unroll<B>([&](auto Bi) {
+            const int64_t k = (int64_t)lane * B + Bi;
+            const bool lft = k < hs, rgt = k >= hs + M && k < 2 * hs + M;
+            want[Bi] = lft || rgt;
+            src[Bi] = rgt ? slot(c, right_w) : slot(c, left_w);
+            idx[Bi] = lft ? M_left - hs + k : (rgt ? k - hs - M : 0);
+        });
+        for (int spin = 0;; spin++) {
+            Site y[B];
+            bool got[B];
+            unroll<B>([&](auto Bi) { got[Bi] = site_load_sync<Q, P>(src[Bi], epitch, idx[Bi], y[Bi]); });
+            const int ab = __hip_atomic_load(ctl + kCtlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bool ready = true;
+            unroll<B>([&](auto Bi) { ready = ready && (got[Bi] || !want[Bi]); });
+            if (__builtin_amdgcn_ballot_w64(!ready) == 0) {
+                unroll<B>([&](auto Bi) {
+                    if (want[Bi]) x[Bi] = y[Bi];
+                });
+                break;
+            }
+            if (__builtin_amdgcn_readfirstlane(ab) || spin >= kSpinLimit) {
+                span_raise_abort(ctl, lane);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
         if (!ok) break;
-        // refresh the halo slots from the neighbours' edges
-        unroll<B>([&](auto Bi) {
-            const int64_t k = (int64_t)lane * B + Bi;
-            if (k < hs) x[Bi] = PL::load(edge(c, left_w, 1), epitch, k);
-            else if (k >= hs + M && k < 2 * hs + M) x[Bi] = PL::load(edge(c, right_w, 0), epitch, k - hs - M);
-        });
         if constexpr (FIX) fix(x);
     }
     if (!ok) return;
-    // final state: only after both neighbours have finished every chunk
-    const int total = (int)((steps + s - 1) / s);
-    if (!handshake(total)) return;
+    // final state: only after both neighbours have finished the launch
+    span_signal(flags + w, 1, lane);
+    if (!span_wait(flags + left_w, flags + right_w, 1, ctl, lane)) return;
     unroll<B>([&](auto Bi) {
         const int64_t k = (int64_t)lane * B + Bi;
         if (k >= hs && k < hs + M) PL::store(st, p, o + k - hs, x[Bi]);
     });
 }
 
-__global__ void k_zero_ints(int* p, int count)
+// Before each launch (one workgroup): clear the abort word and the flags.
+__global__ void k_span_prep(int* ctl, int nwg)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0;
+    for (int i = threadIdx.x; i < nwg; i += blockDim.x) ctl[kCtlFlags + i] = 0;
+    if (threadIdx.x == 0) ctl[kCtlAbort] = 0;
+}
+
+// Sentinel in every word of sites [0, sites) of `copies` edge copies.
+template <int Q, int P>
+__global__ __launch_bounds__(256) void k_span_fill(char* ebase, int64_t ecopy, int64_t epitch, int64_t copies,
+                                                   int sites)
+{
+    const int64_t total = copies * sites;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int64_t c = i / sites, k = i - c * sites;
+        site_store_sentinel<Q, P>(ebase + c * ecopy, epitch, k);
+    }
+}
+
+__global__ void k_span_set_ctl(int* ctl, int index, int value)
+{
+    if (threadIdx.x == 0) ctl[index] = value;
+}
+
+__global__ void k_span_init_ctl(int* ctl, int count)
+{
+    for (int i = threadIdx.x; i < count; i += blockDim.x) ctl[i] = 0;
 }
 
 // ---------------------------------------------------------------- readout and diagnostics
@@ -1259,54 +1423,57 @@ int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegD
     return (int)hipErrorInvalidValue;
 }
 
-int span_sites_per_lane() { return kSpanB; }
-bool span_lanes_valid(int lanes) { return lanes == 64 || lanes == 128 || lanes == 256; }
-int64_t span_edge_copy_bytes(int q, int prec, int hs) { return (int64_t)state_copy_bytes(state_pitch(hs), q, prec); }
+int span_lanes() { return kSpanLD; }
+int span_sites_per_lane(int q) { return span_b_of(q); }
+int span_ctl_ints(int nwg) { return kCtlFlags + nwg; }
+int64_t span_edge_copy_bytes(int q, int prec, int64_t sites) { return (int64_t)state_copy_bytes(state_pitch(sites), q, prec); }
 
-template <int Q, int P, bool FIX, int LD>
-static void span_one(hipStream_t st, unsigned grid, void* state, int64_t n, int nwg, int64_t steps, int s,
-                     char* ebase, int64_t ecopy, int64_t epitch, int* flags, int* abort, const Coef& cf, double rl,
-                     double rr)
+int launch_span_ctl_init(int* ctl, int count, void* stream)
 {
-    using E = Engine<Q, P, kSpanB, LD>;
-    const size_t lds = LD == 64 ? 0 : sizeof(double) * (2 * E::SLOT + 1);
-    k_span<Q, P, FIX, LD><<<grid, LD, lds, st>>>((char*)state, n, state_pitch(n), nwg, steps, s, ebase, ecopy, epitch,
-                                                 flags, abort, cf, rl, rr);
+    k_span_init_ctl<<<1, 256, 0, (hipStream_t)stream>>>(ctl, count);
+    return (int)hipGetLastError();
 }
 
-template <int Q, int P, bool FIX>
-static void span_lanes_dispatch(int lanes, hipStream_t st, unsigned grid, void* state, int64_t n, int nwg,
-                                int64_t steps, int s, char* ebase, int64_t ecopy, int64_t epitch, int* flags,
-                                int* abort, const Coef& cf, double rl, double rr)
+int launch_span_set_ctl(int* ctl, int index, int value, void* stream)
 {
-    if (lanes == 64) span_one<Q, P, FIX, 64>(st, grid, state, n, nwg, steps, s, ebase, ecopy, epitch, flags, abort, cf, rl, rr);
-    else if (lanes == 128) span_one<Q, P, FIX, 128>(st, grid, state, n, nwg, steps, s, ebase, ecopy, epitch, flags, abort, cf, rl, rr);
-    else span_one<Q, P, FIX, 256>(st, grid, state, n, nwg, steps, s, ebase, ecopy, epitch, flags, abort, cf, rl, rr);
+    k_span_set_ctl<<<1, 64, 0, (hipStream_t)stream>>>(ctl, index, value);
+    return (int)hipGetLastError();
 }
 
-int launch_span(int q, int prec, int lanes, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase,
-                int64_t ecopy, int* flags, int* abort, const Coef& cf, void* stream, const Ends* ends)
+int span_ctl_error_index() { return kCtlSticky; }
+
+int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase, int64_t ecopy,
+                int64_t slots, int* ctl, const Coef& cf, void* stream, const Ends* ends)
 {
     hipStream_t st = (hipStream_t)stream;
     const int h = halo_of(q);
     const int64_t hs = (int64_t)h * s;
-    if (!span_lanes_valid(lanes)) return (int)hipErrorInvalidValue;
-    const int64_t W = (int64_t)lanes * kSpanB;
-    if (nwg < 2 || s < 1 || steps < 1) return (int)hipErrorInvalidValue;
+    const int64_t W = (int64_t)kSpanLD * span_b_of(q);
+    if (nwg < 2 || s < 1 || steps < 1 || slots < 1) return (int)hipErrorInvalidValue;
     // every owner holds at least H s sites and its window fits
     const int64_t mmin = n / nwg, mmax = (n + nwg - 1) / nwg;
     if (mmin < hs || mmax + 2 * hs > W) return (int)hipErrorInvalidValue;
-    k_zero_ints<<<(nwg + 1 + 255) / 256, 256, 0, st>>>(flags, nwg + 1);   // flags then abort word
+    // the exchanges of this launch fit the slots, and a slot holds mmax sites
+    if ((steps + s - 1) / s - 1 > slots) return (int)hipErrorInvalidValue;
+    const int64_t epitch = state_pitch(mmax);
+    if (ecopy < (int64_t)state_copy_bytes(epitch, q, prec)) return (int)hipErrorInvalidValue;
+    const int64_t copies = std::min<int64_t>(slots, (steps + s - 1) / s - 1) * nwg;
+    k_span_prep<<<1, 256, 0, st>>>(ctl, nwg);
+    if (copies > 0) {
+        const unsigned fill_blocks = (unsigned)std::min<int64_t>(4096, (copies * mmax + 255) / 256);
+        KSLB_DISPATCH_QP(q, prec, (k_span_fill<Q_, P_><<<fill_blocks, 256, 0, st>>>(ebase, ecopy, epitch, copies,
+                                                                                   (int)mmax)));
+    }
     const int per = (nwg + 7) / 8;
     const unsigned grid = (unsigned)(per * 8);
-    const int64_t epitch = state_pitch(hs);
     if (ends) {
-        KSLB_DISPATCH_QP(q, prec, (span_lanes_dispatch<Q_, P_, true>(lanes, st, grid, state, n, nwg, steps, s, ebase,
-                                                                     ecopy, epitch, flags, abort, cf, ends->rho_l,
-                                                                     ends->rho_r)));
+        KSLB_DISPATCH_QP(q, prec, (k_span<Q_, P_, true><<<grid, kSpanLD, 0, st>>>(
+                                      (char*)state, n, state_pitch(n), nwg, steps, s, ebase, ecopy, epitch, slots, ctl,
+                                      cf, ends->rho_l, ends->rho_r)));
     } else {
-        KSLB_DISPATCH_QP(q, prec, (span_lanes_dispatch<Q_, P_, false>(lanes, st, grid, state, n, nwg, steps, s, ebase,
-                                                                      ecopy, epitch, flags, abort, cf, 0.0, 0.0)));
+        KSLB_DISPATCH_QP(q, prec, (k_span<Q_, P_, false><<<grid, kSpanLD, 0, st>>>(
+                                      (char*)state, n, state_pitch(n), nwg, steps, s, ebase, ecopy, epitch, slots, ctl,
+                                      cf, 0.0, 0.0)));
     }
     return (int)hipGetLastError();
 }

@@ -90,17 +90,9 @@ class Lattice:
         return {"E": E, "G": G, "omega": om.value, "tau": tau.value, "J": jkm[0], "K": jkm[1],
                 "M": jkm[2], "dM": jkm[3], "C6": jkm[4]}
 
-    def set_kernel(self, kind="auto", steps_per_launch: int = 0, span_lanes: Optional[int] = None) -> "Lattice":
-        """Kernel class and its step parameter; ``span_lanes`` (0, 64, 128, 256)
-        sets the SPAN workgroup width first when given."""
-        if span_lanes is not None:
-            call("kslb_set_span_lanes", self._h, int(span_lanes))
+    def set_kernel(self, kind="auto", steps_per_launch: int = 0) -> "Lattice":
         k = _lib.KERNELS[kind] if isinstance(kind, str) else int(kind)
         call("kslb_set_kernel", self._h, k, steps_per_launch)
-        return self
-
-    def set_span_lanes(self, lanes: int) -> "Lattice":
-        call("kslb_set_span_lanes", self._h, int(lanes))
         return self
 
     def kernel(self) -> dict:

@@ -137,7 +137,7 @@ def test_resident_config_in_bench_launch():
     assert rel(lat.f(), oracle.collide(w.q, coef, tau, f_ref)) < TOL64
 
 
-@pytest.mark.parametrize("spl", [8, 16, 24])
+@pytest.mark.parametrize("spl", [8, 16, 0])
 def test_span_kernel_in_bench_shape(spl):
     # D1Q7, N = 4096, the multi-workgroup kernel with s steps between edge exchanges
     w = CFG_RESIDENT_Q7
@@ -156,19 +156,20 @@ def test_span_kernel_in_bench_shape(spl):
 
 
 @pytest.mark.parametrize("q", [5, 7])
-@pytest.mark.parametrize("lanes", [128, 256])
 @pytest.mark.parametrize("n,spl", [(1000, 0), (4096, 0), (4096, 17), (12345, 0), (70001, 0)])
-def test_span_multiwave_bitwise(q, lanes, n, spl):
-    # SPAN workgroups of 2 or 4 waves (LDS exchange inside, flags between
-    # workgroups): bitwise equal to the one-step kernel, and to the oracle
+def test_span_exchange_slots(q, n, spl):
+    # SPAN owners trade edges through write-once slots polled for a sentinel:
+    # bitwise equal to the one-step kernel and to the oracle, over several
+    # advances that reuse the slots
     dX, dT, tau, steps = 0.2, 1e-4, 1.1, 700
     rho0 = ic(n, dX, 17)
     lat = make(q, n, dX=dX, dT=dT, tau=tau)
-    lat.set_kernel("span", spl, span_lanes=lanes)
+    lat.set_kernel("span", spl)
     k = lat.kernel()
-    say("case span multiwave q=%d n=%d lanes=%d s=%d: %s" % (q, n, lanes, spl, k))
-    assert k["kernel"] == "span" and k["lanes"] == lanes and k["workgroups"] >= 2
+    say("case span slots q=%d n=%d s=%d: %s" % (q, n, spl, k))
+    assert k["kernel"] == "span" and k["lanes"] == 64 and k["workgroups"] >= 2
     assert spl == 0 or k["exchange_steps"] == spl
+    assert k["steps_per_launch"] % k["exchange_steps"] == 0
     lat.init_rho(rho0).advance(steps)
     mass, bad = lat.diagnostics()          # raises if a workgroup timed out
     assert not bad
@@ -176,24 +177,40 @@ def test_span_multiwave_bitwise(q, lanes, n, spl):
     assert np.array_equal(lat.f(), ref.f())
     if n <= 4096:
         assert rel(lat.rho(), oracle_run(q, n, dX, dT, tau, steps, 17)[0]) < TOL64
-    # a second advance on the same lattice reuses the exchange area
-    lat.advance(steps // 3)
-    ref.advance(steps // 3)
+    for extra in (steps // 3, 1, k["exchange_steps"], 2 * k["exchange_steps"] + 1):
+        lat.advance(extra)
+        ref.advance(extra)
+        assert np.array_equal(lat.f(), ref.f()), extra
+    lat.diagnostics()
+
+
+def test_span_advance_longer_than_one_launch():
+    # an advance split over several launches (the exchange slots of one launch
+    # cover steps_per_launch steps) equals the one-step kernel
+    w = CFG_RESIDENT_Q7
+    lat = Lattice(w.n, w.q, "fp64").set_physical(w.dX, w.dT, 0.0).set_kernel("span")
+    per = lat.kernel()["steps_per_launch"]
+    steps = 2 * per + 57
+    say("case span %d steps over launches of %d" % (steps, per))
+    rho0 = w.rho0()
+    lat.init_rho(rho0).advance(steps)
+    lat.diagnostics()
+    ref = Lattice(w.n, w.q, "fp64").set_physical(w.dX, w.dT, 0.0).set_kernel("tiled").init_rho(rho0).advance(steps)
     assert np.array_equal(lat.f(), ref.f())
 
 
 @pytest.mark.parametrize("prec", ["fp32", "split", "rho"])
-def test_span_multiwave_reduced_storage(prec):
+def test_span_reduced_storage_bitwise(prec):
     n, dX, dT = 4096, 0.3, 2e-4
     tau = 1.0
     rho0 = ic(n, dX, 23)
-    say("case span multiwave %s" % prec)
+    say("case span storage %s" % prec)
     outs = []
-    for kernel, lanes in (("plain", None), ("span", 64), ("span", 256)):
-        lat = Lattice(n, 7, prec).set_physical(dX, dT, tau).set_kernel(kernel, 0, span_lanes=lanes)
+    for kernel in ("plain", "span"):
+        lat = Lattice(n, 7, prec).set_physical(dX, dT, tau).set_kernel(kernel)
         lat.init_rho(rho0).advance(900)
         outs.append(lat.f())
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    assert np.array_equal(outs[0], outs[1])
 
 
 def test_resident_config_full_length():
@@ -385,23 +402,15 @@ def test_fixed_ends_table3_parity(q, dX):
     X = np.arange(n) * dX
     lo, hi = table3_ends()
     ref = oracle.solve_tanh_fixed(q, dX, dT, tau, steps)
-    from paper_1711_03540_amd import KslbError
     outs = []
-    for kernel, lanes in (("plain", None), ("span", 64), ("span", 128), ("span", 256)):
-        lat = Lattice(n, q, "fp64").set_physical(dX, dT, tau)
-        try:
-            lat.set_kernel(kernel, 0, span_lanes=lanes)
-        except KslbError:
-            assert lanes == 256      # too wide for a few hundred sites
-            continue
-        lat.set_fixed_ends(lo, hi)
-        say("  kernel %s lanes %s: %s" % (kernel, lanes, lat.kernel()))
+    for kernel, spl in (("plain", 0), ("span", 0), ("span", 7)):
+        lat = Lattice(n, q, "fp64").set_physical(dX, dT, tau).set_kernel(kernel, spl).set_fixed_ends(lo, hi)
+        say("  kernel %s: %s" % (kernel, lat.kernel()))
         lat.init_rho(table3_profile(X, 0.0)).advance(steps)
         rho = lat.rho()
-        assert rel(rho, ref) < TOL64, (kernel, lanes)
+        assert rel(rho, ref) < TOL64, (kernel, spl)
         assert rho[0] == pytest.approx(lo, abs=1e-14) and rho[-1] == pytest.approx(hi, abs=1e-14)
         outs.append(lat.f())
-    assert len(outs) >= 3
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
     G = oracle.global_error(ref, oracle.tanh_solution(X, steps * dT))
@@ -501,8 +510,8 @@ def test_resolved_kernel_and_launch_shape():
     say("case resolved kernel")
     # AUTO: a few thousand sites run on SPAN, larger periodic lattices on TILED
     k = make(7, 4096).kernel()
-    assert k["kernel"] == "span" and k["steps_per_launch"] == 1 << 20
-    assert k["exchange_steps"] >= 1 and k["workgroups"] >= 2
+    assert k["kernel"] == "span" and k["steps_per_launch"] % k["exchange_steps"] == 0
+    assert k["exchange_steps"] >= 1 and k["workgroups"] >= 2 and k["lanes"] == 64
     n = 100_000
     for prec, sites in (("fp64", 8), ("rho", 16)):
         lat = Lattice(n, 7, prec).set_physical(0.3, 2e-4, 1.0)

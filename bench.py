@@ -58,6 +58,7 @@ WORKLOADS = {
     "serve": (None, None),
     "table3": (None, None),
     "stats": (None, None),
+    "taumin": (None, None),
 }
 
 
@@ -279,6 +280,100 @@ def bench_table3(args):
     print(json.dumps({"workload": "table3_fixed_ends", "T_end": T_end, "runs": runs, "matched": matched}), flush=True)
 
 
+def bench_taumin(args):
+    """Minimum stable tau on the Table 3 problem (the left panels of the
+    paper's Figs. 1-3, section 3): for dX in {0.2, 0.1, 0.05}, both schemes and
+    a sweep of dT, the smallest tau (to 0.005, by bisection) for which the
+    fixed-end run to T = 0.5 stays bounded (finite and |rho| < 100; the solution
+    lies in [0.6, 5.4]), with the library's stability guard off.  Reported
+    beside the paper's fit, Eq. (general_tau_formula), and beside the lowest
+    tau of the band the library's linear guard (rho_max = 4.5) accepts around
+    the fit (None: no accepted tau up to 8)."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03540_amd import inputs
+    from paper_1711_03540_amd.lattice import Lattice, scheme_coefficients, stability_check, tau_fit
+
+    dev = torch.device("cuda:0")
+    T_end = 0.5
+    lo_end, hi_end = inputs.table3_ends()
+    tau_floor, tol = 0.92, 0.005
+    out = []
+
+    for dX in (0.2, 0.1, 0.05):
+        n = inputs.table3_sites(dX)
+        X = np.arange(n) * dX
+        rho0 = torch.tensor(inputs.table3_profile(X, 0.0), device=dev)
+        for q in (5, 7):
+            for dT in (1e-6, 2e-6, 5e-6, 1e-5, 2e-5, 5e-5, 1e-4, 2e-4, 5e-4, 1e-3):
+                steps = int(round(T_end / dT))
+                if steps > 600_000 or steps < 50:
+                    continue
+                runs = [0]
+
+                def stable(tau):
+                    runs[0] += 1
+                    lat = Lattice(n, q, "fp64", device=dev).set_physical(dX, dT, tau, guard="off")
+                    lat.set_fixed_ends(lo_end, hi_end).init_rho(rho0).advance(steps)
+                    rho = lat.rho()
+                    lat.close()
+                    return bool(np.all(np.isfinite(rho)) and np.max(np.abs(rho)) < 100.0)
+
+                def guard_ok(tau):
+                    _, E, G = scheme_coefficients(q, dX, dT, tau)
+                    return stability_check(q, E, G, 1.0 / tau, dX, dT, 4.5)
+
+                t0 = time.perf_counter()
+                if stable(tau_floor):
+                    tmin = None          # stable at the lowest tau the library accepts
+                else:
+                    lo, hi = tau_floor, max(1.0, tau_fit(q, dX, dT))
+                    while not stable(hi) and hi < 12.0:
+                        lo, hi = hi, hi + 0.5
+                    if hi >= 12.0:
+                        out.append({"dX": dX, "q": q, "dT": dT, "steps": steps, "error": "unstable up to tau = 12"})
+                        continue
+                    while hi - lo > tol:
+                        mid = 0.5 * (lo + hi)
+                        if stable(mid):
+                            hi = mid
+                        else:
+                            lo = mid
+                    tmin = hi
+                # the guard's accepted taus need not extend upwards without
+                # bound (at dX = 0.2 they end near 2), so search from the fit
+                # in steps of 0.02 for the lowest accepted tau of that band,
+                # then bisect the last step
+                k_lo, k_hi = 46, 400                # tau = 0.02 k: 0.92 .. 8
+                k = min(k_hi, max(k_lo, int(round(tau_fit(q, dX, dT) / 0.02))))
+                gmin = None
+                if guard_ok(0.02 * k):
+                    while k > k_lo and guard_ok(0.02 * (k - 1)):
+                        k -= 1
+                else:
+                    while k < k_hi and not guard_ok(0.02 * k):
+                        k += 1
+                    if not guard_ok(0.02 * k):
+                        k = None
+                if k is not None and k == k_lo:
+                    gmin = tau_floor                # accepted down to the floor
+                elif k is not None:
+                    glo, ghi = 0.02 * (k - 1), 0.02 * k
+                    while ghi - glo > tol:
+                        mid = 0.5 * (glo + ghi)
+                        if guard_ok(mid):
+                            ghi = mid
+                        else:
+                            glo = mid
+                    gmin = ghi
+                out.append({"dX": dX, "q": q, "dT": dT, "steps": steps, "tau_min": tmin, "tau_fit": tau_fit(q, dX, dT),
+                            "tau_guard": gmin, "runs": runs[0], "seconds": time.perf_counter() - t0})
+                print(json.dumps(out[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "taumin_table3", "T_end": T_end, "tau_floor": tau_floor, "tol": tol, "scan": out}),
+          flush=True)
+
+
 def bench_stats(args):
     """Reduced-precision error on long-time statistics: the D1Q7 N = 4096 lattice
     (L = 256 pi, dT = 1e-4, fitted tau, 16 random modes) run to T = 1000 in FP64,
@@ -365,6 +460,9 @@ def main():
         return
     if args.workload == "stats":
         bench_stats(args)
+        return
+    if args.workload == "taumin":
+        bench_taumin(args)
         return
     import numpy as np
     import torch

@@ -584,7 +584,10 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
         const int64_t ecopy = span_copy_bytes(L, nwg);
         int* ctl = reinterpret_cast<int*>(L->span_scratch);
         char* ebase = L->span_scratch + kSpanCtlBytes;
-        const int64_t chunk = std::min<int64_t>(kMaxStepsPerLaunch, (slots + 1) * sp);
+        // launches of equal length (to a multiple of sp), each within the slots
+        const int64_t cap = std::min<int64_t>(kMaxStepsPerLaunch, (slots + 1) * sp);
+        const int64_t nl = (n_steps + cap - 1) / cap;
+        const int64_t chunk = std::min(cap, ((n_steps + nl - 1) / nl + sp - 1) / sp * sp);
         for (int64_t done = 0; done < n_steps; done += chunk) {
             const int64_t s = std::min(chunk, n_steps - done);
             e = launch_span(L->q, L->prec, L->state(), L->n, nwg, s, sp, ebase, ecopy, slots, ctl, L->ph.cf,

@@ -170,7 +170,9 @@ double spectral_radius(int q, const double* E, const double* G, double omega, do
             z[i] -= dz;
             change = std::fmax(change, std::abs(dz));
         }
-        if (change < 1e-17) break;
+        // roots are O(1): a step below 1e-15 is within a few ulp (quadratic
+        // convergence reaches it from about 1e-8 in one iteration)
+        if (change < 1e-15) break;
     }
     double r = 0.0;
     for (int i = 0; i < q; i++) r = std::fmax(r, std::abs(z[i]));

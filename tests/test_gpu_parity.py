@@ -534,3 +534,31 @@ def test_resolved_kernel_and_launch_shape():
     lat = make(7, 70001)
     lat.set_fixed_ends(1.0, 2.0)
     assert lat.kernel()["kernel"] == "plain"
+
+
+def test_blowup_threshold_matches_oracle():
+    # the minimum stable tau of one Table 3 case (section 3's scan), found by
+    # bisection on the GPU, also separates bounded from unbounded oracle runs
+    from paper_1711_03540_amd.inputs import table3_ends, table3_profile, table3_sites
+    q, dX, dT, steps = 5, 0.2, 1e-3, 500
+    n = table3_sites(dX)
+    X = np.arange(n) * dX
+    lo_end, hi_end = table3_ends()
+    say("case blow-up threshold q=%d dX=%g dT=%g" % (q, dX, dT))
+
+    def bounded(rho):
+        return bool(np.all(np.isfinite(rho)) and np.max(np.abs(rho)) < 100.0)
+
+    def gpu_stable(tau):
+        lat = Lattice(n, q, "fp64").set_physical(dX, dT, tau, guard="off").set_fixed_ends(lo_end, hi_end)
+        return bounded(lat.init_rho(table3_profile(X, 0.0)).advance(steps).rho())
+
+    lo, hi = 0.92, 3.0
+    assert not gpu_stable(lo) and gpu_stable(hi)
+    while hi - lo > 0.01:
+        mid = 0.5 * (lo + hi)
+        lo, hi = (lo, mid) if gpu_stable(mid) else (mid, hi)
+    say("  GPU threshold in (%.4f, %.4f]" % (lo, hi))
+    with np.errstate(all="ignore"):
+        assert bounded(oracle.solve_tanh_fixed(q, dX, dT, hi + 0.01, steps))
+        assert not bounded(oracle.solve_tanh_fixed(q, dX, dT, lo - 0.01, steps))

@@ -280,6 +280,20 @@ kslb_status kslb_ensemble_advance(kslb_ensemble* ens, const int64_t* steps);
 
 kslb_status kslb_ensemble_read_rho(kslb_ensemble* ens, int idx, double* out, int on_device);
 
+/* Benettin renormalisation of trajectory pairs, a tool for the largest
+ * Lyapunov exponent of the scheme's dynamics (the chaotic dynamics the paper
+ * names as its next subject, section 4).  For each pair p of instances of an
+ * FP64 ensemble (ref[p], pert[p]: host arrays of instance indices; equal
+ * sites and steps; no instance perturbed twice or both reference and
+ * perturbed): with d = || S_pert - S_ref ||_2 over all Q x n stored
+ * (post-collision) populations, set S_pert <- S_ref + (S_pert - S_ref) delta / d
+ * and add ln(d / delta) to log_accum[p] (device array of npairs doubles, owned
+ * by the caller, which zeroes it first).  A zero or non-finite d leaves the
+ * pair unchanged and stores NaN in log_accum[p].  Enqueued on the ensemble's
+ * stream.  EINVAL for other precisions or bad pairs.                        */
+kslb_status kslb_ensemble_renormalize(kslb_ensemble* ens, int npairs, const int* ref, const int* pert,
+                                      double delta, double* log_accum);
+
 /* Step counter and non-finite flag of instance idx (synchronises). */
 kslb_status kslb_ensemble_status(kslb_ensemble* ens, int idx, int64_t* step, int* nonfinite);
 

@@ -75,6 +75,7 @@ SIGNATURES = {
     "kslb_ensemble_advance": (_st, [_vp, _vp]),
     "kslb_ensemble_read_rho": (_st, [_vp, _i, _vp, _i]),
     "kslb_ensemble_status": (_st, [_vp, _i, _vp, _vp]),
+    "kslb_ensemble_renormalize": (_st, [_vp, _i, _vp, _vp, _d, _vp]),
     "kslb_ensemble_destroy": (_st, [_vp]),
     "kslb_last_error": (ctypes.c_char_p, []),
 }

@@ -810,6 +810,12 @@ struct kslb_ensemble {
     uint64_t gkey[5] = {0, 0, 0, 0, 0};
     double* staging = nullptr;
     int64_t staging_n = 0;
+    // trajectory pairs: device table and its pinned staging
+    char* d_pairs = nullptr;
+    char* h_pairs = nullptr;
+    size_t pairs_cap = 0;
+    hipEvent_t pairs_ev = nullptr;
+    bool pairs_pending = false;
 };
 
 namespace {
@@ -1290,6 +1296,67 @@ kslb_status kslb_ensemble_status(kslb_ensemble* E, int idx, int64_t* step, int* 
     return KSLB_OK;
 }
 
+kslb_status kslb_ensemble_renormalize(kslb_ensemble* E, int npairs, const int* ref, const int* pert, double delta,
+                                      double* log_accum)
+{
+    if (!E) return fail(KSLB_EINVAL, "null ensemble");
+    if (npairs < 0 || (npairs > 0 && (!ref || !pert || !log_accum)))
+        return fail(KSLB_EINVAL, "bad pair arguments");
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(KSLB_EINVAL, "delta must be positive and finite");
+    if (E->prec != kFP64) return fail(KSLB_EINVAL, "trajectory pairs need FP64 storage");
+    if (npairs == 0) return KSLB_OK;
+    std::vector<PairDesc> pd((size_t)npairs);
+    for (int p = 0; p < npairs; p++) {
+        const int a = ref[p], b = pert[p];
+        if (a < 0 || a >= E->count || b < 0 || b >= E->count || a == b)
+            return fail(KSLB_EINVAL, "pair %d: bad instances (%d, %d)", p, a, b);
+        if (!E->have_state[a] || !E->have_state[b]) return fail(KSLB_ESTATE, "pair %d: instance without state", p);
+        if (E->n[a] != E->n[b] || E->step[a] != E->step[b])
+            return fail(KSLB_EINVAL, "pair %d: instances differ in sites or steps", p);
+        pd[p] = PairDesc{(int64_t)(E->off[a] + (size_t)E->cur[a] * E->copy[a]),
+                         (int64_t)(E->off[b] + (size_t)E->cur[b] * E->copy[b]), E->n[a], state_pitch(E->n[a]), p, 0};
+    }
+    for (int p = 0; p < npairs; p++)
+        for (int r = p + 1; r < npairs; r++)
+            if (pert[p] == pert[r] || pert[p] == ref[r] || ref[p] == pert[r])
+                return fail(KSLB_EINVAL, "pairs %d and %d share a perturbed instance", p, r);
+    DeviceGuard g(E->device);
+    const size_t bytes = sizeof(PairDesc) * (size_t)npairs;
+    int e = 0;
+    if (E->pairs_pending) {   // the staging may still feed the previous upload
+        e = hipEventSynchronize(E->pairs_ev);
+        if (e) return hip_fail(e, "pair table event");
+        E->pairs_pending = false;
+    }
+    if (E->pairs_cap < bytes) {
+        if (E->d_pairs) (void)hipFree(E->d_pairs);
+        if (E->h_pairs) (void)hipHostFree(E->h_pairs);
+        E->d_pairs = E->h_pairs = nullptr;
+        E->pairs_cap = 0;
+        void* dp = nullptr;
+        void* hp = nullptr;
+        if (hipMalloc(&dp, bytes)) return fail(KSLB_ENOMEM, "pair table of %zu bytes", bytes);
+        if (hipHostMalloc(&hp, bytes, hipHostMallocDefault)) {
+            (void)hipFree(dp);
+            return fail(KSLB_ENOMEM, "pinned pair table of %zu bytes", bytes);
+        }
+        E->d_pairs = (char*)dp;
+        E->h_pairs = (char*)hp;
+        E->pairs_cap = bytes;
+    }
+    if (!E->pairs_ev && hipEventCreateWithFlags(&E->pairs_ev, hipEventDisableTiming))
+        return fail(KSLB_EDEVICE, "event creation failed");
+    std::memcpy(E->h_pairs, pd.data(), bytes);
+    e = hipMemcpyAsync(E->d_pairs, E->h_pairs, bytes, hipMemcpyHostToDevice, E->stream);
+    if (!e) e = hipEventRecord(E->pairs_ev, E->stream);
+    if (e) return hip_fail(e, "pair table upload");
+    E->pairs_pending = true;
+    e = launch_pair_renorm(E->q, E->buf, reinterpret_cast<const PairDesc*>(E->d_pairs), npairs, delta, log_accum,
+                           E->stream);
+    if (e) return hip_fail(e, "pair renormalisation kernel");
+    return KSLB_OK;
+}
+
 kslb_status kslb_ensemble_destroy(kslb_ensemble* E)
 {
     if (!E) return KSLB_OK;
@@ -1303,6 +1370,9 @@ kslb_status kslb_ensemble_destroy(kslb_ensemble* E)
         if (E->up_ev[k]) (void)hipEventDestroy(E->up_ev[k]);
     }
     if (E->staging) (void)hipFree(E->staging);
+    if (E->d_pairs) (void)hipFree(E->d_pairs);
+    if (E->h_pairs) (void)hipHostFree(E->h_pairs);
+    if (E->pairs_ev) (void)hipEventDestroy(E->pairs_ev);
     delete E;
     return KSLB_OK;
 }

@@ -72,6 +72,14 @@ int span_ctl_error_index();   // sticky: a launch timed out since the state was 
 int64_t span_edge_copy_bytes(int q, int prec, int64_t sites);
 int launch_span_ctl_init(int* ctl, int count, void* stream);
 int launch_span_set_ctl(int* ctl, int index, int value, void* stream);
+// Trajectory pair of an FP64 ensemble: byte offsets of the two current state
+// copies from the ensemble base, sites, row pitch and the accumulator slot.
+struct PairDesc {
+    int64_t ref_off, pert_off, n, pitch;
+    int32_t slot, pad;
+};
+int launch_pair_renorm(int q, char* base, const PairDesc* desc, int npairs, double delta, double* log_accum,
+                       void* stream);
 // fixed-end boundary values (NULL / absent = periodic)
 struct Ends {
     double rho_l, rho_r;

@@ -1179,6 +1179,63 @@ __global__ void k_span_init_ctl(int* ctl, int count)
     for (int i = threadIdx.x; i < count; i += blockDim.x) ctl[i] = 0;
 }
 
+// ---------------------------------------------------------------- trajectory pairs
+
+// Benettin renormalisation of FP64 trajectory pairs (one workgroup per pair):
+// d = || S_pert - S_ref ||_2 over the Q x n post-collision populations, summed
+// in a fixed order (strided per thread, then a tree over the workgroup);
+// S_pert <- S_ref + (S_pert - S_ref) delta / d; log_accum[slot] += ln(d / delta).
+// A zero or non-finite d leaves the pair unchanged and stores NaN.
+constexpr int kPairLD = 1024;
+
+template <int Q>
+__global__ __launch_bounds__(kPairLD) void k_pair_renorm(char* __restrict__ base, const PairDesc* __restrict__ pd,
+                                                        double delta, double* __restrict__ log_accum)
+{
+    __shared__ double red[kPairLD];
+    __shared__ double scale_sh;
+    const PairDesc d = pd[blockIdx.x];
+    const double* r = reinterpret_cast<const double*>(base + d.ref_off);
+    double* x = reinterpret_cast<double*>(base + d.pert_off);
+    const int t = threadIdx.x;
+    const int64_t total = (int64_t)Q * d.n;
+    double ss = 0.0;
+    for (int64_t e = t; e < total; e += kPairLD) {
+        const int64_t i = e / d.n, j = e - i * d.n;
+        const double diff = x[i * d.pitch + j] - r[i * d.pitch + j];
+        ss = __builtin_fma(diff, diff, ss);
+    }
+    red[t] = ss;
+    __syncthreads();
+    for (int h = kPairLD / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double dist = sqrt(red[0]);
+        const bool ok = dist > 0.0 && __builtin_isfinite(dist);
+        scale_sh = ok ? delta / dist : 0.0;
+        log_accum[d.slot] = ok ? log_accum[d.slot] + log(dist / delta) : __builtin_nan("");
+    }
+    __syncthreads();
+    const double sc = scale_sh;
+    if (sc == 0.0) return;
+    for (int64_t e = t; e < total; e += kPairLD) {
+        const int64_t i = e / d.n, j = e - i * d.n;
+        const double ref = r[i * d.pitch + j];
+        x[i * d.pitch + j] = __builtin_fma(x[i * d.pitch + j] - ref, sc, ref);
+    }
+}
+
+int launch_pair_renorm(int q, char* base, const PairDesc* desc, int npairs, double delta, double* log_accum,
+                       void* stream)
+{
+    if (npairs <= 0) return 0;
+    if (q == 5) k_pair_renorm<5><<<npairs, kPairLD, 0, (hipStream_t)stream>>>(base, desc, delta, log_accum);
+    else k_pair_renorm<7><<<npairs, kPairLD, 0, (hipStream_t)stream>>>(base, desc, delta, log_accum);
+    return (int)hipGetLastError();
+}
+
 // ---------------------------------------------------------------- readout and diagnostics
 
 template <int Q, int P>

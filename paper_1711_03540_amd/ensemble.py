@@ -98,6 +98,17 @@ class Ensemble:
         call("kslb_ensemble_status", self._h, int(idx), ctypes.byref(s), ctypes.byref(f))
         return s.value, bool(f.value)
 
+    def renormalize(self, ref, pert, delta: float, log_accum):
+        """Benettin step on trajectory pairs (ref[p], pert[p]); adds ln(d / delta)
+        to log_accum[p], a float64 device tensor of len(ref) entries."""
+        import numpy as np
+        r = np.ascontiguousarray(np.asarray(ref, dtype=np.int32))
+        p = np.ascontiguousarray(np.asarray(pert, dtype=np.int32))
+        assert r.size == p.size and log_accum.numel() >= r.size and log_accum.is_cuda
+        call("kslb_ensemble_renormalize", self._h, int(r.size), r.ctypes.data_as(ctypes.c_void_p),
+             p.ctypes.data_as(ctypes.c_void_p), float(delta), ctypes.c_void_p(log_accum.data_ptr()))
+        return self
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             fn("kslb_ensemble_destroy")(self._h)

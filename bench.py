@@ -59,6 +59,7 @@ WORKLOADS = {
     "table3": (None, None),
     "stats": (None, None),
     "taumin": (None, None),
+    "lyapunov": (None, None),
 }
 
 
@@ -374,6 +375,80 @@ def bench_taumin(args):
           flush=True)
 
 
+def bench_lyapunov(args):
+    """Largest Lyapunov exponent of the scheme's KS dynamics against the
+    domain length L (the chaotic dynamics the paper names as its next subject,
+    section 4).  D1Q7 FP64, dX = pi/16, dT = 1e-4, fitted tau; N in {112, 184,
+    256, 512, 1024, 2048, 4096} (L = N dX, about 22 to 804); per L four pairs
+    (reference and perturbed trajectory, 16 random modes of amplitude 0.1 with
+    seeds 100 + 10 L-index + pair, perturbation 1e-8 times another seeded
+    field), all in one ensemble.  Benettin renormalisation every unit of time
+    to delta = 1e-8 on the GPU; lambda = sum of ln(d / delta) over T in
+    [T0, T] / (T - T0), T0 = 200, T = --stats-t (1000).  Also the time-averaged
+    energy spectrum of the references (one sample per unit time, T >= T0): its
+    peak wavenumber and <rho^2>."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03540_amd.ensemble import Ensemble
+    from paper_1711_03540_amd.inputs import random_modes_ic
+
+    dev = torch.device("cuda:0")
+    sizes_L = [112, 184, 256, 512, 1024, 2048, 4096]
+    npair = 4
+    dX, dT = math.pi / 16, 1e-4
+    per = int(round(1.0 / dT))
+    T0, T = 200, args.stats_t
+    delta = 1e-8
+    sizes, ref, pert, meta = [], [], [], []
+    for li, n in enumerate(sizes_L):
+        for p in range(npair):
+            ref.append(len(sizes)); sizes.append(n)
+            pert.append(len(sizes)); sizes.append(n)
+            meta.append((li, n, p))
+    ens = Ensemble(sizes, 7, "fp64", device=dev).set_physical(dX, dT, 0.0)
+    for k, (li, n, p) in enumerate(meta):
+        rho0 = random_modes_ic(n, n * dX, seed=100 + 10 * li + p)
+        ens.init_rho(ref[k], rho0)
+        ens.init_rho(pert[k], rho0 + 1e-8 * random_modes_ic(n, n * dX, seed=5000 + 10 * li + p, amplitude=1.0))
+    acc = torch.zeros(len(meta), dtype=torch.float64, device=dev)
+    spec = {n: torch.zeros(n // 2 + 1, dtype=torch.float64, device=dev) for n in sizes_L}
+    rho2 = {n: 0.0 for n in sizes_L}
+    buf = {n: torch.empty(n, dtype=torch.float64, device=dev) for n in sizes_L}
+    samples = 0
+    acc_T0 = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(1, T + 1):
+        ens.advance(per)
+        ens.renormalize(ref, pert, delta, acc)
+        if t == T0:
+            acc_T0 = acc.clone()
+        if t > T0:
+            for k, (li, n, p) in enumerate(meta):
+                if p == 0:
+                    r = ens.read_rho(ref[k], buf[n])
+                    spec[n] += torch.abs(torch.fft.rfft(r) / n) ** 2
+            samples += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lam = ((acc - acc_T0) / (T - T0)).cpu().numpy()
+    out = []
+    for li, n in enumerate(sizes_L):
+        v = np.array([lam[k] for k, m in enumerate(meta) if m[0] == li])
+        E = (spec[n] / samples).cpu().numpy()
+        kap = 2 * np.pi * np.arange(E.size) / (n * dX)
+        peak = int(np.argmax(E[1:]) + 1)
+        out.append({"N": n, "L": n * dX, "lambda_pairs": v.tolist(), "lambda_mean": float(v.mean()),
+                    "lambda_se": float(v.std(ddof=1) / np.sqrt(v.size)), "spectrum_peak_kappa": float(kap[peak]),
+                    "rho2_ref0": float(2 * E[1:].sum() - (E[-1] if n % 2 == 0 else 0.0))})
+        print(json.dumps(out[-1]), file=sys.stderr, flush=True)
+    site_updates = float(sum(sizes)) * per * T
+    print(json.dumps({"workload": "lyapunov_d1q7", "dX": dX, "dT": dT, "tau": ens.tau, "T0": T0, "T": T,
+                      "delta": delta, "pairs_per_L": npair, "results": out, "wall_s": wall,
+                      "glups_including_readouts": site_updates / wall / 1e9}), flush=True)
+
+
 def bench_stats(args):
     """Reduced-precision error on long-time statistics: the D1Q7 N = 4096 lattice
     (L = 256 pi, dT = 1e-4, fitted tau, 16 random modes) run to T = 1000 in FP64,
@@ -463,6 +538,9 @@ def main():
         return
     if args.workload == "taumin":
         bench_taumin(args)
+        return
+    if args.workload == "lyapunov":
+        bench_lyapunov(args)
         return
     import numpy as np
     import torch

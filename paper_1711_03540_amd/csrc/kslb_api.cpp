@@ -265,10 +265,12 @@ KernelChoice resolve_kernel(const kslb_lattice* L)
 
 }  // namespace
 
-// Bytes of one SPAN edge copy: ceil(n / nwg) sites in state format.
+// Bytes of one SPAN edge copy: one window (lanes x sites per lane) in state
+// format (own sites sit at their [site within lane][lane] positions).
 int64_t span_copy_bytes(const kslb_lattice* L, int nwg)
 {
-    return span_edge_copy_bytes(L->q, L->prec, (L->n + nwg - 1) / nwg);
+    (void)nwg;
+    return span_edge_copy_bytes(L->q, L->prec, (int64_t)span_lanes() * span_sites_per_lane(L->q));
 }
 
 // Edge slots one SPAN launch can use, and the steps such a launch covers.

@@ -61,8 +61,8 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
                 const Coef& cf, void* stream);
 // One small lattice over nwg single-wave workgroups exchanging edges every s
 // steps through `slots` edge slots per launch (slots * nwg copies of ecopy
-// bytes from ebase, each holding ceil(n / nwg) sites in state format; see
-// span_edge_copy_bytes).  ctl holds span_ctl_ints(nwg) ints (abort, sticky
+// bytes from ebase, each one window of span_lanes() x span_sites_per_lane(q)
+// positions in state format; see span_edge_copy_bytes).  ctl holds span_ctl_ints(nwg) ints (abort, sticky
 // error, then the handshake flags), set up by launch_span_ctl_init.  The
 // state is advanced in place.
 int span_lanes();

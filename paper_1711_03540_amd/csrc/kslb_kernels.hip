@@ -1055,6 +1055,10 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
     const int left = lane == 0 ? kSpanLD - 1 : lane - 1;
     const int right = lane + 1 == kSpanLD ? 0 : lane + 1;
     auto slot = [&](int64_t chunk, int who) { return ebase + (chunk * nwg + who) * ecopy; };
+    // slot layout [site within lane][lane]: window slot k = lane B + b of the
+    // writer sits at b * 64 + lane, so every store and poll instruction covers
+    // consecutive words
+    auto pos = [](int64_t k) { return (k % B) * kSpanLD + k / B; };
     const int64_t M_left = n * (left_w + 1) / nwg - n * left_w / nwg;   // own sites of the left neighbour
 
     Site x[B];
@@ -1098,7 +1102,7 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         unroll<B>([&](auto Bi) {
             const int64_t k = (int64_t)lane * B + Bi;
-            if (k >= hs && k < hs + M) site_store_sync<Q, P>(slot(c, w), epitch, k - hs, x[Bi]);
+            if (k >= hs && k < hs + M) site_store_sync<Q, P>(slot(c, w), epitch, pos(k), x[Bi]);
         });
         // receive the halo: poll the neighbours' slots until every word is
         // written.  Every slot of the lane loads (slots outside the halo read
@@ -1115,7 +1119,9 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
             const bool lft = k < hs, rgt = k >= hs + M && k < 2 * hs + M;
             want[Bi] = lft || rgt;
             src[Bi] = rgt ? slot(c, right_w) : slot(c, left_w);
-            idx[Bi] = lft ? M_left - hs + k : (rgt ? k - hs - M : 0);
+            // the writer's window slot of this halo site: M_left + k (left
+            // neighbour), k - M (right neighbour)
+            idx[Bi] = lft ? pos(M_left + k) : (rgt ? pos(k - M) : 0);
         });
         for (int spin = 0;; spin++) {
             Site y[B];
@@ -1157,15 +1163,17 @@ __global__ void k_span_prep(int* ctl, int nwg)
     if (threadIdx.x == 0) ctl[kCtlAbort] = 0;
 }
 
-// Sentinel in every word of sites [0, sites) of `copies` edge copies.
+// Sentinel in the words of `copies` edge copies that hold own sites: window
+// slots [hs, hs + sites) at their [site within lane][lane] positions.
 template <int Q, int P>
 __global__ __launch_bounds__(256) void k_span_fill(char* ebase, int64_t ecopy, int64_t epitch, int64_t copies,
-                                                   int sites)
+                                                   int hs, int sites)
 {
+    constexpr int B = span_b_of(Q);
     const int64_t total = copies * sites;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-        const int64_t c = i / sites, k = i - c * sites;
-        site_store_sentinel<Q, P>(ebase + c * ecopy, epitch, k);
+        const int64_t c = i / sites, k = hs + (i - c * sites);
+        site_store_sentinel<Q, P>(ebase + c * ecopy, epitch, (k % B) * kSpanLD + k / B);
     }
 }
 
@@ -1512,14 +1520,14 @@ int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps,
     if (mmin < hs || mmax + 2 * hs > W) return (int)hipErrorInvalidValue;
     // the exchanges of this launch fit the slots, and a slot holds mmax sites
     if ((steps + s - 1) / s - 1 > slots) return (int)hipErrorInvalidValue;
-    const int64_t epitch = state_pitch(mmax);
+    const int64_t epitch = state_pitch(W);   // a slot row holds every window position
     if (ecopy < (int64_t)state_copy_bytes(epitch, q, prec)) return (int)hipErrorInvalidValue;
     const int64_t copies = std::min<int64_t>(slots, (steps + s - 1) / s - 1) * nwg;
     k_span_prep<<<1, 256, 0, st>>>(ctl, nwg);
     if (copies > 0) {
         const unsigned fill_blocks = (unsigned)std::min<int64_t>(4096, (copies * mmax + 255) / 256);
         KSLB_DISPATCH_QP(q, prec, (k_span_fill<Q_, P_><<<fill_blocks, 256, 0, st>>>(ebase, ecopy, epitch, copies,
-                                                                                   (int)mmax)));
+                                                                                   (int)hs, (int)mmax)));
     }
     const int per = (nwg + 7) / 8;
     const unsigned grid = (unsigned)(per * 8);

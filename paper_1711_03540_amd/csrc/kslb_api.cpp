@@ -185,27 +185,29 @@ constexpr int kTileB = 8;
 constexpr int kSpanMaxOwners = 2048;
 int tile_sites_per_lane(int prec) { return prec == kRHO ? 16 : kTileB; }
 // Multi-workgroup plan: nwg single-wave owners of about n / nwg sites each,
-// every window (own sites + 2 H s halo) within span_lanes() x
-// span_sites_per_lane(q) slots, every owner at least H s sites.  Returns nwg,
+// every window (own sites + 2 H s halo, a halo possibly spanning several
+// owners) within span_lanes() x span_sites_per_lane(q) slots.  Returns nwg,
 // or 0 when the shape cannot use it.
 int span_plan(int64_t n, int q, int s)
 {
     const int64_t W = (int64_t)span_lanes() * span_sites_per_lane(q);
     const int64_t hs = (int64_t)halo(q) * s;
     const int64_t own = W - 2 * hs;
-    if (s < 1 || own < hs) return 0;
+    if (s < 1 || own < 1) return 0;
     const int64_t nwg = (n + own - 1) / own;
     if (nwg < 2 || nwg > kSpanMaxOwners) return 0;
-    if (n / nwg < hs) return 0;
     return (int)nwg;
 }
 
-// Default steps between edge exchanges: the largest s whose owners still hold
-// H s sites (W >= 3 H s), or less when the lattice is too small for that.
+// Default steps between edge exchanges: the largest s that plans with each
+// owner's own sites at least 2/3 of the halo depth (3 W >= 8 H s).  Longer
+// intervals mean more, thinner owners whose halos gather from many slots;
+// measured on D1Q7 N = 4096: s = 21, 24, 28, 31 (63, 86, 171, 683 owners) ran
+// 26.7, 25.1, 26.1, 57 ms per 10^5 steps.
 int span_default_steps(int64_t n, int q)
 {
     const int64_t W = (int64_t)span_lanes() * span_sites_per_lane(q);
-    for (int s = (int)(W / (3 * halo(q))); s >= 1; s--)
+    for (int s = (int)((3 * W) / (8 * halo(q))); s >= 1; s--)
         if (span_plan(n, q, s)) return s;
     return 0;
 }
@@ -213,7 +215,7 @@ int span_default_steps(int64_t n, int q)
 // Device scratch of the SPAN kernel: a control block sized for the most
 // owners, then the edge slots of one launch, at most kSpanSlotBytes of them
 // (a longer advance is split into launches of (slots + 1) s steps).
-constexpr size_t kSpanCtlBytes = (size_t)(kSpanMaxOwners + 64) * sizeof(int);
+constexpr size_t kSpanCtlBytes = 256;
 constexpr size_t kSpanSlotBytes = size_t(256) << 20;
 
 // AUTO: one lattice small enough for a few hundred single-wave owners runs
@@ -265,18 +267,16 @@ KernelChoice resolve_kernel(const kslb_lattice* L)
 
 }  // namespace
 
-// Bytes of one SPAN edge copy: one window (lanes x sites per lane) in state
-// format (own sites sit at their [site within lane][lane] positions).
-int64_t span_copy_bytes(const kslb_lattice* L, int nwg)
+// Bytes of one SPAN edge copy (one owner's own sites in state format).
+int64_t span_copy_bytes(const kslb_lattice* L, int nwg, int s)
 {
-    (void)nwg;
-    return span_edge_copy_bytes(L->q, L->prec, (int64_t)span_lanes() * span_sites_per_lane(L->q));
+    return span_edge_copy_bytes(L->q, L->prec, L->n, nwg, s);
 }
 
 // Edge slots one SPAN launch can use, and the steps such a launch covers.
 int64_t span_slot_capacity(const kslb_lattice* L, int nwg, int s)
 {
-    const int64_t per = (int64_t)nwg * span_copy_bytes(L, nwg);
+    const int64_t per = (int64_t)nwg * span_copy_bytes(L, nwg, s);
     return std::max<int64_t>(1, std::min<int64_t>((int64_t)kSpanSlotBytes / per, kMaxStepsPerLaunch / s));
 }
 
@@ -290,7 +290,7 @@ int64_t span_steps_per_launch(const kslb_lattice* L, int nwg, int s)
 // this geometry.  Each launch refills the slots it uses with the sentinel.
 kslb_status span_prepare(kslb_lattice* L, int nwg, int s, int64_t n_steps, int64_t* slots_out)
 {
-    const int64_t per = (int64_t)nwg * span_copy_bytes(L, nwg);
+    const int64_t per = (int64_t)nwg * span_copy_bytes(L, nwg, s);
     const int64_t exchanges = (std::min(n_steps, span_steps_per_launch(L, nwg, s)) + s - 1) / s - 1;
     const int64_t want = std::max<int64_t>(1, std::min(span_slot_capacity(L, nwg, s), exchanges));
     int64_t have = L->span_scratch ? (int64_t)(L->span_bytes - kSpanCtlBytes) / per : 0;
@@ -583,7 +583,7 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
         if (!nwg) return fail(KSLB_EINVAL, "shape cannot use the multi-workgroup kernel");
         int64_t slots = 0;
         if (auto st = span_prepare(L, nwg, sp, n_steps, &slots)) return st;
-        const int64_t ecopy = span_copy_bytes(L, nwg);
+        const int64_t ecopy = span_copy_bytes(L, nwg, sp);
         int* ctl = reinterpret_cast<int*>(L->span_scratch);
         char* ebase = L->span_scratch + kSpanCtlBytes;
         // launches of equal length (to a multiple of sp), each within the slots
@@ -592,9 +592,10 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
         const int64_t chunk = std::min(cap, ((n_steps + nl - 1) / nl + sp - 1) / sp * sp);
         for (int64_t done = 0; done < n_steps; done += chunk) {
             const int64_t s = std::min(chunk, n_steps - done);
-            e = launch_span(L->q, L->prec, L->state(), L->n, nwg, s, sp, ebase, ecopy, slots, ctl, L->ph.cf,
-                            L->stream, L->fixed ? &L->ends : nullptr);
+            e = launch_span(L->q, L->prec, L->state(), L->other(), L->n, nwg, s, sp, ebase, ecopy, slots, ctl,
+                            L->ph.cf, L->stream, L->fixed ? &L->ends : nullptr);
             if (e) return hip_fail(e, "multi-workgroup kernel");
+            L->cur ^= 1;
         }
     } else if (kernel == KSLB_KERNEL_RESIDENT) {
         if (!ringB) return fail(KSLB_EINVAL, "shape cannot use the resident kernel");

@@ -61,15 +61,15 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
                 const Coef& cf, void* stream);
 // One small lattice over nwg single-wave workgroups exchanging edges every s
 // steps through `slots` edge slots per launch (slots * nwg copies of ecopy
-// bytes from ebase, each one window of span_lanes() x span_sites_per_lane(q)
-// positions in state format; see span_edge_copy_bytes).  ctl holds span_ctl_ints(nwg) ints (abort, sticky
-// error, then the handshake flags), set up by launch_span_ctl_init.  The
-// state is advanced in place.
+// bytes from ebase, each holding one owner's own sites in state format; see
+// span_edge_copy_bytes).  ctl holds
+// span_ctl_ints() ints (abort word, sticky error word), set up by
+// launch_span_ctl_init.  The state is read from src and written to dst.
 int span_lanes();
 int span_sites_per_lane(int q);
-int span_ctl_ints(int nwg);
+int span_ctl_ints();
 int span_ctl_error_index();   // sticky: a launch timed out since the state was set
-int64_t span_edge_copy_bytes(int q, int prec, int64_t sites);
+int64_t span_edge_copy_bytes(int q, int prec, int64_t n, int nwg, int s);   // one slot copy
 int launch_span_ctl_init(int* ctl, int count, void* stream);
 int launch_span_set_ctl(int* ctl, int index, int value, void* stream);
 // Trajectory pair of an FP64 ensemble: byte offsets of the two current state
@@ -84,8 +84,8 @@ int launch_pair_renorm(int q, char* base, const PairDesc* desc, int npairs, doub
 struct Ends {
     double rho_l, rho_r;
 };
-int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase, int64_t ecopy,
-                int64_t slots, int* ctl, const Coef& cf, void* stream, const Ends* ends);
+int launch_span(int q, int prec, const void* src, void* dst, int64_t n, int nwg, int64_t steps, int s, char* ebase,
+                int64_t ecopy, int64_t slots, int* ctl, const Coef& cf, void* stream, const Ends* ends);
 int launch_plain_fixed(int q, int prec, const void* src, void* dst, int64_t n, const Coef& cf, const Ends& ends,
                        void* stream);
 int launch_init_fixed(int q, int prec, void* state, int64_t n, const double* rho0, const Coef& cf, const Ends& ends,

@@ -869,10 +869,9 @@ constexpr int kSpinLimit = 1 << 21;
 constexpr int kFirstPollDelay = 6;   // units of 64 clocks before the first poll of an exchange
 
 // Control words of the multi-workgroup kernel (device memory, kept by the
-// lattice across launches): the abort word of the current launch, a sticky
-// error word (set with it, cleared only when the state is replaced), then the
-// nwg flags of the final handshake.
-constexpr int kCtlAbort = 0, kCtlSticky = 1, kCtlFlags = 4;
+// lattice across launches): the abort word of the current launch and a
+// sticky error word (set with it, cleared only when the state is replaced).
+constexpr int kCtlAbort = 0, kCtlSticky = 1, kCtlWords = 64;
 
 // Edge slots.  At exchange c owner w stores its own sites, once, into slot
 // (c, w); its left neighbour reads the first H s of them, its right
@@ -986,10 +985,24 @@ __device__ __forceinline__ void site_store_sentinel(char* st, int64_t p, int64_t
     SiteWords<Q, P>::each(st, p, j, y, [](auto* a, auto) { st_sent(a); });
 }
 
-// Final handshake of a launch: a release fence and a relaxed store of the
-// flag; relaxed polls of both neighbours' flags (with the abort word, one
-// memory round trip per poll), then one acquire fence.  Bounded: on timeout
-// the abort and sticky words are raised and every waiter gives up.
+// Layout of an edge slot: the own sites of the writer (window slots
+// [hs, hs + mmax)) occupy lanes first .. first + lanes - 1; slot k = lane B + b
+// sits at b * lanes + (lane - first) of each row, so each store and poll
+// instruction covers consecutive words.  Rows hold `pitch` words.
+struct SpanSlot {
+    int64_t first, lanes, b, pitch;
+    __host__ __device__ int64_t pos(int64_t k) const { return (k % b) * lanes + (k / b - first); }
+};
+__host__ __device__ inline SpanSlot span_slot_shape(int b, int64_t hs, int64_t mmax)
+{
+    SpanSlot s;
+    s.b = b;
+    s.first = hs / b;
+    s.lanes = (hs + mmax - 1) / b - s.first + 1;
+    s.pitch = (b * s.lanes + 15) / 16 * 16;
+    return s;
+}
+
 __device__ __forceinline__ void span_raise_abort(int* ctl, int lane)
 {
     if (lane == 0) {
@@ -998,73 +1011,73 @@ __device__ __forceinline__ void span_raise_abort(int* ctl, int lane)
     }
 }
 
-__device__ __forceinline__ void span_signal(int* flag, int value, int lane)
+// First site of owner w when n sites are split over nwg owners, and the owner
+// of site j (0 <= j < n): the largest w with o(w) <= j.
+__device__ __forceinline__ int64_t span_first(int64_t n, int nwg, int64_t w) { return n * w / nwg; }
+__device__ __forceinline__ int span_owner(int64_t n, int nwg, int64_t j)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (lane == 0) __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ bool span_wait(const int* fa, const int* fb, int target, int* ctl, int lane)
-{
-    for (int spin = 0;; spin++) {
-        const int a = __hip_atomic_load(fa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int b = __hip_atomic_load(fb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int ab = __hip_atomic_load(ctl + kCtlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (__builtin_amdgcn_readfirstlane(a) >= target && __builtin_amdgcn_readfirstlane(b) >= target) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            return true;
-        }
-        if (__builtin_amdgcn_readfirstlane(ab) || spin >= kSpinLimit) {
-            span_raise_abort(ctl, lane);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
+    int64_t w = j * nwg / n;
+    while (w + 1 < nwg && span_first(n, nwg, w + 1) <= j) w++;
+    while (w > 0 && span_first(n, nwg, w) > j) w--;
+    return (int)w;
 }
 
 // Workgroup w owns sites [o_w, o_w + M_w) of the lattice and holds them, plus
 // H s halo sites on each side, in its registers (window slot k <-> site
-// o_w - H s + k).  Every s steps it stores its own sites to its edge slot of
-// this exchange and loads its halo from the neighbours' slots, polling until
-// no word holds the sentinel.  The final state is written in place after a
-// flag handshake with both neighbours, so no initial load can see it.  Every
-// wait is bounded; on timeout a workgroup raises the abort word and every
-// workgroup stops.
+// o_w - H s + k); a halo may span several owners.  The state is read from src
+// at the start of a launch and written to dst at its end.  Every s steps each
+// owner stores its own sites to its edge slot of this exchange and loads its
+// halo from the slots of the owners of those sites, polling until no word
+// holds the sentinel.  Every wait is bounded; on timeout a workgroup raises
+// the abort word and every workgroup stops.
 template <int Q, int P, bool FIX>
-__global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t n, int64_t p, int nwg,
-                                                  int64_t steps, int s, char* __restrict__ ebase, int64_t ecopy,
-                                                  int64_t epitch, int64_t slots, int* __restrict__ ctl, Coef cf,
-                                                  double rho_l, double rho_r)
+__global__ __launch_bounds__(kSpanLD) void k_span(const char* __restrict__ src, char* __restrict__ dst, int64_t n,
+                                                  int64_t p, int nwg, int64_t steps, int s, char* __restrict__ ebase,
+                                                  int64_t ecopy, int64_t epitch, int64_t slots,
+                                                  int* __restrict__ ctl, Coef cf, double rho_l, double rho_r)
 {
     using E = Engine<Q, P, span_b_of(Q), kSpanLD>;
     using PL = typename E::PL;
     using Site = typename E::Site;
     constexpr int B = span_b_of(Q);
     double* xch = nullptr;   // single wave: the engine exchanges by DPP
-    int* flags = ctl + kCtlFlags;
     // consecutive owners share an XCD (workgroups are dealt round-robin to 8 XCDs)
     const int per = (nwg + 7) / 8;
     const int w = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (w >= nwg) return;
-    const int left_w = w == 0 ? nwg - 1 : w - 1;
-    const int right_w = w + 1 == nwg ? 0 : w + 1;
-    const int64_t o = n * w / nwg;
-    const int64_t M = n * (w + 1) / nwg - o;
+    const int64_t o = span_first(n, nwg, w);
+    const int64_t M = span_first(n, nwg, w + 1) - o;
     const int hs = E::H * s;
     const int lane = threadIdx.x;
     const int left = lane == 0 ? kSpanLD - 1 : lane - 1;
     const int right = lane + 1 == kSpanLD ? 0 : lane + 1;
     auto slot = [&](int64_t chunk, int who) { return ebase + (chunk * nwg + who) * ecopy; };
-    // slot layout [site within lane][lane]: window slot k = lane B + b of the
-    // writer sits at b * 64 + lane, so every store and poll instruction covers
-    // consecutive words
-    auto pos = [](int64_t k) { return (k % B) * kSpanLD + k / B; };
-    const int64_t M_left = n * (left_w + 1) / nwg - n * left_w / nwg;   // own sites of the left neighbour
+    const SpanSlot sl = span_slot_shape(B, hs, (n + nwg - 1) / nwg);
+    auto pos = [&](int64_t k) { return sl.pos(k); };
+
+    // where each halo slot of this lane comes from: the owner of its site and
+    // that owner's window slot of it (slots outside the halo read the first
+    // word of this owner's own slot and ignore it)
+    int src_w[B];
+    int64_t idx[B];
+    bool want[B];
+    unroll<B>([&](auto Bi) {
+        const int64_t k = (int64_t)lane * B + Bi;
+        want[Bi] = k < hs || k >= hs + M;
+        src_w[Bi] = w;
+        idx[Bi] = 0;
+        if (want[Bi]) {
+            const int64_t j = wrap_site(o - hs + k, n);
+            const int ow = span_owner(n, nwg, j);
+            src_w[Bi] = ow;
+            idx[Bi] = pos(hs + (j - span_first(n, nwg, ow)));
+        }
+    });
 
     Site x[B];
     unroll<B>([&](auto Bi) {
         const int64_t k = (int64_t)lane * B + Bi;
-        x[Bi] = PL::load(st, p, wrap_site(o - hs + k, n));
+        x[Bi] = PL::load(src, p, wrap_site(o - hs + k, n));
     });
     // fixed ends: sites <= 0 and >= n-1 (boundary sites and the ghosts
     // beyond them) hold the end-value equilibria after every step; only the
@@ -1082,7 +1095,6 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
         }
     };
     if constexpr (FIX) fix(x);
-    bool ok = true;
     int64_t done = 0;
     for (int64_t c = 0; done < steps; c++) {
         const int sc = (int)(steps - done < s ? steps - done : s);
@@ -1092,8 +1104,7 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
         if (done >= steps) break;
         if (c >= slots) {   // the host sizes launches to their slots; stop rather than overrun
             span_raise_abort(ctl, lane);
-            ok = false;
-            break;
+            return;
         }
         // Publish own sites (one store per word).  No memory access of this
         // wave is outstanding here (the halo loads were consumed by the last
@@ -1104,29 +1115,16 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
             const int64_t k = (int64_t)lane * B + Bi;
             if (k >= hs && k < hs + M) site_store_sync<Q, P>(slot(c, w), epitch, pos(k), x[Bi]);
         });
-        // receive the halo: poll the neighbours' slots until every word is
-        // written.  Every slot of the lane loads (slots outside the halo read
-        // a valid word and ignore it), so all loads of a poll are in flight
-        // together: one memory round trip per poll.
-        char* src[B];
-        int64_t idx[B];
-        bool want[B];
-        // the neighbours' stores leave at the same time as ours: a first poll
-        // issued at once mostly reaches memory before them, so wait a little
+        // Receive the halo: every lane loads (so all loads of a poll are in
+        // flight together: one memory round trip per poll), polling until no
+        // wanted word holds the sentinel.  The neighbours' stores leave at the
+        // same time as ours, so a first poll issued at once mostly reaches
+        // memory before them: wait a little first.
         __builtin_amdgcn_s_sleep(kFirstPollDelay);
-        unroll<B>([&](auto Bi) {
-            const int64_t k = (int64_t)lane * B + Bi;
-            const bool lft = k < hs, rgt = k >= hs + M && k < 2 * hs + M;
-            want[Bi] = lft || rgt;
-            src[Bi] = rgt ? slot(c, right_w) : slot(c, left_w);
-            // the writer's window slot of this halo site: M_left + k (left
-            // neighbour), k - M (right neighbour)
-            idx[Bi] = lft ? pos(M_left + k) : (rgt ? pos(k - M) : 0);
-        });
         for (int spin = 0;; spin++) {
             Site y[B];
             bool got[B];
-            unroll<B>([&](auto Bi) { got[Bi] = site_load_sync<Q, P>(src[Bi], epitch, idx[Bi], y[Bi]); });
+            unroll<B>([&](auto Bi) { got[Bi] = site_load_sync<Q, P>(slot(c, src_w[Bi]), epitch, idx[Bi], y[Bi]); });
             const int ab = __hip_atomic_load(ctl + kCtlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             bool ready = true;
             unroll<B>([&](auto Bi) { ready = ready && (got[Bi] || !want[Bi]); });
@@ -1138,42 +1136,35 @@ __global__ __launch_bounds__(kSpanLD) void k_span(char* __restrict__ st, int64_t
             }
             if (__builtin_amdgcn_readfirstlane(ab) || spin >= kSpinLimit) {
                 span_raise_abort(ctl, lane);
-                ok = false;
-                break;
+                return;
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        if (!ok) break;
         if constexpr (FIX) fix(x);
     }
-    if (!ok) return;
-    // final state: only after both neighbours have finished the launch
-    span_signal(flags + w, 1, lane);
-    if (!span_wait(flags + left_w, flags + right_w, 1, ctl, lane)) return;
     unroll<B>([&](auto Bi) {
         const int64_t k = (int64_t)lane * B + Bi;
-        if (k >= hs && k < hs + M) PL::store(st, p, o + k - hs, x[Bi]);
+        if (k >= hs && k < hs + M) PL::store(dst, p, o + k - hs, x[Bi]);
     });
 }
 
-// Before each launch (one workgroup): clear the abort word and the flags.
-__global__ void k_span_prep(int* ctl, int nwg)
+// Before each launch: clear the abort word.
+__global__ void k_span_prep(int* ctl)
 {
-    for (int i = threadIdx.x; i < nwg; i += blockDim.x) ctl[kCtlFlags + i] = 0;
     if (threadIdx.x == 0) ctl[kCtlAbort] = 0;
 }
 
 // Sentinel in the words of `copies` edge copies that hold own sites: window
-// slots [hs, hs + sites) at their [site within lane][lane] positions.
+// slots [hs, hs + sites) at their slot positions.
 template <int Q, int P>
 __global__ __launch_bounds__(256) void k_span_fill(char* ebase, int64_t ecopy, int64_t epitch, int64_t copies,
                                                    int hs, int sites)
 {
-    constexpr int B = span_b_of(Q);
+    const SpanSlot sl = span_slot_shape(span_b_of(Q), hs, sites);
     const int64_t total = copies * sites;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
         const int64_t c = i / sites, k = hs + (i - c * sites);
-        site_store_sentinel<Q, P>(ebase + c * ecopy, epitch, (k % B) * kSpanLD + k / B);
+        site_store_sentinel<Q, P>(ebase + c * ecopy, epitch, sl.pos(k));
     }
 }
 
@@ -1490,8 +1481,12 @@ int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegD
 
 int span_lanes() { return kSpanLD; }
 int span_sites_per_lane(int q) { return span_b_of(q); }
-int span_ctl_ints(int nwg) { return kCtlFlags + nwg; }
-int64_t span_edge_copy_bytes(int q, int prec, int64_t sites) { return (int64_t)state_copy_bytes(state_pitch(sites), q, prec); }
+int span_ctl_ints() { return kCtlWords; }
+int64_t span_edge_copy_bytes(int q, int prec, int64_t n, int nwg, int s)
+{
+    const SpanSlot sl = span_slot_shape(span_b_of(q), (int64_t)halo_of(q) * s, (n + nwg - 1) / nwg);
+    return ((int64_t)state_copy_bytes(sl.pitch, q, prec) + 255) / 256 * 256;
+}
 
 int launch_span_ctl_init(int* ctl, int count, void* stream)
 {
@@ -1507,23 +1502,23 @@ int launch_span_set_ctl(int* ctl, int index, int value, void* stream)
 
 int span_ctl_error_index() { return kCtlSticky; }
 
-int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps, int s, char* ebase, int64_t ecopy,
-                int64_t slots, int* ctl, const Coef& cf, void* stream, const Ends* ends)
+int launch_span(int q, int prec, const void* src, void* dst, int64_t n, int nwg, int64_t steps, int s, char* ebase,
+                int64_t ecopy, int64_t slots, int* ctl, const Coef& cf, void* stream, const Ends* ends)
 {
     hipStream_t st = (hipStream_t)stream;
     const int h = halo_of(q);
     const int64_t hs = (int64_t)h * s;
     const int64_t W = (int64_t)kSpanLD * span_b_of(q);
     if (nwg < 2 || s < 1 || steps < 1 || slots < 1) return (int)hipErrorInvalidValue;
-    // every owner holds at least H s sites and its window fits
+    // every owner holds at least one site and its window fits
     const int64_t mmin = n / nwg, mmax = (n + nwg - 1) / nwg;
-    if (mmin < hs || mmax + 2 * hs > W) return (int)hipErrorInvalidValue;
-    // the exchanges of this launch fit the slots, and a slot holds mmax sites
+    if (mmin < 1 || mmax + 2 * hs > W) return (int)hipErrorInvalidValue;
+    // the exchanges of this launch fit the slots
     if ((steps + s - 1) / s - 1 > slots) return (int)hipErrorInvalidValue;
-    const int64_t epitch = state_pitch(W);   // a slot row holds every window position
+    const int64_t epitch = span_slot_shape(span_b_of(q), hs, mmax).pitch;
     if (ecopy < (int64_t)state_copy_bytes(epitch, q, prec)) return (int)hipErrorInvalidValue;
     const int64_t copies = std::min<int64_t>(slots, (steps + s - 1) / s - 1) * nwg;
-    k_span_prep<<<1, 256, 0, st>>>(ctl, nwg);
+    k_span_prep<<<1, 64, 0, st>>>(ctl);
     if (copies > 0) {
         const unsigned fill_blocks = (unsigned)std::min<int64_t>(4096, (copies * mmax + 255) / 256);
         KSLB_DISPATCH_QP(q, prec, (k_span_fill<Q_, P_><<<fill_blocks, 256, 0, st>>>(ebase, ecopy, epitch, copies,
@@ -1533,12 +1528,12 @@ int launch_span(int q, int prec, void* state, int64_t n, int nwg, int64_t steps,
     const unsigned grid = (unsigned)(per * 8);
     if (ends) {
         KSLB_DISPATCH_QP(q, prec, (k_span<Q_, P_, true><<<grid, kSpanLD, 0, st>>>(
-                                      (char*)state, n, state_pitch(n), nwg, steps, s, ebase, ecopy, epitch, slots, ctl,
-                                      cf, ends->rho_l, ends->rho_r)));
+                                      (const char*)src, (char*)dst, n, state_pitch(n), nwg, steps, s, ebase, ecopy,
+                                      epitch, slots, ctl, cf, ends->rho_l, ends->rho_r)));
     } else {
         KSLB_DISPATCH_QP(q, prec, (k_span<Q_, P_, false><<<grid, kSpanLD, 0, st>>>(
-                                      (char*)state, n, state_pitch(n), nwg, steps, s, ebase, ecopy, epitch, slots, ctl,
-                                      cf, 0.0, 0.0)));
+                                      (const char*)src, (char*)dst, n, state_pitch(n), nwg, steps, s, ebase, ecopy,
+                                      epitch, slots, ctl, cf, 0.0, 0.0)));
     }
     return (int)hipGetLastError();
 }

@@ -611,11 +611,15 @@ struct Engine {
 
     // one step x -> y from registers plus hv, the values pulled from the
     // neighbour lanes (hv[koff(i) + t] as published by publish_vals)
-    __device__ static __forceinline__ void step_hv(const Site (&x)[B], Site (&y)[B], const double (&hv)[NX],
-                                                   const Coef& cf)
+    // sites whose sources all lie in this lane (H <= b < B - H) first, so the
+    // neighbours' values have time to arrive; then the edge sites
+    template <bool INTERIOR>
+    __device__ static __forceinline__ void step_sites(const Site (&x)[B], Site (&y)[B], const double (&hv)[NX],
+                                                      const Coef& cf)
     {
         unroll<B>([&](auto Bi) {
             constexpr int b = Bi;
+            if constexpr ((b >= H && b < B - H) != INTERIOR) return;
             double g[Q];
             unroll<Q>([&](auto I) {
                 constexpr int i = I;
@@ -628,6 +632,13 @@ struct Engine {
             });
             PL::update(g, y[b], cf);
         });
+    }
+
+    __device__ static __forceinline__ void step_hv(const Site (&x)[B], Site (&y)[B], const double (&hv)[NX],
+                                                   const Coef& cf)
+    {
+        step_sites<true>(x, y, hv, cf);
+        step_sites<false>(x, y, hv, cf);
     }
 
     // one step x -> y: left/right point at the neighbours' columns of the slot

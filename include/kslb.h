@@ -252,7 +252,7 @@ kslb_status kslb_ensemble_set_physical(kslb_ensemble* ens, double dX, double dT,
  *   max_segments    instance tiles one workgroup window may hold, 1..256
  *                   (1 = one tile per workgroup);
  *   steps_per_chunk steps per launch, with 2 max|c| steps < the window.
- * Defaults: 8 sites, 16 segments, 32 steps.                                */
+ * Defaults: 8 sites, 16 segments, 64 steps.                                */
 kslb_status kslb_ensemble_set_tiling(kslb_ensemble* ens, int sites_per_lane, int max_segments,
                                      int steps_per_chunk);
 

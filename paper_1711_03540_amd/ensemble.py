@@ -38,7 +38,7 @@ class Ensemble:
                  ctypes.c_void_p(self.stream.cuda_stream))
         self._h = h
         self.n = self.sizes.copy()
-        self.chunk = 32
+        self.chunk = 64
 
     def set_physical(self, dX: float, dT: float, tau: float = 0.0, dm_variant: int = 0,
                      guard: str = "refuse", rho_max: float = 3.0) -> "Ensemble":
@@ -55,7 +55,7 @@ class Ensemble:
     def set_tiling(self, sites_per_lane: int = 0, max_segments: int = 0, steps_per_chunk: int = 0) -> "Ensemble":
         """Sites per lane (4/8), instance tiles per workgroup window, steps per launch (0 = keep)."""
         call("kslb_ensemble_set_tiling", self._h, sites_per_lane, max_segments, steps_per_chunk)
-        self.chunk = steps_per_chunk or getattr(self, "chunk", 32)
+        self.chunk = steps_per_chunk or getattr(self, "chunk", 64)
         return self
 
     def set_graphs(self, enable: bool = True) -> "Ensemble":

@@ -51,8 +51,10 @@ def _time(fn, reps: int = 3) -> float:
 
 def tune_lattice(n: int, q: int = 7, precision: str = "fp64", steps: int = 2000, dX: float = math.pi / 16,
                  dT: float = 1e-4, cache: Optional[str] = DEFAULT_CACHE,
-                 tile_steps: Iterable[int] = (8, 16, 24, 32, 40, 48, 64)) -> Dict:
-    """Best (kernel, steps_per_launch) for one periodic lattice of n sites."""
+                 tile_steps: Iterable[int] = (8, 16, 24, 32, 40, 48, 64),
+                 span_steps: Iterable[int] = (0, 12, 18, 24)) -> Dict:
+    """Best (kernel, steps_per_launch) for one periodic lattice of n sites
+    (steps_per_launch is the exchange interval for SPAN; 0 = its default)."""
     key = "lattice/q%d/%s/n%d" % (q, precision, n)
     data = _load(cache) if cache else {}
     if key in data:
@@ -61,7 +63,7 @@ def tune_lattice(n: int, q: int = 7, precision: str = "fp64", steps: int = 2000,
     cands: List[Dict] = []
     lat = Lattice(n, q, precision).set_physical(dX, dT, 0.0)
     lat.init_rho(rho0)
-    options = [("resident", 0)] + [("tiled", s) for s in tile_steps]
+    options = [("span", s) for s in span_steps] + [("resident", 0)] + [("tiled", s) for s in tile_steps]
     for kind, s in options:
         try:
             lat.set_kernel(kind, s)

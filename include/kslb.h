@@ -231,24 +231,38 @@ kslb_status kslb_diagnostics(kslb_lattice* lat, double* mass, int* nonfinite);
 kslb_status kslb_destroy(kslb_lattice* lat);
 
 /* ---------------------------------------------------------------------- */
-/* Ensembles: many independent periodic lattices of one scheme, precision  */
-/* and coefficient set, of any sizes, advanced together by one launch per  */
-/* chunk of steps.  Each instance has its own step budget.                 */
+/* Ensembles: many independent periodic lattices, each with its own size,  */
+/* scheme, storage mode, coefficients and step budget, advanced together:  */
+/* each chunk of steps is one launch per (scheme, storage) present, whose  */
+/* workgroups each hold tiles of one or more instances of one coefficient  */
+/* set.  The one-step arithmetic of an instance is that of a lattice of the */
+/* same scheme, storage and coefficients (bitwise).                        */
 /* ---------------------------------------------------------------------- */
 
-/* Device bytes for instances of the given sizes (ping-pong state of each,
- * 256-byte aligned, plus diagnostics).                                     */
-size_t kslb_ensemble_bytes(int count, const int64_t* n_sites, int q, int precision);
+/* Device bytes for instances i = 0 .. count-1 of n_sites[i] sites, scheme
+ * q[i] (KSLB_D1Q5 / KSLB_D1Q7) and storage precision[i] (host arrays): the
+ * ping-pong state of each, 256-byte aligned, plus diagnostics.  0 for a bad
+ * shape.                                                                   */
+size_t kslb_ensemble_bytes(int count, const int64_t* n_sites, const int* q, const int* precision);
 
-kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* n_sites, int q,
-                                 int precision, void* dev_buf, size_t buf_bytes, void* hip_stream);
+/* Carve the caller's device buffer (>= kslb_ensemble_bytes, 256-byte
+ * aligned; never freed by the library) into the instances' states; work is
+ * enqueued on the caller's stream.  The arrays are copied.                 */
+kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* n_sites, const int* q,
+                                 const int* precision, void* dev_buf, size_t buf_bytes, void* hip_stream);
 
-/* Coefficients shared by every instance (as kslb_set_physical). */
-kslb_status kslb_ensemble_set_physical(kslb_ensemble* ens, double dX, double dT, double tau,
+/* Coefficients of instance idx, or of every instance for idx = -1 (one set
+ * per scheme present), as kslb_set_physical: dX, dT, tau <= 0 for the fit of
+ * Eq. (general_tau_formula), the delta-M reading, the stability guard and
+ * its rho_max.  For idx = -1 nothing is assigned unless every instance's
+ * set is valid.  KSLB_RHO instances need tau = 1.  An instance's state is
+ * kept: new coefficients apply from its next step.                         */
+kslb_status kslb_ensemble_set_physical(kslb_ensemble* ens, int idx, double dX, double dT, double tau,
                                        int dm_variant, int guard_policy, double rho_max);
 
 /* Tiling knobs (0 keeps the current value):
- *   sites_per_lane  4 or 8 (window of 256 lanes x that many sites);
+ *   sites_per_lane  4 or 8 (window of 256 lanes x that many sites; 16 when
+ *                   every instance has the rho-only storage);
  *   max_segments    instance tiles one workgroup window may hold, 1..256
  *                   (1 = one tile per workgroup);
  *   steps_per_chunk steps per launch, with 2 max|c| steps < the window.
@@ -262,8 +276,8 @@ kslb_status kslb_ensemble_set_tiling(kslb_ensemble* ens, int sites_per_lane, int
  * are bitwise those of the launch-per-chunk path.                          */
 kslb_status kslb_ensemble_set_graphs(kslb_ensemble* ens, int enable);
 
-/* The tau in use (after the fit and the guard). */
-kslb_status kslb_ensemble_get_tau(const kslb_ensemble* ens, double* tau);
+/* The tau instance idx uses (after the fit and the guard). */
+kslb_status kslb_ensemble_get_tau(const kslb_ensemble* ens, int idx, double* tau);
 
 /* Reuse instance idx's memory for a lattice of n_sites <= its capacity (the
  * size given at create).  Its state is dropped; init it again.             */
@@ -282,15 +296,15 @@ kslb_status kslb_ensemble_read_rho(kslb_ensemble* ens, int idx, double* out, int
 
 /* Benettin renormalisation of trajectory pairs, a tool for the largest
  * Lyapunov exponent of the scheme's dynamics (the chaotic dynamics the paper
- * names as its next subject, section 4).  For each pair p of instances of an
- * FP64 ensemble (ref[p], pert[p]: host arrays of instance indices; equal
- * sites and steps; no instance perturbed twice or both reference and
- * perturbed): with d = || S_pert - S_ref ||_2 over all Q x n stored
+ * names as its next subject, section 4).  For each pair p of instances
+ * (ref[p], pert[p]: host arrays of indices of FP64 instances of one scheme
+ * with equal sites and steps; no instance perturbed twice, or both
+ * reference and perturbed): with d = || S_pert - S_ref ||_2 over all Q x n stored
  * (post-collision) populations, set S_pert <- S_ref + (S_pert - S_ref) delta / d
  * and add ln(d / delta) to log_accum[p] (device array of npairs doubles, owned
  * by the caller, which zeroes it first).  A zero or non-finite d leaves the
  * pair unchanged and stores NaN in log_accum[p].  Enqueued on the ensemble's
- * stream.  EINVAL for other precisions or bad pairs.                        */
+ * stream.  EINVAL for other storage modes or bad pairs.                 */
 kslb_status kslb_ensemble_renormalize(kslb_ensemble* ens, int npairs, const int* ref, const int* pert,
                                       double delta, double* log_accum);
 

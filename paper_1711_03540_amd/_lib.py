@@ -64,10 +64,10 @@ SIGNATURES = {
     "kslb_step_count": (_st, [_vp, _vp]),
     "kslb_diagnostics": (_st, [_vp, _vp, _vp]),
     "kslb_destroy": (_st, [_vp]),
-    "kslb_ensemble_bytes": (_sz, [_i, _vp, _i, _i]),
-    "kslb_ensemble_create": (_st, [_vp, _i, _vp, _i, _i, _vp, _sz, _vp]),
-    "kslb_ensemble_set_physical": (_st, [_vp, _d, _d, _d, _i, _i, _d]),
-    "kslb_ensemble_get_tau": (_st, [_vp, _vp]),
+    "kslb_ensemble_bytes": (_sz, [_i, _vp, _vp, _vp]),
+    "kslb_ensemble_create": (_st, [_vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "kslb_ensemble_set_physical": (_st, [_vp, _i, _d, _d, _d, _i, _i, _d]),
+    "kslb_ensemble_get_tau": (_st, [_vp, _i, _vp]),
     "kslb_ensemble_set_tiling": (_st, [_vp, _i, _i, _i]),
     "kslb_ensemble_set_graphs": (_st, [_vp, _i]),
     "kslb_ensemble_resize": (_st, [_vp, _i, _i64]),

@@ -782,33 +782,42 @@ const char* kslb_last_error(void) { return g_err.c_str(); }
 // ============================================================================
 
 struct kslb_ensemble {
-    int count = 0, q = 0, prec = 0, device = 0;
+    int count = 0, device = 0;
     char* buf = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
+    std::vector<int> q, prec;          // scheme and storage of each instance
     std::vector<int64_t> cap, n;       // capacity and current size (sites) per instance
     std::vector<size_t> off, copy;     // byte offset of copy 0, bytes per copy (at capacity)
     std::vector<int> cur;
     std::vector<int64_t> step;
     std::vector<char> have_state;
-    Physics ph;
+    // Coefficient sets: instance i uses set cls[i] (-1: not set yet), of
+    // scheme set_q[k].  gen changes whenever any instance's set changes.
+    std::vector<int> cls;
+    std::vector<Physics> sets;
+    std::vector<int> set_q;
+    uint64_t coef_gen = 1;
     // defaults: the fastest of the tuner's grid for the 4096-instance workload
     // (64-step chunks: 783 GLUPS against 739 for 32)
     int B = 8, chunk = 64, max_seg = 16;
     size_t diag_off = 0;
-    // Descriptor tables: two device slots (one per ping-pong parity), each
-    // remembered by the signature of the plan it holds.
+    // Descriptor tables (window headers, segments, coefficient sets): two
+    // device slots (one per ping-pong parity), each remembered by the
+    // signature of the plan it holds, with the launches of that plan.
+    struct Launch { int q, prec, w0, nwin; };
     char* d_tab[2] = {nullptr, nullptr};
     size_t d_cap[2] = {0, 0};
     std::vector<uint64_t> sig[2];
-    int nwin[2] = {0, 0};
+    std::vector<Launch> launches[2];
+    size_t seg_at[2] = {0, 0}, coef_at[2] = {0, 0};   // byte offsets in the slot
     int next_slot = 0;
     char* h_pin[2] = {nullptr, nullptr};   // pinned staging of each slot's upload
     size_t h_cap[2] = {0, 0};
     hipEvent_t up_ev[2] = {nullptr, nullptr};
     bool up_pending[2] = {false, false};
     uint64_t slot_gen[2] = {0, 0};          // bumped whenever a slot is rewritten
-    // steady state: the two alternating chunk launches captured as one graph
+    // steady state: the two alternating chunks' launches captured as one graph
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;       // private stream the graph is recorded on
     hipGraphExec_t gexec = nullptr;
@@ -825,12 +834,12 @@ struct kslb_ensemble {
 
 namespace {
 
-size_t ens_layout(int count, const int64_t* n_sites, int q, int prec, std::vector<size_t>* off,
+size_t ens_layout(int count, const int64_t* n_sites, const int* q, const int* prec, std::vector<size_t>* off,
                   std::vector<size_t>* copy)
 {
     size_t pos = 0;
     for (int i = 0; i < count; i++) {
-        const size_t c = state_copy_bytes(n_sites[i], q, prec);
+        const size_t c = state_copy_bytes(n_sites[i], q[i], prec[i]);
         if (off) off->push_back(pos);
         if (copy) copy->push_back(c);
         pos += 2 * c;
@@ -862,6 +871,51 @@ kslb_status ens_staging(kslb_ensemble* E, int64_t n)
 
 char* ens_state(kslb_ensemble* E, int i) { return E->buf + E->off[i] + (size_t)E->cur[i] * E->copy[i]; }
 
+int ens_max_halo(const kslb_ensemble* E)
+{
+    int h = 0;
+    for (int i = 0; i < E->count; i++) h = std::max(h, halo(E->q[i]));
+    return h;
+}
+
+// Give instance i (every instance for i < 0) the coefficient set ph of
+// scheme q, sharing an equal set already held.  Sets no instance uses are
+// dropped once they outnumber the instances.
+void ens_assign(kslb_ensemble* E, int i, int q, const Physics& ph)
+{
+    int k = -1;
+    for (size_t j = 0; j < E->sets.size(); j++)
+        if (E->set_q[j] == q && E->sets[j].tau == ph.tau && std::memcmp(&E->sets[j].cf, &ph.cf, sizeof(Coef)) == 0) {
+            k = (int)j;
+            break;
+        }
+    if (k < 0) {
+        E->sets.push_back(ph);
+        E->set_q.push_back(q);
+        k = (int)E->sets.size() - 1;
+    }
+    for (int j = 0; j < E->count; j++)
+        if (j == i || (i < 0 && E->q[j] == q)) E->cls[j] = k;
+    E->coef_gen++;
+    if ((int)E->sets.size() > E->count + 8) {
+        std::vector<int> map(E->sets.size(), -1);
+        std::vector<Physics> sets;
+        std::vector<int> set_q;
+        for (int j = 0; j < E->count; j++) {
+            const int c = E->cls[j];
+            if (c < 0) continue;
+            if (map[c] < 0) {
+                map[c] = (int)sets.size();
+                sets.push_back(E->sets[c]);
+                set_q.push_back(E->set_q[c]);
+            }
+            E->cls[j] = map[c];
+        }
+        E->sets.swap(sets);
+        E->set_q.swap(set_q);
+    }
+}
+
 struct Tile {
     int inst;
     int64_t start;
@@ -869,18 +923,43 @@ struct Tile {
     int lanes;
 };
 
+// A planned chunk: the launches (one per scheme and storage present), their
+// windows in the slot's header table, and the slot's segment and coefficient
+// tables.
+struct EnsPlan {
+    const WinHdr* hdr = nullptr;
+    const SegDesc* seg = nullptr;
+    const Coef* coefs = nullptr;
+    const std::vector<kslb_ensemble::Launch>* launches = nullptr;
+    int slot = 0;
+    int nwin = 0;
+};
+
+void ens_plan_view(const kslb_ensemble* E, int k, EnsPlan* plan)
+{
+    plan->hdr = reinterpret_cast<const WinHdr*>(E->d_tab[k]);
+    plan->seg = reinterpret_cast<const SegDesc*>(E->d_tab[k] + E->seg_at[k]);
+    plan->coefs = reinterpret_cast<const Coef*>(E->d_tab[k] + E->coef_at[k]);
+    plan->launches = &E->launches[k];
+    plan->slot = k;
+    plan->nwin = 0;
+    for (const auto& l : E->launches[k]) plan->nwin += l.nwin;
+}
+
 // Build and upload the descriptor tables of one chunk (instances advancing
 // s_i = adv[i] > 0 steps), or reuse a device slot that already holds the same
 // plan.  Tiles of at most W - 2 H s sites (a multiple of B) cut each
-// instance; best-fit-decreasing packs tiles with equal step counts into
-// windows of tile_lanes() lanes and at most max_seg segments.
-kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, const WinHdr** hdr, const SegDesc** seg,
-                     int* nwin, int* slot_out = nullptr, int avoid = -1)
+// instance; best-fit-decreasing packs tiles of one scheme, storage, step
+// count and coefficient set into windows of tile_lanes() lanes and at most
+// max_seg segments.  Windows are ordered by scheme and storage, one launch
+// each.
+kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, EnsPlan* plan, int avoid = -1)
 {
     std::vector<uint64_t> key;
-    key.reserve(3 * (size_t)E->count + 3);
+    key.reserve(3 * (size_t)E->count + 4);
     key.push_back((uint64_t)E->B);
     key.push_back((uint64_t)E->max_seg);
+    key.push_back(E->coef_gen);
     for (int i = 0; i < E->count; i++) {
         if (adv[i] <= 0) continue;
         key.push_back((uint64_t)i);
@@ -889,23 +968,26 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, const WinHdr
     }
     for (int k = 0; k < 2; k++) {
         if (E->d_tab[k] && E->sig[k] == key) {
-            *hdr = reinterpret_cast<const WinHdr*>(E->d_tab[k]);
-            *seg = reinterpret_cast<const SegDesc*>(E->d_tab[k] + sizeof(WinHdr) * (size_t)E->nwin[k]);
-            *nwin = E->nwin[k];
-            if (slot_out) *slot_out = k;
+            ens_plan_view(E, k, plan);
             return KSLB_OK;
         }
     }
-    const int H = halo(E->q);
     const int B = E->B;
     const int LANES = tile_lanes();
     const int64_t W = (int64_t)LANES * B;
-    // tiles grouped by step count
-    std::vector<std::pair<int, Tile>> tiles;   // (steps, tile)
+    // a tile's packing class: scheme, storage, steps, coefficient set
+    struct Cls {
+        int q, prec, steps, coef;
+        bool operator==(const Cls& o) const
+        {
+            return q == o.q && prec == o.prec && steps == o.steps && coef == o.coef;
+        }
+    };
+    std::vector<std::pair<Cls, Tile>> tiles;
     for (int i = 0; i < E->count; i++) {
         const int st = adv[i];
         if (st <= 0) continue;
-        const int64_t hs = (int64_t)H * st;
+        const int64_t hs = (int64_t)halo(E->q[i]) * st;
         int64_t tmax = W - 2 * hs;
         tmax -= tmax % B;
         const int64_t n = E->n[i];
@@ -915,27 +997,31 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, const WinHdr
             t.start = t0 - hs;
             t.valid = (int32_t)std::min<int64_t>(tmax, n - t0);
             t.lanes = (int)((t.valid + 2 * hs + B - 1) / B);
-            tiles.push_back({st, t});
+            tiles.push_back({Cls{E->q[i], E->prec[i], st, E->cls[i]}, t});
         }
     }
-    std::sort(tiles.begin(), tiles.end(), [](const std::pair<int, Tile>& a, const std::pair<int, Tile>& b) {
-        if (a.first != b.first) return a.first > b.first;
+    std::sort(tiles.begin(), tiles.end(), [](const std::pair<Cls, Tile>& a, const std::pair<Cls, Tile>& b) {
+        const Cls &x = a.first, &y = b.first;
+        if (x.q != y.q) return x.q < y.q;
+        if (x.prec != y.prec) return x.prec < y.prec;
+        if (x.steps != y.steps) return x.steps > y.steps;
+        if (x.coef != y.coef) return x.coef < y.coef;
         return a.second.lanes > b.second.lanes;
     });
-    struct Win { int steps; int used; std::vector<Tile> t; };
+    struct Win { Cls c; int used; std::vector<Tile> t; };
     std::vector<Win> wins;
     size_t g0 = 0;
     while (g0 < tiles.size()) {
-        const int st = tiles[g0].first;
+        const Cls c = tiles[g0].first;
         size_t g1 = g0;
-        while (g1 < tiles.size() && tiles[g1].first == st) g1++;
+        while (g1 < tiles.size() && tiles[g1].first == c) g1++;
         std::multimap<int, size_t> free_lanes;   // remaining lanes -> window index
         for (size_t k = g0; k < g1; k++) {
             const Tile& t = tiles[k].second;
             auto it = free_lanes.lower_bound(t.lanes);
             size_t w;
             if (it == free_lanes.end()) {
-                wins.push_back(Win{st, 0, {}});
+                wins.push_back(Win{c, 0, {}});
                 w = wins.size() - 1;
             } else {
                 w = it->second;
@@ -950,13 +1036,17 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, const WinHdr
     }
     std::vector<WinHdr> hv;
     std::vector<SegDesc> sv;
+    std::vector<kslb_ensemble::Launch> lv;
     hv.reserve(wins.size());
     for (const Win& w : wins) {
+        if (lv.empty() || lv.back().q != w.c.q || lv.back().prec != w.c.prec)
+            lv.push_back(kslb_ensemble::Launch{w.c.q, w.c.prec, (int)hv.size(), 0});
+        lv.back().nwin++;
         WinHdr h;
         h.first_seg = (int32_t)sv.size();
         h.nseg = (int32_t)w.t.size();
-        h.steps = w.steps;
-        h.pad_ = 0;
+        h.steps = w.c.steps;
+        h.coef = w.c.coef;
         hv.push_back(h);
         int lane = 0;
         for (const Tile& t : w.t) {
@@ -973,11 +1063,14 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, const WinHdr
             lane += t.lanes;
         }
     }
-    const size_t bytes = sizeof(WinHdr) * hv.size() + sizeof(SegDesc) * sv.size();
+    const size_t seg_at = sizeof(WinHdr) * hv.size();
+    const size_t coef_at = seg_at + sizeof(SegDesc) * sv.size();
+    const size_t bytes = coef_at + sizeof(Coef) * E->sets.size();
     int k = E->next_slot;
     if (k == avoid) k ^= 1;
     E->next_slot = k ^ 1;
     E->slot_gen[k]++;
+    E->sig[k].clear();   // the slot holds no valid plan until the upload below is enqueued
     if (E->d_cap[k] < bytes) {
         if (E->d_tab[k]) {
             (void)hipStreamSynchronize(E->stream);
@@ -1007,42 +1100,51 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, const WinHdr
     }
     if (!E->up_ev[k] && hipEventCreateWithFlags(&E->up_ev[k], hipEventDisableTiming))
         return fail(KSLB_EDEVICE, "hipEventCreate failed");
-    std::memcpy(E->h_pin[k], hv.data(), sizeof(WinHdr) * hv.size());
-    std::memcpy(E->h_pin[k] + sizeof(WinHdr) * hv.size(), sv.data(), sizeof(SegDesc) * sv.size());
+    std::memcpy(E->h_pin[k], hv.data(), seg_at);
+    std::memcpy(E->h_pin[k] + seg_at, sv.data(), coef_at - seg_at);
+    for (size_t j = 0; j < E->sets.size(); j++)
+        std::memcpy(E->h_pin[k] + coef_at + j * sizeof(Coef), &E->sets[j].cf, sizeof(Coef));
     // stream order keeps earlier kernels reading this slot ahead of the copy
     int e = hipMemcpyAsync(E->d_tab[k], E->h_pin[k], bytes, hipMemcpyHostToDevice, E->stream);
     if (!e) e = hipEventRecord(E->up_ev[k], E->stream);
     if (e) return hip_fail(e, "descriptor upload");
     E->up_pending[k] = true;
     E->sig[k] = key;
-    E->nwin[k] = (int)hv.size();
-    *hdr = reinterpret_cast<const WinHdr*>(E->d_tab[k]);
-    *seg = reinterpret_cast<const SegDesc*>(E->d_tab[k] + sizeof(WinHdr) * hv.size());
-    *nwin = (int)hv.size();
-    if (slot_out) *slot_out = k;
+    E->launches[k] = lv;
+    E->seg_at[k] = seg_at;
+    E->coef_at[k] = coef_at;
+    ens_plan_view(E, k, plan);
     return KSLB_OK;
+}
+
+// Enqueue a planned chunk: one kernel per scheme and storage present.
+int ens_launch(const kslb_ensemble* E, const EnsPlan& plan, hipStream_t stream)
+{
+    for (const auto& l : *plan.launches) {
+        int e = launch_ens(l.q, l.prec, E->B, E->buf, plan.hdr + l.w0, plan.seg, l.nwin, plan.coefs, stream);
+        if (e) return e;
+    }
+    return 0;
 }
 
 // Steady state: every active instance has at least `pairs` * 2 more full
 // chunks.  The chunk with the current parities and the one after it (all
 // parities flipped) are planned into the two descriptor slots and captured
-// once as a graph of two kernel launches, replayed `pairs` times.  The graph
-// holds kernels only (no memset or copy nodes); it is rebuilt whenever either
-// slot is rewritten.
+// once as a graph of their kernel launches, replayed `pairs` times.  The
+// graph holds kernels only (no memset or copy nodes); it is rebuilt whenever
+// either slot is rewritten.
 kslb_status ens_replay_pairs(kslb_ensemble* E, const std::vector<int>& adv, int64_t pairs)
 {
-    const WinHdr *ha, *hb;
-    const SegDesc *sa, *sb;
-    int na, nb, ka, kb;
-    if (auto s = ens_plan(E, adv, &ha, &sa, &na, &ka)) return s;
+    EnsPlan pa, pb;
+    if (auto s = ens_plan(E, adv, &pa)) return s;
     for (int i = 0; i < E->count; i++)
         if (adv[i] > 0) E->cur[i] ^= 1;
-    kslb_status st = ens_plan(E, adv, &hb, &sb, &nb, &kb, ka);
+    kslb_status st = ens_plan(E, adv, &pb, pa.slot);
     for (int i = 0; i < E->count; i++)
         if (adv[i] > 0) E->cur[i] ^= 1;
     if (st) return st;
-    const uint64_t key[5] = {(uint64_t)ka, E->slot_gen[ka], (uint64_t)kb, E->slot_gen[kb],
-                             ((uint64_t)E->B << 32) | (uint64_t)(na + nb)};
+    const uint64_t key[5] = {(uint64_t)pa.slot, E->slot_gen[pa.slot], (uint64_t)pb.slot, E->slot_gen[pb.slot],
+                             ((uint64_t)E->B << 32) | (uint64_t)(pa.nwin + pb.nwin)};
     if (!E->gexec || std::memcmp(key, E->gkey, sizeof key) != 0) {
         if (E->gexec) {
             (void)hipStreamSynchronize(E->stream);
@@ -1058,8 +1160,8 @@ kslb_status ens_replay_pairs(kslb_ensemble* E, const std::vector<int>& adv, int6
         hipGraph_t graph = nullptr;
         int e = hipStreamBeginCapture(E->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e) return hip_fail(e, "hipStreamBeginCapture");
-        int e1 = launch_ens(E->q, E->prec, E->B, E->buf, ha, sa, na, E->ph.cf, E->cap_stream);
-        int e2 = launch_ens(E->q, E->prec, E->B, E->buf, hb, sb, nb, E->ph.cf, E->cap_stream);
+        int e1 = ens_launch(E, pa, E->cap_stream);
+        int e2 = e1 ? 0 : ens_launch(E, pb, E->cap_stream);
         e = hipStreamEndCapture(E->cap_stream, &graph);
         if (e1 || e2 || e) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -1084,22 +1186,22 @@ kslb_status ens_replay_pairs(kslb_ensemble* E, const std::vector<int>& adv, int6
 
 extern "C" {
 
-size_t kslb_ensemble_bytes(int count, const int64_t* n_sites, int q, int precision)
+size_t kslb_ensemble_bytes(int count, const int64_t* n_sites, const int* q, const int* precision)
 {
-    if (count <= 0 || !n_sites) return 0;
+    if (count <= 0 || !n_sites || !q || !precision) return 0;
     for (int i = 0; i < count; i++)
-        if (!valid_shape(n_sites[i], q, precision)) return 0;
+        if (!valid_shape(n_sites[i], q[i], precision[i])) return 0;
     return ens_layout(count, n_sites, q, precision, nullptr, nullptr) + kDiagBytes;
 }
 
-kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* n_sites, int q, int precision,
-                                 void* dev_buf, size_t buf_bytes, void* hip_stream)
+kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* n_sites, const int* q,
+                                 const int* precision, void* dev_buf, size_t buf_bytes, void* hip_stream)
 {
     if (!out) return fail(KSLB_EINVAL, "out must not be NULL");
     *out = nullptr;
-    if (count <= 0 || !n_sites) return fail(KSLB_EINVAL, "count must be > 0 with sizes");
+    if (count <= 0 || !n_sites || !q || !precision) return fail(KSLB_EINVAL, "count must be > 0 with sizes, schemes and storage modes");
     for (int i = 0; i < count; i++)
-        if (!valid_shape(n_sites[i], q, precision))
+        if (!valid_shape(n_sites[i], q[i], precision[i]))
             return fail(KSLB_EINVAL, "bad shape of instance %d", i);
     if (!dev_buf || reinterpret_cast<uintptr_t>(dev_buf) % 256)
         return fail(KSLB_EINVAL, "device buffer missing or not 256-byte aligned");
@@ -1111,8 +1213,8 @@ kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* 
     kslb_ensemble* E = new (std::nothrow) kslb_ensemble;
     if (!E) return fail(KSLB_ENOMEM, "host allocation failed");
     E->count = count;
-    E->q = q;
-    E->prec = precision;
+    E->q.assign(q, q + count);
+    E->prec.assign(precision, precision + count);
     E->device = dev;
     E->buf = (char*)dev_buf;
     E->bytes = buf_bytes;
@@ -1123,27 +1225,46 @@ kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* 
     E->cur.assign(count, 0);
     E->step.assign(count, 0);
     E->have_state.assign(count, 0);
+    E->cls.assign(count, -1);
     *out = E;
     return KSLB_OK;
 }
 
-kslb_status kslb_ensemble_set_physical(kslb_ensemble* E, double dX, double dT, double tau, int dm_variant,
+kslb_status kslb_ensemble_set_physical(kslb_ensemble* E, int idx, double dX, double dT, double tau, int dm_variant,
                                        int guard_policy, double rho_max)
 {
     if (!E) return fail(KSLB_EINVAL, "null ensemble");
-    Physics ph;
-    kslb_status st = set_physics(ph, E->q, dX, dT, tau, dm_variant, guard_policy, rho_max);
-    if (st) return st;
-    if ((st = rho_mode_check(E->prec, ph))) return st;
-    E->ph = ph;
+    if (idx >= 0) {
+        if (auto s = check_ens(E, idx)) return s;
+        Physics ph;
+        kslb_status st = set_physics(ph, E->q[idx], dX, dT, tau, dm_variant, guard_policy, rho_max);
+        if (st) return st;
+        if ((st = rho_mode_check(E->prec[idx], ph))) return st;
+        ens_assign(E, idx, E->q[idx], ph);
+        return KSLB_OK;
+    }
+    // every instance: one set per scheme present, all checked before any is assigned
+    Physics ph[2];
+    bool want[2] = {false, false};
+    for (int i = 0; i < E->count; i++) want[E->q[i] == 7] = true;
+    for (int s = 0; s < 2; s++) {
+        if (!want[s]) continue;
+        kslb_status st = set_physics(ph[s], s ? 7 : 5, dX, dT, tau, dm_variant, guard_policy, rho_max);
+        if (st) return st;
+    }
+    for (int i = 0; i < E->count; i++)
+        if (auto st = rho_mode_check(E->prec[i], ph[E->q[i] == 7])) return st;
+    for (int s = 0; s < 2; s++)
+        if (want[s]) ens_assign(E, -1, s ? 7 : 5, ph[s]);
     return KSLB_OK;
 }
 
-kslb_status kslb_ensemble_get_tau(const kslb_ensemble* E, double* tau)
+kslb_status kslb_ensemble_get_tau(const kslb_ensemble* E, int idx, double* tau)
 {
-    if (!E || !tau) return fail(KSLB_EINVAL, "bad arguments");
-    if (!E->ph.set) return fail(KSLB_ESTATE, "coefficients not set");
-    *tau = E->ph.tau;
+    if (auto s = check_ens(E, idx)) return s;
+    if (!tau) return fail(KSLB_EINVAL, "tau must not be NULL");
+    if (E->cls[idx] < 0) return fail(KSLB_ESTATE, "coefficients of instance %d not set", idx);
+    *tau = E->sets[E->cls[idx]].tau;
     return KSLB_OK;
 }
 
@@ -1153,11 +1274,13 @@ kslb_status kslb_ensemble_set_tiling(kslb_ensemble* E, int sites_per_lane, int m
     int B = sites_per_lane ? sites_per_lane : E->B;
     int m = max_segments ? max_segments : E->max_seg;
     int c = steps_per_chunk ? steps_per_chunk : E->chunk;
-    if (B != 4 && B != 8 && !(B == 16 && E->prec == kRHO))
-        return fail(KSLB_EINVAL, "sites_per_lane must be 4 or 8 (or 16 with the rho-only storage)");
+    bool all_rho = true;
+    for (int i = 0; i < E->count; i++) all_rho = all_rho && E->prec[i] == kRHO;
+    if (B != 4 && B != 8 && !(B == 16 && all_rho))
+        return fail(KSLB_EINVAL, "sites_per_lane must be 4 or 8 (or 16 with the rho-only storage throughout)");
     if (m < 1 || m > tile_lanes()) return fail(KSLB_EINVAL, "max_segments must lie in [1, %d]", tile_lanes());
     const int64_t W = (int64_t)tile_lanes() * B;
-    if (c < 1 || W - 2 * halo(E->q) * (int64_t)c < B)
+    if (c < 1 || W - 2 * ens_max_halo(E) * (int64_t)c < B)
         return fail(KSLB_EINVAL, "steps_per_chunk %d leaves no valid sites in a %lld-site window", c, (long long)W);
     E->B = B;
     E->max_seg = m;
@@ -1188,7 +1311,7 @@ kslb_status kslb_ensemble_init_rho(kslb_ensemble* E, int idx, const double* rho,
 {
     if (auto s = check_ens(E, idx)) return s;
     if (!rho) return fail(KSLB_EINVAL, "rho must not be NULL");
-    if (!E->ph.set) return fail(KSLB_ESTATE, "set the coefficients before init_rho");
+    if (E->cls[idx] < 0) return fail(KSLB_ESTATE, "set the coefficients of instance %d before init_rho", idx);
     DeviceGuard g(E->device);
     const double* src = rho;
     if (!on_device) {
@@ -1198,7 +1321,7 @@ kslb_status kslb_ensemble_init_rho(kslb_ensemble* E, int idx, const double* rho,
         src = E->staging;
     }
     E->cur[idx] = 0;
-    int e = launch_init(E->q, E->prec, ens_state(E, idx), E->n[idx], src, E->ph.cf, E->stream);
+    int e = launch_init(E->q[idx], E->prec[idx], ens_state(E, idx), E->n[idx], src, E->sets[E->cls[idx]].cf, E->stream);
     if (e) return hip_fail(e, "init kernel");
     if (!on_device) {
         e = hipStreamSynchronize(E->stream);
@@ -1244,11 +1367,9 @@ kslb_status kslb_ensemble_advance(kslb_ensemble* E, const int64_t* steps)
                 continue;
             }
         }
-        const WinHdr* hdr = nullptr;
-        const SegDesc* seg = nullptr;
-        int nwin = 0;
-        if (auto s = ens_plan(E, adv, &hdr, &seg, &nwin)) return s;
-        int e = launch_ens(E->q, E->prec, E->B, E->buf, hdr, seg, nwin, E->ph.cf, E->stream);
+        EnsPlan plan;
+        if (auto s = ens_plan(E, adv, &plan)) return s;
+        int e = ens_launch(E, plan, E->stream);
         if (e) return hip_fail(e, "ensemble kernel");
         for (int i = 0; i < E->count; i++) {
             if (adv[i] <= 0) continue;
@@ -1271,7 +1392,7 @@ kslb_status kslb_ensemble_read_rho(kslb_ensemble* E, int idx, double* out, int o
         if (auto s = ens_staging(E, E->n[idx])) return s;
         dst = E->staging;
     }
-    int e = launch_read_rho(E->q, E->prec, ens_state(E, idx), E->n[idx], dst, E->stream);
+    int e = launch_read_rho(E->q[idx], E->prec[idx], ens_state(E, idx), E->n[idx], dst, E->stream);
     if (e) return hip_fail(e, "readout kernel");
     if (!on_device) {
         e = hipMemcpyAsync(out, dst, sizeof(double) * (size_t)E->n[idx], hipMemcpyDeviceToHost, E->stream);
@@ -1291,7 +1412,7 @@ kslb_status kslb_ensemble_status(kslb_ensemble* E, int idx, int64_t* step, int* 
     double* partial = reinterpret_cast<double*>(E->buf + E->diag_off);
     double* mass_d = partial + 256;
     int* flag_d = reinterpret_cast<int*>(partial + 257);
-    int e = launch_diag(E->q, E->prec, ens_state(E, idx), E->n[idx], partial, flag_d, mass_d, E->stream);
+    int e = launch_diag(E->q[idx], E->prec[idx], ens_state(E, idx), E->n[idx], partial, flag_d, mass_d, E->stream);
     if (e) return hip_fail(e, "diagnostics kernel");
     int f = 0;
     e = hipMemcpyAsync(&f, flag_d, sizeof f, hipMemcpyDeviceToHost, E->stream);
@@ -1308,23 +1429,32 @@ kslb_status kslb_ensemble_renormalize(kslb_ensemble* E, int npairs, const int* r
     if (npairs < 0 || (npairs > 0 && (!ref || !pert || !log_accum)))
         return fail(KSLB_EINVAL, "bad pair arguments");
     if (!(delta > 0.0) || !std::isfinite(delta)) return fail(KSLB_EINVAL, "delta must be positive and finite");
-    if (E->prec != kFP64) return fail(KSLB_EINVAL, "trajectory pairs need FP64 storage");
     if (npairs == 0) return KSLB_OK;
     std::vector<PairDesc> pd((size_t)npairs);
+    int nq5 = 0;   // pairs of D1Q5 instances, placed first in the table
     for (int p = 0; p < npairs; p++) {
         const int a = ref[p], b = pert[p];
         if (a < 0 || a >= E->count || b < 0 || b >= E->count || a == b)
             return fail(KSLB_EINVAL, "pair %d: bad instances (%d, %d)", p, a, b);
+        if (E->prec[a] != kFP64 || E->prec[b] != kFP64)
+            return fail(KSLB_EINVAL, "pair %d: trajectory pairs need FP64 storage", p);
+        if (E->q[a] != E->q[b]) return fail(KSLB_EINVAL, "pair %d: instances differ in scheme", p);
         if (!E->have_state[a] || !E->have_state[b]) return fail(KSLB_ESTATE, "pair %d: instance without state", p);
         if (E->n[a] != E->n[b] || E->step[a] != E->step[b])
             return fail(KSLB_EINVAL, "pair %d: instances differ in sites or steps", p);
-        pd[p] = PairDesc{(int64_t)(E->off[a] + (size_t)E->cur[a] * E->copy[a]),
-                         (int64_t)(E->off[b] + (size_t)E->cur[b] * E->copy[b]), E->n[a], state_pitch(E->n[a]), p, 0};
+        nq5 += E->q[a] == 5;
     }
     for (int p = 0; p < npairs; p++)
         for (int r = p + 1; r < npairs; r++)
             if (pert[p] == pert[r] || pert[p] == ref[r] || ref[p] == pert[r])
                 return fail(KSLB_EINVAL, "pairs %d and %d share a perturbed instance", p, r);
+    int at5 = 0, at7 = nq5;
+    for (int p = 0; p < npairs; p++) {
+        const int a = ref[p], b = pert[p];
+        pd[E->q[a] == 5 ? at5++ : at7++] =
+            PairDesc{(int64_t)(E->off[a] + (size_t)E->cur[a] * E->copy[a]),
+                     (int64_t)(E->off[b] + (size_t)E->cur[b] * E->copy[b]), E->n[a], state_pitch(E->n[a]), p, 0};
+    }
     DeviceGuard g(E->device);
     const size_t bytes = sizeof(PairDesc) * (size_t)npairs;
     int e = 0;
@@ -1356,8 +1486,9 @@ kslb_status kslb_ensemble_renormalize(kslb_ensemble* E, int npairs, const int* r
     if (!e) e = hipEventRecord(E->pairs_ev, E->stream);
     if (e) return hip_fail(e, "pair table upload");
     E->pairs_pending = true;
-    e = launch_pair_renorm(E->q, E->buf, reinterpret_cast<const PairDesc*>(E->d_pairs), npairs, delta, log_accum,
-                           E->stream);
+    const PairDesc* dt = reinterpret_cast<const PairDesc*>(E->d_pairs);
+    if (nq5) e = launch_pair_renorm(5, E->buf, dt, nq5, delta, log_accum, E->stream);
+    if (!e && npairs > nq5) e = launch_pair_renorm(7, E->buf, dt + nq5, npairs - nq5, delta, log_accum, E->stream);
     if (e) return hip_fail(e, "pair renormalisation kernel");
     return KSLB_OK;
 }

@@ -99,12 +99,13 @@ int launch_diag(int q, int prec, const void* state, int64_t n, double* partial, 
                 double* mass_out, void* stream);
 
 // ensemble: one window per workgroup; a window holds one or more segments,
-// each a tile of one instance on a consecutive range of lanes.
+// each a tile of one instance on a consecutive range of lanes.  Every
+// segment of a window shares the window's step count and coefficient set.
 struct WinHdr {
     int32_t first_seg;  // index of the window's first segment
     int32_t nseg;       // segments in the window (>= 1)
     int32_t steps;      // steps every segment of the window advances
-    int32_t pad_;
+    int32_t coef;       // index of the window's coefficient set in the launch's table
 };
 struct SegDesc {
     int64_t src_off;    // byte offset of the instance's source state copy
@@ -115,7 +116,8 @@ struct SegDesc {
     int32_t lane_lo;    // first lane of the segment
     int32_t valid;      // sites written back, from slot H * steps on
 };
+// coefs: device table of coefficient sets, indexed by WinHdr::coef
 int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegDesc* seg, int nwin,
-               const Coef& cf, void* stream);
+               const Coef* coefs, void* stream);
 
 }  // namespace kslb

@@ -851,14 +851,16 @@ __global__ __launch_bounds__(kTileLD) void k_tile(const char* __restrict__ src, 
 // Ensemble: workgroup w runs window hdr[w], whose segments seg[first ..
 // first + nseg) occupy consecutive lane ranges; each segment is one tile of
 // one instance with its own halo, so several small instances share a window.
-// Lanes past the last segment's tile carry junk that is never stored.
+// Lanes past the last segment's tile carry junk that is never stored.  The
+// window's coefficient set is uniform over the workgroup (scalar loads).
 template <int Q, int P, int B>
 __global__ __launch_bounds__(kTileLD) void k_ens(char* base, const WinHdr* __restrict__ hdr,
-                                                 const SegDesc* __restrict__ seg, Coef cf)
+                                                 const SegDesc* __restrict__ seg, const Coef* __restrict__ coefs)
 {
     extern __shared__ double xch[];
     constexpr int H = halo_of(Q);
     const WinHdr h = hdr[blockIdx.x];
+    const Coef cf = coefs[h.coef];
     const int lane = threadIdx.x;
     int my = 0;
     for (int k = 1; k < h.nseg; k++)
@@ -1468,7 +1470,7 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
 }
 
 template <int Q, int P, int B>
-static int ens_one(char* base, const WinHdr* hdr, const SegDesc* seg, int nwin, const Coef& cf, void* stream)
+static int ens_one(char* base, const WinHdr* hdr, const SegDesc* seg, int nwin, const Coef* cf, void* stream)
 {
     const int lds = tile_lds_bytes(Q);
     int e = prep_lds(k_ens<Q, P, B>, lds);
@@ -1478,7 +1480,7 @@ static int ens_one(char* base, const WinHdr* hdr, const SegDesc* seg, int nwin, 
 }
 
 int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegDesc* seg, int nwin,
-               const Coef& cf, void* stream)
+               const Coef* cf, void* stream)
 {
     if (nwin <= 0) return 0;
     if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 4>(base, hdr, seg, nwin, cf, stream))); }

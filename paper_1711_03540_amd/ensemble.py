@@ -12,20 +12,26 @@ from .lattice import _dptr, _prec
 
 
 class Ensemble:
-    """``len(sizes)`` independent periodic lattices of one scheme and precision.
+    """``len(sizes)`` independent periodic lattices.
 
-    Instance i has capacity ``sizes[i]`` sites; all share one coefficient set.
+    Instance i has capacity ``sizes[i]`` sites, scheme ``q[i]`` and storage
+    ``precision[i]`` (either may be one value for all) and its own
+    coefficients (``set_physical``, for one instance or all).
     ``advance(steps)`` moves instance i by ``steps[i]`` steps, one kernel
-    launch per chunk of steps for the whole ensemble.
+    launch per chunk of steps for each (scheme, storage) present.
     """
 
-    def __init__(self, sizes: Sequence[int], q: int = 7, precision="fp64", device=None, stream=None):
+    def __init__(self, sizes: Sequence[int], q=7, precision="fp64", device=None, stream=None):
         import torch
         self.sizes = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
         self.count = int(self.sizes.size)
-        self.q, self.precision = int(q), _prec(precision)
+        self.qs = np.ascontiguousarray(np.broadcast_to(np.asarray(q, dtype=np.int32), (self.count,)))
+        precs = [precision] * self.count if isinstance(precision, (str, int)) else list(precision)
+        if len(precs) != self.count:
+            raise ValueError("one precision per instance, or one for all")
+        self.precs = np.ascontiguousarray(np.asarray([_prec(p) for p in precs], dtype=np.int32))
         self.device = torch.device(device if device is not None else "cuda")
-        nbytes = fn("kslb_ensemble_bytes")(self.count, _dptr(self.sizes), self.q, self.precision)
+        nbytes = fn("kslb_ensemble_bytes")(self.count, _dptr(self.sizes), _dptr(self.qs), _dptr(self.precs))
         if nbytes == 0:
             raise ValueError("bad ensemble shape")
         self.nbytes = nbytes
@@ -33,24 +39,30 @@ class Ensemble:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            call("kslb_ensemble_create", ctypes.byref(h), self.count, _dptr(self.sizes), self.q,
-                 self.precision, ctypes.c_void_p(self.buf.data_ptr()), nbytes,
+            call("kslb_ensemble_create", ctypes.byref(h), self.count, _dptr(self.sizes), _dptr(self.qs),
+                 _dptr(self.precs), ctypes.c_void_p(self.buf.data_ptr()), nbytes,
                  ctypes.c_void_p(self.stream.cuda_stream))
         self._h = h
         self.n = self.sizes.copy()
         self.chunk = 64
 
     def set_physical(self, dX: float, dT: float, tau: float = 0.0, dm_variant: int = 0,
-                     guard: str = "refuse", rho_max: float = 3.0) -> "Ensemble":
+                     guard: str = "refuse", rho_max: float = 3.0, idx: int = -1) -> "Ensemble":
+        """Coefficients of instance idx, or of every instance (idx = -1)."""
         g = {"refuse": _lib.GUARD_REFUSE, "raise": _lib.GUARD_RAISE_TAU, "off": _lib.GUARD_OFF}[guard]
-        call("kslb_ensemble_set_physical", self._h, dX, dT, tau, dm_variant, g, rho_max)
+        call("kslb_ensemble_set_physical", self._h, int(idx), dX, dT, tau, dm_variant, g, rho_max)
         return self
+
+    def tau_of(self, idx: int) -> float:
+        t = ctypes.c_double()
+        call("kslb_ensemble_get_tau", self._h, int(idx), ctypes.byref(t))
+        return t.value
 
     @property
     def tau(self) -> float:
-        t = ctypes.c_double()
-        call("kslb_ensemble_get_tau", self._h, ctypes.byref(t))
-        return t.value
+        """tau of instance 0 (the tau of every instance after set_physical for all
+        instances of one scheme)."""
+        return self.tau_of(0)
 
     def set_tiling(self, sites_per_lane: int = 0, max_segments: int = 0, steps_per_chunk: int = 0) -> "Ensemble":
         """Sites per lane (4/8), instance tiles per workgroup window, steps per launch (0 = keep)."""

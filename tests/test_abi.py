@@ -69,3 +69,25 @@ def test_errors_are_reported_without_device_work():
     assert st == _lib.KSLB_EINVAL
     st = lib.kslb_advance(None, 1)
     assert st == _lib.KSLB_EINVAL
+
+
+def test_ensemble_bytes_per_instance_shapes():
+    import numpy as np
+    f = _lib.fn("kslb_ensemble_bytes")
+    one = _lib.fn("kslb_state_bytes")
+    sizes = np.array([1000, 64, 4096, 7], dtype=np.int64)
+    qs = np.array([7, 5, 7, 5], dtype=np.int32)
+    precs = np.array([0, 1, 2, 3], dtype=np.int32)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    # each instance's ping-pong state as a lattice of its own, one diagnostics block
+    want = sum(one(int(n), int(q), int(p)) - 4096 for n, q, p in zip(sizes, qs, precs)) + 4096
+    assert f(4, ptr(sizes), ptr(qs), ptr(precs)) == want
+    bad = qs.copy()
+    bad[2] = 6
+    assert f(4, ptr(sizes), ptr(bad), ptr(precs)) == 0
+    assert f(4, ptr(sizes), None, ptr(precs)) == 0
+    h = ctypes.c_void_p()
+    lib = _lib.load()
+    assert lib.kslb_ensemble_create(ctypes.byref(h), 4, ptr(sizes), ptr(bad), ptr(precs), None, 0, None) \
+        == _lib.KSLB_EINVAL
+    assert "instance 2" in _lib.last_error()

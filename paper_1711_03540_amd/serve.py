@@ -98,15 +98,21 @@ class ServeStats:
     results: List[Result]
     wall: float
     site_updates: float
+    queue_max: int = 0          # most requests waiting for a slot at once
+    queue_mean: float = 0.0     # time-averaged number waiting
 
     def summary(self) -> dict:
         lat = np.array([r.latency for r in self.results])
         done = np.isfinite(lat)
         lat_ms = lat[done] * 1e3
+        wait = np.array([r.admitted - r.arrival for r in self.results])
+        wait_ms = wait[np.isfinite(wait)] * 1e3
+        pct = lambda a, q: float(np.percentile(a, q)) if a.size else None
         return {"requests": len(self.results), "completed": int(done.sum()),
-                "p50_ms": float(np.percentile(lat_ms, 50)) if done.any() else None,
-                "p99_ms": float(np.percentile(lat_ms, 99)) if done.any() else None,
+                "p50_ms": pct(lat_ms, 50), "p99_ms": pct(lat_ms, 99),
                 "mean_ms": float(lat_ms.mean()) if done.any() else None,
+                "queue_wait_p50_ms": pct(wait_ms, 50), "queue_wait_p99_ms": pct(wait_ms, 99),
+                "queue_depth_max": self.queue_max, "queue_depth_mean": self.queue_mean,
                 "wall_s": self.wall, "site_updates": self.site_updates,
                 "achieved_glups": self.site_updates / self.wall / 1e9}
 
@@ -137,12 +143,18 @@ class SolveServer:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if realtime else (lambda: math.inf)
+        q_max, q_area, q_last = 0, 0.0, 0.0      # admission queue depth statistics
         while unfinished:
             now = clock()
+            t_now = time.perf_counter() - t0
+            depth = sum(len(w) for w in waiting.values())
+            q_area += depth * (t_now - q_last)
+            q_last = t_now
             while pending and requests[pending[0]].arrival <= now:
                 i = pending.popleft()
                 r = requests[i]
                 waiting[(r.q, SERVE_PRECISION[r.precision])].append(i)
+            q_max = max(q_max, sum(len(w) for w in waiting.values()))
             progressed = False
             for key, pool in self.pools.items():
                 w = waiting[key]
@@ -177,4 +189,4 @@ class SolveServer:
             if res.rho is not None:
                 res.finite = bool(torch.isfinite(res.rho).all().item())
         su = float(sum(r.n * r.steps for r in requests))
-        return ServeStats(results, wall, su)
+        return ServeStats(results, wall, su, q_max, q_area / wall if wall > 0 else 0.0)

@@ -26,11 +26,11 @@
  *     is rho_j = sum_i f_i(j) of the paper's f at time n.
  *   - Device memory and HIP streams belong to the caller.  The library never
  *     frees a caller buffer.  It allocates only small descriptor tables, the
- *     exchange area of the SPAN kernel (two edges of H s sites per workgroup
- *     and exchange, for the exchanges of one launch, at most 256 MiB; a
- *     longer advance is split into several launches) and, when a host
- *     pointer is passed to a transfer call, one device staging buffer of
- *     Q * n_sites doubles; all live until destroy.
+ *     exchange area of the SPAN kernel (a 256-byte control block and, for
+ *     each exchange of one launch, one copy of every workgroup's own sites;
+ *     at most 256 MiB, a longer advance being split into several launches)
+ *     and, when a host pointer is passed to a transfer call, one device
+ *     staging buffer of Q * n_sites doubles; all live until destroy.
  *   - Every function returns a kslb_status (0 = OK, < 0 = error) and never
  *     aborts or throws; kslb_last_error() describes the last failure of the
  *     calling thread.  Work enqueued on the stream is asynchronous; a device
@@ -92,11 +92,14 @@ enum { KSLB_GUARD_REFUSE = 0, KSLB_GUARD_RAISE_TAU = 1, KSLB_GUARD_OFF = 2 };
  *              steps; needs n_sites = B * L with B in {4, 8}, L <= 512.
  *   TILED    : halo-widened tiles, several steps per launch in registers.
  *   SPAN     : thousands of steps per launch; single-wave workgroups each
- *              own a slice in registers and swap edge sites with their two
- *              neighbours every steps_per_launch steps (default: the
- *              largest s with 3 max|c| s <= 256, 28 for D1Q7) through a
- *              library-owned exchange area; for lattices of about 2 to 2048
- *              slices of (256 - 2 H s) sites.
+ *              hold W = 64 max|c| sites in registers (max|c| per lane):
+ *              their own W - 2 max|c| s sites and a halo of max|c| s sites
+ *              per side, refreshed every s steps from the own sites the
+ *              other workgroups publish in a library-owned exchange area (a
+ *              halo may reach past the nearest neighbour).  s is the
+ *              steps_per_launch of kslb_set_kernel; by default the largest
+ *              with 3 W >= 8 max|c| s (24 for both schemes).  For lattices
+ *              of 2 to 2048 such slices.
  * All classes give bitwise identical results.                              */
 enum { KSLB_KERNEL_AUTO = 0, KSLB_KERNEL_PLAIN = 1, KSLB_KERNEL_RESIDENT = 2,
        KSLB_KERNEL_TILED = 3, KSLB_KERNEL_SPAN = 4 };

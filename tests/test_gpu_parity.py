@@ -593,11 +593,11 @@ def test_resolved_kernel_and_launch_shape():
     assert k["kernel"] == "span" and k["steps_per_launch"] % k["exchange_steps"] == 0
     assert k["exchange_steps"] >= 1 and k["workgroups"] >= 2 and k["lanes"] == 64
     n = 100_000
-    for prec, sites in (("fp64", 8), ("rho", 16)):
+    for prec, sites, s_default in (("fp64", 8, 64), ("rho", 16, 80)):
         lat = Lattice(n, 7, prec).set_physical(0.3, 2e-4, 1.0)
         k = lat.kernel()
         s = k["steps_per_launch"]
-        assert k["kernel"] == "tiled" and s % 8 == 0 and 2 * 3 * s <= 256 * sites // 8
+        assert k["kernel"] == "tiled" and s == s_default
         assert k["workgroups"] == -(-n // (256 * sites - 2 * 3 * s))
         # a tiled advance of s + 1 steps is two launches: same result as s + 1 plain steps
         lat.init_rho(ic(n, 0.3, 5)).advance(s + 1)

@@ -80,6 +80,7 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0, help="ensemble/serve: steps per launch (0 = default)")
     ap.add_argument("--segments", type=int, default=0, help="ensemble: instance tiles per window (0 = default)")
     ap.add_argument("--requests", type=int, default=2000, help="serve workload: requests")
+    ap.add_argument("--round-steps", type=int, default=0, help="serve workload: steps per scheduling round (0 = default)")
     ap.add_argument("--stats-t", type=int, default=1000, help="stats workload: final time T")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (reference kernel for HBM counters)")
@@ -226,7 +227,7 @@ def bench_serve(args):
     reqs = inputs.request_stream(args.requests, seed=3)
     init = [torch.tensor(inputs.random_modes_ic(r.n, r.n * dX, seed=r.seed % (1 << 63)), device=dev)
             for r in reqs]
-    srv = SolveServer(dX, dT, chunk=args.chunk or 32, device=dev)
+    srv = SolveServer(dX, dT, chunk=args.chunk or 64, round_steps=args.round_steps or 256, device=dev)
     warm = inputs.request_stream(8, seed=99, steps_lo=1000, steps_hi=1000)
     srv.serve(warm, [torch.tensor(inputs.random_modes_ic(r.n, r.n * dX, seed=5), device=dev) for r in warm],
               realtime=False)

@@ -120,7 +120,7 @@ class ServeStats:
 class SolveServer:
     """Slot pools per (scheme, storage precision) class and the serving loop."""
 
-    def __init__(self, dX: float, dT: float, slots: int = 256, capacity: int = 65536, chunk: int = 32,
+    def __init__(self, dX: float, dT: float, slots: int = 256, capacity: int = 65536, chunk: int = 64,
                  round_steps: int = 256, depth: int = 2, device="cuda:0",
                  classes: Sequence[Tuple[int, str]] = ((5, "fp64"), (5, "split"), (7, "fp64"), (7, "split")),
                  tau: Dict[int, float] = None):

@@ -145,6 +145,13 @@ struct Pol<Q, kFP64> {
         unroll<Q>([&](auto I) { reinterpret_cast<double*>(st)[I * p + j] = x.s[I]; });
     }
 
+    // as store, with non-temporal hints (streaming writes no later access in
+    // the same launch reads)
+    __device__ static __forceinline__ void store_nt(char* st, int64_t p, int64_t j, const Site& x)
+    {
+        unroll<Q>([&](auto I) { __builtin_nontemporal_store(x.s[I], reinterpret_cast<double*>(st) + I * p + j); });
+    }
+
     // B consecutive sites from j0 (j0 and p multiples of 2)
     template <int B>
     __device__ static __forceinline__ void load_vec(const char* st, int64_t p, int64_t j0, Site (&x)[B])
@@ -228,6 +235,11 @@ struct Pol<Q, kFP32> {
     __device__ static __forceinline__ void store(char* st, int64_t p, int64_t j, const Site& x)
     {
         unroll<Q>([&](auto I) { reinterpret_cast<float*>(st)[I * p + j] = x.s[I]; });
+    }
+
+    __device__ static __forceinline__ void store_nt(char* st, int64_t p, int64_t j, const Site& x)
+    {
+        unroll<Q>([&](auto I) { __builtin_nontemporal_store(x.s[I], reinterpret_cast<float*>(st) + I * p + j); });
     }
 
     // B consecutive sites from j0 (j0 and p multiples of 4)
@@ -348,6 +360,13 @@ struct Pol<Q, kSPLIT> {
         unroll<Q>([&](auto I) { nb[I * p + j] = x.n[I]; });
     }
 
+    __device__ static __forceinline__ void store_nt(char* st, int64_t p, int64_t j, const Site& x)
+    {
+        __builtin_nontemporal_store(x.rho, reinterpret_cast<double*>(st) + j);
+        float* nb = const_cast<float*>(nbase(st, p));
+        unroll<Q>([&](auto I) { __builtin_nontemporal_store(x.n[I], nb + I * p + j); });
+    }
+
     // B consecutive sites from j0 (j0 and p multiples of 4)
     template <int B>
     __device__ static __forceinline__ void load_vec(const char* st, int64_t p, int64_t j0, Site (&x)[B])
@@ -458,6 +477,10 @@ struct Pol<Q, kRHO> {
         reinterpret_cast<double*>(st)[j] = x.rho;
     }
 
+    // plain stores here: with one double per site the non-temporal hint
+    // measured slower (227 against 296 GLUPS, D1Q7 at N = 2^24)
+    __device__ static __forceinline__ void store_nt(char* st, int64_t p, int64_t j, const Site& x) { store(st, p, j, x); }
+
     template <int B>
     __device__ static __forceinline__ void load_vec(const char* st, int64_t, int64_t j0, Site (&x)[B])
     {
@@ -532,7 +555,10 @@ __global__ __launch_bounds__(256) void k_plain(const char* __restrict__ src, cha
     }
     typename PL::Site y;
     PL::update(g, y, cf);
-    PL::store(dst, p, j, y);
+    // non-temporal stores (except for the rho-only state): at N = 2^24, D1Q7
+    // FP64 streams 5.70 TB/s against 5.58 with plain stores, FP32 and split
+    // gain 4 %, D1Q5 3-4 % (bitwise the same state)
+    PL::store_nt(dst, p, j, y);
 }
 
 // Fixed ends (the Table 3 problem of section 3): sites 0 and n-1 and the

@@ -416,6 +416,34 @@ def test_mixed_ensemble_matches_single_lattices():
     assert a.status(9) == (40, False)
 
 
+def test_ensemble_per_instance_errors():
+    from paper_1711_03540_amd import KslbError
+    say("case ensemble per-instance errors")
+    ens = Ensemble([64, 128, 256], [5, 7, 7], ["fp64", "rho", "split"])
+    with pytest.raises(KslbError):
+        ens.set_physical(0.3, 2e-4, 1.1, idx=3)            # no such instance
+    with pytest.raises(KslbError):
+        ens.set_physical(0.3, 2e-4, 1.1, idx=1)            # rho-only storage needs tau = 1
+    with pytest.raises(KslbError):
+        ens.tau_of(1)                                      # nothing assigned yet
+    with pytest.raises(KslbError):
+        ens.init_rho(0, np.ones(64))                       # coefficients first
+    with pytest.raises(KslbError):
+        ens.set_tiling(16, 0, 0)                           # 16 sites per lane: rho-only throughout
+    ens.set_physical(0.3, 2e-4, 1.0)                       # every instance, one set per scheme
+    assert ens.tau_of(0) == ens.tau_of(1) == ens.tau_of(2) == 1.0
+    ens.set_physical(0.3, 2e-4, 1.1, idx=2)
+    assert ens.tau_of(2) == 1.1 and ens.tau_of(1) == 1.0
+    import torch
+    acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for i, n in enumerate((64, 128, 256)):
+        ens.init_rho(i, ic(n, 0.3, 3 + i))
+    with pytest.raises(KslbError):
+        ens.renormalize([1], [2], 1e-6, acc)               # not FP64, and sizes differ
+    ens.advance([10, 0, 5])
+    assert [ens.status(i)[0] for i in range(3)] == [10, 0, 5]
+
+
 def test_renormalize_pairs_of_both_schemes_in_one_call():
     # pairs given D1Q7 first: results land in each pair's own accumulator slot
     import torch

@@ -203,7 +203,8 @@ int span_plan(int64_t n, int q, int s)
 // owner's own sites at least 2/3 of the halo depth (3 W >= 8 H s).  Longer
 // intervals mean more, thinner owners whose halos gather from many slots;
 // measured on D1Q7 N = 4096: s = 21, 24, 28, 31 (63, 86, 171, 683 owners) ran
-// 26.7, 25.1, 26.1, 57 ms per 10^5 steps.
+// 26.7, 25.1, 26.1, 57 ms per 10^5 steps; s = 22, 23, 25, 26, 27 ran 26.7,
+// 26.3, 26.2, 26.4, 26.6 ms.
 int span_default_steps(int64_t n, int q)
 {
     const int64_t W = (int64_t)span_lanes() * span_sites_per_lane(q);

@@ -732,3 +732,29 @@ def test_served_stream_full_size_sampled():
         err = rel(stats.results[i].rho.cpu().numpy(), ref)
         say("  request %d (D1Q%d, N = %d, %d steps): rel err vs oracle %.3e" % (i, r.q, r.n, r.steps, err))
         assert err < 1e-10
+
+
+def test_tuner_choices_give_identical_results():
+    # the autotuner only times candidates: whatever it picks computes the same bits
+    from paper_1711_03540_amd import tune
+    say("case autotuner")
+    n, dX, dT = 1000, math.pi / 16, 1e-4
+    t = tune.tune_lattice(n, 7, "fp64", steps=200, cache=None, tile_steps=(0, 32), span_steps=(0,))
+    assert t["best"] in t["candidates"] and len(t["candidates"]) >= 2
+    rho0 = random_modes_ic(n, n * dX, seed=1)
+    lat = tune.apply_lattice(Lattice(n, 7, "fp64").set_physical(dX, dT, 0.0), t)
+    lat.init_rho(rho0).advance(300)
+    ref = Lattice(n, 7, "fp64").set_physical(dX, dT, 0.0).set_kernel("plain").init_rho(rho0).advance(300)
+    assert np.array_equal(lat.f(), ref.f())
+    sizes = [300, 700, 1500]
+    e = tune.tune_ensemble(sizes, 7, "fp64", steps=64, cache=None, sites_per_lane=(8,), chunks=(16, 32),
+                           segments=(1, 16))
+    assert e["best"] in e["candidates"] and len(e["candidates"]) == 4
+    a = tune.apply_ensemble(Ensemble(sizes, 7, "fp64").set_physical(dX, dT, 0.0), e)
+    b = Ensemble(sizes, 7, "fp64").set_physical(dX, dT, 0.0)
+    for ens in (a, b):
+        for i, m in enumerate(sizes):
+            ens.init_rho(i, random_modes_ic(m, m * dX, seed=1000 + i))
+        ens.advance([100, 100, 100])
+    for i in range(len(sizes)):
+        assert np.array_equal(a.rho(i), b.rho(i)), i

@@ -290,6 +290,14 @@ kslb_status kslb_ensemble_resize(kslb_ensemble* ens, int idx, int64_t n_sites);
  * host).                                                                    */
 kslb_status kslb_ensemble_init_rho(kslb_ensemble* ens, int idx, const double* rho, int on_device);
 
+/* Initialise every instance at once, as kslb_ensemble_init_rho for each:
+ * rho holds the densities of all instances back to back in instance order
+ * (sum over i of the current n_sites of instance i doubles), on the device
+ * (on_device = 1) or the host (then the call synchronises).  One launch per
+ * (scheme, storage) present instead of one per instance.  ESTATE unless
+ * every instance has its coefficients.                                     */
+kslb_status kslb_ensemble_init_rho_all(kslb_ensemble* ens, const double* rho, int on_device);
+
 /* Advance instance i by steps[i] >= 0 steps (asynchronous).  Launches one
  * kernel per chunk; instances with fewer steps left drop out of later
  * chunks.                                                                  */

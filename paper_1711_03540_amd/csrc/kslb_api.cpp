@@ -832,6 +832,12 @@ struct kslb_ensemble {
     uint64_t gkey[5] = {0, 0, 0, 0, 0};
     double* staging = nullptr;
     int64_t staging_n = 0;
+    // batched init: descriptor and coefficient table, its pinned staging
+    char* d_init = nullptr;
+    char* h_init = nullptr;
+    size_t init_cap = 0;
+    hipEvent_t init_ev = nullptr;
+    bool init_pending = false;
     // trajectory pairs: device table and its pinned staging
     char* d_pairs = nullptr;
     char* h_pairs = nullptr;
@@ -1340,6 +1346,97 @@ kslb_status kslb_ensemble_init_rho(kslb_ensemble* E, int idx, const double* rho,
     return KSLB_OK;
 }
 
+kslb_status kslb_ensemble_init_rho_all(kslb_ensemble* E, const double* rho, int on_device)
+{
+    if (!E) return fail(KSLB_EINVAL, "null ensemble");
+    if (!rho) return fail(KSLB_EINVAL, "rho must not be NULL");
+    for (int i = 0; i < E->count; i++)
+        if (E->cls[i] < 0) return fail(KSLB_ESTATE, "set the coefficients of instance %d before init", i);
+    DeviceGuard g(E->device);
+    // descriptors grouped by (scheme, storage), one launch per group
+    std::vector<int> order(E->count);
+    for (int i = 0; i < E->count; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return E->q[a] != E->q[b] ? E->q[a] < E->q[b] : E->prec[a] < E->prec[b];
+    });
+    std::vector<InitDesc> dv((size_t)E->count);
+    std::vector<int64_t> rho_off((size_t)E->count);
+    int64_t total = 0;
+    for (int i = 0; i < E->count; i++) {
+        rho_off[i] = total;
+        total += E->n[i];
+    }
+    for (int k = 0; k < E->count; k++) {
+        const int i = order[k];
+        dv[k] = InitDesc{(int64_t)E->off[i], rho_off[i], E->n[i], state_pitch(E->n[i]), E->cls[i], 0};
+    }
+    const size_t coef_at = sizeof(InitDesc) * dv.size();
+    const size_t bytes = coef_at + sizeof(Coef) * E->sets.size();
+    int e = 0;
+    if (E->init_pending) {   // the staging may still feed the previous upload
+        e = hipEventSynchronize(E->init_ev);
+        if (e) return hip_fail(e, "init table event");
+        E->init_pending = false;
+    }
+    if (E->init_cap < bytes) {
+        if (E->d_init) {
+            (void)hipStreamSynchronize(E->stream);
+            (void)hipFree(E->d_init);
+        }
+        if (E->h_init) (void)hipHostFree(E->h_init);
+        E->d_init = E->h_init = nullptr;
+        E->init_cap = 0;
+        void* dp = nullptr;
+        void* hp = nullptr;
+        if (hipMalloc(&dp, bytes)) return fail(KSLB_ENOMEM, "init table of %zu bytes", bytes);
+        if (hipHostMalloc(&hp, bytes, hipHostMallocDefault)) {
+            (void)hipFree(dp);
+            return fail(KSLB_ENOMEM, "pinned init table of %zu bytes", bytes);
+        }
+        E->d_init = (char*)dp;
+        E->h_init = (char*)hp;
+        E->init_cap = bytes;
+    }
+    if (!E->init_ev && hipEventCreateWithFlags(&E->init_ev, hipEventDisableTiming))
+        return fail(KSLB_EDEVICE, "event creation failed");
+    std::memcpy(E->h_init, dv.data(), coef_at);
+    for (size_t j = 0; j < E->sets.size(); j++)
+        std::memcpy(E->h_init + coef_at + j * sizeof(Coef), &E->sets[j].cf, sizeof(Coef));
+    const double* src = rho;
+    if (!on_device) {
+        if (auto st = ens_staging(E, total)) return st;
+        e = hipMemcpyAsync(E->staging, rho, sizeof(double) * (size_t)total, hipMemcpyHostToDevice, E->stream);
+        if (e) return hip_fail(e, "hipMemcpyAsync(rho)");
+        src = E->staging;
+    }
+    e = hipMemcpyAsync(E->d_init, E->h_init, bytes, hipMemcpyHostToDevice, E->stream);
+    if (!e) e = hipEventRecord(E->init_ev, E->stream);
+    if (e) return hip_fail(e, "init table upload");
+    E->init_pending = true;
+    const InitDesc* dd = reinterpret_cast<const InitDesc*>(E->d_init);
+    const Coef* dc = reinterpret_cast<const Coef*>(E->d_init + coef_at);
+    for (int k0 = 0; k0 < E->count;) {
+        const int i0 = order[k0];
+        int k1 = k0;
+        int64_t max_n = 0;
+        while (k1 < E->count && E->q[order[k1]] == E->q[i0] && E->prec[order[k1]] == E->prec[i0])
+            max_n = std::max(max_n, E->n[order[k1++]]);
+        e = launch_init_many(E->q[i0], E->prec[i0], E->buf, dd + k0, k1 - k0, max_n, dc, src, E->stream);
+        if (e) return hip_fail(e, "init kernel");
+        k0 = k1;
+    }
+    if (!on_device) {
+        e = hipStreamSynchronize(E->stream);
+        if (e) return hip_fail(e, "hipStreamSynchronize");
+    }
+    for (int i = 0; i < E->count; i++) {
+        E->cur[i] = 0;
+        E->have_state[i] = 1;
+        E->step[i] = 0;
+    }
+    return KSLB_OK;
+}
+
 kslb_status kslb_ensemble_advance(kslb_ensemble* E, const int64_t* steps)
 {
     if (!E) return fail(KSLB_EINVAL, "null ensemble");
@@ -1517,6 +1614,9 @@ kslb_status kslb_ensemble_destroy(kslb_ensemble* E)
     if (E->d_pairs) (void)hipFree(E->d_pairs);
     if (E->h_pairs) (void)hipHostFree(E->h_pairs);
     if (E->pairs_ev) (void)hipEventDestroy(E->pairs_ev);
+    if (E->d_init) (void)hipFree(E->d_init);
+    if (E->h_init) (void)hipHostFree(E->h_init);
+    if (E->init_ev) (void)hipEventDestroy(E->init_ev);
     delete E;
     return KSLB_OK;
 }

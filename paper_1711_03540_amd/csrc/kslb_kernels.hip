@@ -524,6 +524,19 @@ __global__ __launch_bounds__(256) void k_init(char* st, int64_t n, int64_t p, co
     if (j < n) PL::store(st, p, j, PL::equilibrium(rho0[j], cf));
 }
 
+// Equilibrium init of many lattices in one launch: block row y initialises
+// instance d[y] (its descriptor and coefficient set are uniform over the
+// block), block column x its sites [256 x, 256 x + 256).
+template <int Q, int P>
+__global__ __launch_bounds__(256) void k_init_many(char* base, const InitDesc* __restrict__ d,
+                                                   const Coef* __restrict__ coefs, const double* __restrict__ rho)
+{
+    using PL = Pol<Q, P>;
+    const InitDesc e = d[blockIdx.y];
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < e.n) PL::store(base + e.state_off, e.pitch, j, PL::equilibrium(rho[e.rho_off + j], coefs[e.coef]));
+}
+
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
 // Renumber them so that XCD x runs a contiguous run of logical blocks: the
 // halo lines two neighbouring tiles share then sit in one L2.  Used by the
@@ -1437,6 +1450,20 @@ int launch_init(int q, int prec, void* state, int64_t n, const double* rho0, con
     KSLB_DISPATCH_QP(q, prec, (k_init<Q_, P_><<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(
                                   (char*)state, n, state_pitch(n), rho0, cf)));
     return (int)hipGetLastError();
+}
+
+int launch_init_many(int q, int prec, char* base, const InitDesc* desc, int count, int64_t max_n,
+                     const Coef* coefs, const double* rho, void* stream)
+{
+    constexpr int kMaxRows = 65535;   // grid y limit
+    for (int y0 = 0; y0 < count; y0 += kMaxRows) {
+        const dim3 grid(blocks_for(max_n), (unsigned)std::min(kMaxRows, count - y0));
+        KSLB_DISPATCH_QP(q, prec, (k_init_many<Q_, P_><<<grid, 256, 0, (hipStream_t)stream>>>(
+                                      base, desc + y0, coefs, rho)));
+        int e = (int)hipGetLastError();
+        if (e) return e;
+    }
+    return 0;
 }
 
 int launch_plain(int q, int prec, const void* src, void* dst, int64_t n, const Coef& cf, void* stream)

@@ -91,6 +91,21 @@ class Ensemble:
             call("kslb_ensemble_init_rho", self._h, int(idx), _dptr(r), 0)
         return self
 
+    def init_rho_all(self, rho) -> "Ensemble":
+        """Initialise every instance from the densities of all instances back to
+        back in instance order (one launch per scheme and storage present)."""
+        import torch
+        total = int(np.sum(self.n))
+        if isinstance(rho, torch.Tensor) and rho.is_cuda:
+            r = rho.to(torch.float64).contiguous()
+            assert r.numel() == total
+            call("kslb_ensemble_init_rho_all", self._h, ctypes.c_void_p(r.data_ptr()), 1)
+        else:
+            r = np.ascontiguousarray(np.asarray(rho, dtype=np.float64))
+            assert r.size == total
+            call("kslb_ensemble_init_rho_all", self._h, _dptr(r), 0)
+        return self
+
     def advance(self, steps) -> "Ensemble":
         s = np.ascontiguousarray(np.broadcast_to(np.asarray(steps, dtype=np.int64), (self.count,)))
         call("kslb_ensemble_advance", self._h, _dptr(s))

@@ -444,6 +444,37 @@ def test_ensemble_per_instance_errors():
     assert [ens.status(i)[0] for i in range(3)] == [10, 0, 5]
 
 
+def test_ensemble_init_all_equals_per_instance_init():
+    # one launch per (scheme, storage) gives the states per-instance inits give,
+    # from device and from host densities, after a resize too
+    import torch
+    say("case ensemble init all")
+    sizes = [m[0] for m in MIXED]
+    qs, precs = [m[1] for m in MIXED], [m[2] for m in MIXED]
+
+    def make_one():
+        ens = Ensemble(sizes, qs, precs)
+        for i, m in enumerate(MIXED):
+            ens.set_physical(*MIXED_SETS[m[3]], idx=i)
+        return ens
+    a, b, c = make_one(), make_one(), make_one()
+    a.resize(3, 1234)
+    b.resize(3, 1234)
+    c.resize(3, 1234)
+    rhos = [ic(int(a.n[i]), MIXED_SETS[m[3]][0], 40 + i) for i, m in enumerate(MIXED)]
+    for i, r in enumerate(rhos):
+        a.init_rho(i, r)
+    b.init_rho_all(torch.tensor(np.concatenate(rhos), device="cuda"))
+    c.init_rho_all(np.concatenate(rhos))
+    steps = [m[4] for m in MIXED]
+    for e in (a, b, c):
+        e.advance(steps)
+    for i in range(len(MIXED)):
+        ra = a.rho(i)
+        assert np.array_equal(ra, b.rho(i)) and np.array_equal(ra, c.rho(i)), i
+        assert b.status(i) == (steps[i], False)
+
+
 def test_renormalize_pairs_of_both_schemes_in_one_call():
     # pairs given D1Q7 first: results land in each pair's own accumulator slot
     import torch
@@ -686,8 +717,7 @@ def test_ensemble_full_size_sampled():
     ens.set_tiling(0, 0, 0)
     tau = ens.tau
     rho0 = [random_modes_ic(int(n), n * dX, seed=1000 + i) for i, n in enumerate(sizes)]
-    for i, r in enumerate(rho0):
-        ens.init_rho(i, torch.tensor(r, device="cuda"))
+    ens.init_rho_all(torch.tensor(np.concatenate(rho0), device="cuda"))
     ens.advance(np.full(sizes.size, steps, dtype=np.int64))
     order = np.argsort(sizes, kind="stable")
     for i in (int(order[0]), int(order[sizes.size // 2]), int(order[-1])):

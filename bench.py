@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--segments", type=int, default=0, help="ensemble: instance tiles per window (0 = default)")
     ap.add_argument("--requests", type=int, default=2000, help="serve workload: requests")
     ap.add_argument("--round-steps", type=int, default=0, help="serve workload: steps per scheduling round (0 = default)")
+    ap.add_argument("--serve-fp32", default="fp32", choices=["fp32", "split"],
+                    help="serve workload: storage of the FP32 requests")
     ap.add_argument("--stats-t", type=int, default=1000, help="stats workload: final time T")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (reference kernel for HBM counters)")
@@ -220,7 +222,8 @@ def bench_ensemble(args):
 
 def bench_serve(args):
     """Served request stream: Poisson arrivals at 2000/s, D1Q5/D1Q7, N log-uniform in
-    [256, 65536], 10^3..10^5 steps, FP32 (split storage) or FP64, dX = pi/16, dT = 1e-4."""
+    [256, 65536], 10^3..10^5 steps, FP32 (FP32 storage by default, `--serve-fp32 split`
+    for the split storage) or FP64, dX = pi/16, dT = 1e-4."""
     import numpy as np
     import torch
 
@@ -232,12 +235,14 @@ def bench_serve(args):
     reqs = inputs.request_stream(args.requests, seed=3)
     init = [torch.tensor(inputs.random_modes_ic(r.n, r.n * dX, seed=r.seed % (1 << 63)), device=dev)
             for r in reqs]
-    srv = SolveServer(dX, dT, chunk=args.chunk or 64, round_steps=args.round_steps or 256, device=dev)
+    srv = SolveServer(dX, dT, chunk=args.chunk or 64, round_steps=args.round_steps or 256, device=dev,
+                      fp32_storage=args.serve_fp32)
     warm = inputs.request_stream(8, seed=99, steps_lo=1000, steps_hi=1000)
     srv.serve(warm, [torch.tensor(inputs.random_modes_ic(r.n, r.n * dX, seed=5), device=dev) for r in warm],
               realtime=False)
     st = srv.serve(reqs, init, realtime=True)
-    out = {"workload": "serve_%d_requests" % len(reqs), "offered_glups": float(
+    out = {"workload": "serve_%d_requests" % len(reqs), "fp32_requests_storage": args.serve_fp32,
+           "offered_glups": float(
         sum(r.n * r.steps for r in reqs) / reqs[-1].arrival / 1e9)}
     out.update(st.summary())
     print(json.dumps(out), flush=True)

@@ -1,8 +1,10 @@
 """Continuous-batching solve server for KS lattice Boltzmann requests.
 
 Each request asks for one periodic solve: scheme (D1Q5 or D1Q7), size N,
-number of steps, precision ("fp64", or "fp32", served in the split mode: rho
-in double, non-equilibrium part in single) and a seed for its initial density.
+number of steps, precision ("fp64", or "fp32": by default served in the FP32
+storage mode, populations in single precision with the density sum and the
+rho^2 term in double; optionally in the split mode, rho in double and the
+non-equilibrium part in single) and a seed for its initial density.
 Requests of one (scheme, precision) class share a slot pool: one libkslb
 ensemble whose instances are slots of a fixed capacity, on its own stream.
 
@@ -29,7 +31,6 @@ import numpy as np
 
 from .ensemble import Ensemble
 
-SERVE_PRECISION = {"fp64": "fp64", "fp32": "split"}
 
 
 @dataclass
@@ -122,11 +123,16 @@ class SolveServer:
 
     def __init__(self, dX: float, dT: float, slots: int = 256, capacity: int = 65536, chunk: int = 64,
                  round_steps: int = 256, depth: int = 2, device="cuda:0",
-                 classes: Sequence[Tuple[int, str]] = ((5, "fp64"), (5, "split"), (7, "fp64"), (7, "split")),
-                 tau: Dict[int, float] = None):
+                 classes: Optional[Sequence[Tuple[int, str]]] = None,
+                 tau: Dict[int, float] = None, fp32_storage: str = "fp32"):
+        if fp32_storage not in ("fp32", "split"):
+            raise ValueError("fp32 requests are served in the fp32 or split storage")
         self.dX, self.dT = dX, dT
         self.round_steps, self.depth = round_steps, depth
         self.device = device
+        self.storage = {"fp64": "fp64", "fp32": fp32_storage}     # request precision -> storage mode
+        if classes is None:
+            classes = [(q, p) for q in (5, 7) for p in ("fp64", fp32_storage)]
         tau = tau or {}
         self.pools = {(q, p): _Pool(q, p, dX, dT, slots, capacity, chunk, device, tau.get(q, 0.0))
                       for q, p in classes}
@@ -153,7 +159,7 @@ class SolveServer:
             while pending and requests[pending[0]].arrival <= now:
                 i = pending.popleft()
                 r = requests[i]
-                waiting[(r.q, SERVE_PRECISION[r.precision])].append(i)
+                waiting[(r.q, self.storage[r.precision])].append(i)
             q_max = max(q_max, sum(len(w) for w in waiting.values()))
             progressed = False
             for key, pool in self.pools.items():

@@ -502,7 +502,7 @@ def test_served_results_equal_solo_solves():
     say("case serving alone vs mix")
     import torch
     from paper_1711_03540_amd.inputs import request_stream
-    from paper_1711_03540_amd.serve import SERVE_PRECISION, SolveServer
+    from paper_1711_03540_amd.serve import SolveServer
     dX, dT = math.pi / 16, 1e-4
     reqs = request_stream(40, seed=17, rate=20000.0, n_lo=64, n_hi=6000, steps_lo=50, steps_hi=1500)
     init = [torch.tensor(random_modes_ic(r.n, r.n * dX, seed=r.seed % 1000003, n_modes=min(16, r.n // 2)),
@@ -511,20 +511,21 @@ def test_served_results_equal_solo_solves():
     # must not disturb the requests sharing its launches
     bad = 7
     init[bad] = init[bad] * 1e300
-    srv = SolveServer(dX, dT, slots=6, capacity=6000, chunk=24, round_steps=100)
-    stats = srv.serve(reqs, init, realtime=True)
-    summ = stats.summary()
-    say("serve summary", summ)
-    assert summ["completed"] == len(reqs)
-    assert summ["p99_ms"] >= summ["p50_ms"] > 0
-    assert stats.results[bad].finite is False
-    for i, r in enumerate(reqs):
-        if i == bad:
-            continue
-        assert stats.results[i].finite
-        lat = Lattice(r.n, r.q, SERVE_PRECISION[r.precision]).set_physical(dX, dT, 0.0).set_kernel("plain")
-        lat.init_rho(init[i]).advance(r.steps)
-        assert torch.equal(stats.results[i].rho, lat.read_rho()), i
+    for fp32_storage in ("fp32", "split"):
+        srv = SolveServer(dX, dT, slots=6, capacity=6000, chunk=24, round_steps=100, fp32_storage=fp32_storage)
+        stats = srv.serve(reqs, init, realtime=True)
+        summ = stats.summary()
+        say("serve summary (fp32 requests in %s storage)" % fp32_storage, summ)
+        assert summ["completed"] == len(reqs)
+        assert summ["p99_ms"] >= summ["p50_ms"] > 0
+        assert stats.results[bad].finite is False
+        for i, r in enumerate(reqs):
+            if i == bad:
+                continue
+            assert stats.results[i].finite
+            lat = Lattice(r.n, r.q, srv.storage[r.precision]).set_physical(dX, dT, 0.0).set_kernel("plain")
+            lat.init_rho(init[i]).advance(r.steps)
+            assert torch.equal(stats.results[i].rho, lat.read_rho()), (fp32_storage, i)
 
 
 @pytest.mark.parametrize("q", [5, 7])
@@ -739,7 +740,7 @@ def test_served_stream_full_size_sampled():
     # same solve run alone, and the smallest FP64 ones match the oracle
     import torch
     from paper_1711_03540_amd.inputs import request_stream
-    from paper_1711_03540_amd.serve import SERVE_PRECISION, SolveServer
+    from paper_1711_03540_amd.serve import SolveServer
     dX, dT = math.pi / 16, 1e-4
     reqs = request_stream(2000, seed=3)
     init = [torch.tensor(random_modes_ic(r.n, r.n * dX, seed=r.seed % (1 << 63)), device="cuda") for r in reqs]
@@ -750,7 +751,7 @@ def test_served_stream_full_size_sampled():
     assert all(r.finite for r in stats.results)
     for i in range(0, len(reqs), 211):
         r = reqs[i]
-        lat = Lattice(r.n, r.q, SERVE_PRECISION[r.precision]).set_physical(dX, dT, 0.0).set_kernel("auto")
+        lat = Lattice(r.n, r.q, srv.storage[r.precision]).set_physical(dX, dT, 0.0).set_kernel("auto")
         lat.init_rho(init[i]).advance(r.steps)
         assert torch.equal(stats.results[i].rho, lat.read_rho()), i
     small = sorted((r.n * r.steps, i) for i, r in enumerate(reqs) if r.precision == "fp64")[:3]

@@ -148,7 +148,9 @@ def cpu_baseline(w, tau):
 
 def bench_ensemble(args):
     """Ragged ensemble: D1Q7 instances, N log-uniform in [512, 8192], dX = pi/16, dT = 1e-4,
-    fitted tau, `--lb-steps` steps each; throughput against the plain one-step kernel."""
+    fitted tau, `--lb-steps` steps each; one solve = batched init from densities in
+    HBM, the steps, batched density readout into HBM; throughput against the plain
+    one-step kernel."""
     import numpy as np
     import torch
 
@@ -164,12 +166,14 @@ def bench_ensemble(args):
     rho0 = [torch.tensor(inputs.random_modes_ic(int(n), n * dX, seed=1000 + i), device=dev)
             for i, n in enumerate(sizes)]
     rho_all = torch.cat(rho0)          # every instance's density, resident in HBM
+    rho_out = torch.empty_like(rho_all)
     steps = np.full(len(sizes), args.lb_steps, dtype=np.int64)
     su = float(np.sum(sizes)) * args.lb_steps
 
     def solve():
         ens.init_rho_all(rho_all)       # one init launch for the whole ensemble
         ens.advance(steps)
+        ens.rho_all(rho_out)            # one readout launch, into HBM
 
     for _ in range(args.warmup):
         solve()
@@ -714,8 +718,15 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         pg = w.n * psteps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        hbm = pg * bytes_per_site_update(w.q, args.precision)     # GB/s, algorithmic bytes
         out["plain_kernel"] = {"glups": pg, "timed_lb_steps": psteps, "speedup": value / pg,
-                               "bitwise_identical_state_after_%d_steps" % chk: same}
+                               "bitwise_identical_state_after_%d_steps" % chk: same,
+                               "hbm_gb_s": hbm, "hbm_frac": hbm / PEAK_HBM_GBS}
+    # the one-step HBM roofline (2 Q b bytes per site update at 8 TB/s) that
+    # temporal blocking lifts the solve above
+    s1 = PEAK_HBM_GBS / bytes_per_site_update(w.q, args.precision)
+    out["s1_hbm_roofline_glups"] = s1
+    out["vs_s1_hbm_roofline"] = value / s1
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, tau)

@@ -305,6 +305,12 @@ kslb_status kslb_ensemble_advance(kslb_ensemble* ens, const int64_t* steps);
 
 kslb_status kslb_ensemble_read_rho(kslb_ensemble* ens, int idx, double* out, int on_device);
 
+/* The densities of every instance back to back in instance order (sum over
+ * i of the current n_sites of instance i doubles), into device memory
+ * (on_device = 1, enqueued) or host memory (synchronises).  One launch per
+ * (scheme, storage) present.  ESTATE unless every instance has a state.    */
+kslb_status kslb_ensemble_read_rho_all(kslb_ensemble* ens, double* out, int on_device);
+
 /* Benettin renormalisation of trajectory pairs, a tool for the largest
  * Lyapunov exponent of the scheme's dynamics (the chaotic dynamics the paper
  * names as its next subject, section 4).  For each pair p of instances

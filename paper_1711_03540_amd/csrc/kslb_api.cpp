@@ -832,12 +832,16 @@ struct kslb_ensemble {
     uint64_t gkey[5] = {0, 0, 0, 0, 0};
     double* staging = nullptr;
     int64_t staging_n = 0;
-    // batched init: descriptor and coefficient table, its pinned staging
-    char* d_init = nullptr;
-    char* h_init = nullptr;
-    size_t init_cap = 0;
-    hipEvent_t init_ev = nullptr;
-    bool init_pending = false;
+    // batched init and readout: descriptor (and coefficient) tables, each
+    // with its pinned staging and the event of its last upload
+    struct Table {
+        char* d = nullptr;
+        char* h = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    };
+    Table init_tab, read_tab;
     // trajectory pairs: device table and its pinned staging
     char* d_pairs = nullptr;
     char* h_pairs = nullptr;
@@ -1196,6 +1200,94 @@ kslb_status ens_replay_pairs(kslb_ensemble* E, const std::vector<int>& adv, int6
     return KSLB_OK;
 }
 
+// Stage `bytes` of host data into table t and enqueue its upload on the
+// ensemble's stream; *dev receives the device copy.  The pinned staging is
+// rewritten only after its previous upload has completed.
+kslb_status ens_upload(kslb_ensemble* E, kslb_ensemble::Table& t, const void* data, size_t bytes, char** dev)
+{
+    int e = 0;
+    if (t.pending) {
+        e = hipEventSynchronize(t.ev);
+        if (e) return hip_fail(e, "table upload event");
+        t.pending = false;
+    }
+    if (t.cap < bytes) {
+        if (t.d) {
+            (void)hipStreamSynchronize(E->stream);
+            (void)hipFree(t.d);
+        }
+        if (t.h) (void)hipHostFree(t.h);
+        t.d = t.h = nullptr;
+        t.cap = 0;
+        void* dp = nullptr;
+        void* hp = nullptr;
+        if (hipMalloc(&dp, bytes)) return fail(KSLB_ENOMEM, "table of %zu bytes", bytes);
+        if (hipHostMalloc(&hp, bytes, hipHostMallocDefault)) {
+            (void)hipFree(dp);
+            return fail(KSLB_ENOMEM, "pinned table of %zu bytes", bytes);
+        }
+        t.d = (char*)dp;
+        t.h = (char*)hp;
+        t.cap = bytes;
+    }
+    if (!t.ev && hipEventCreateWithFlags(&t.ev, hipEventDisableTiming))
+        return fail(KSLB_EDEVICE, "event creation failed");
+    std::memcpy(t.h, data, bytes);
+    e = hipMemcpyAsync(t.d, t.h, bytes, hipMemcpyHostToDevice, E->stream);
+    if (!e) e = hipEventRecord(t.ev, E->stream);
+    if (e) return hip_fail(e, "table upload");
+    t.pending = true;
+    *dev = t.d;
+    return KSLB_OK;
+}
+
+void ens_table_free(kslb_ensemble::Table& t)
+{
+    if (t.d) (void)hipFree(t.d);
+    if (t.h) (void)hipHostFree(t.h);
+    if (t.ev) (void)hipEventDestroy(t.ev);
+    t = kslb_ensemble::Table{};
+}
+
+// One launch's share of a batched init or readout: table rows [begin, end),
+// all of one scheme and storage, sizes up to max_n.
+struct InstGroup {
+    int begin, end, q, prec;
+    int64_t max_n;
+};
+
+// Instances in (scheme, storage) order with their packed-density offsets
+// (instance order) and the state copy copy_of(i); *groups receives the runs.
+template <class CopyOf>
+std::vector<InstDesc> ens_inst_table(const kslb_ensemble* E, CopyOf copy_of, int64_t* total,
+                                     std::vector<InstGroup>* groups)
+{
+    std::vector<int> order(E->count);
+    for (int i = 0; i < E->count; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return E->q[a] != E->q[b] ? E->q[a] < E->q[b] : E->prec[a] < E->prec[b];
+    });
+    std::vector<int64_t> rho_off((size_t)E->count);
+    int64_t pos = 0;
+    for (int i = 0; i < E->count; i++) {
+        rho_off[i] = pos;
+        pos += E->n[i];
+    }
+    *total = pos;
+    std::vector<InstDesc> dv((size_t)E->count);
+    groups->clear();
+    for (int k = 0; k < E->count; k++) {
+        const int i = order[k];
+        dv[k] = InstDesc{(int64_t)(E->off[i] + (size_t)copy_of(i) * E->copy[i]), rho_off[i], E->n[i],
+                         state_pitch(E->n[i]), std::max(E->cls[i], 0), 0};
+        if (groups->empty() || groups->back().q != E->q[i] || groups->back().prec != E->prec[i])
+            groups->push_back(InstGroup{k, k, E->q[i], E->prec[i], 0});
+        groups->back().end = k + 1;
+        groups->back().max_n = std::max(groups->back().max_n, E->n[i]);
+    }
+    return dv;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1353,80 +1445,33 @@ kslb_status kslb_ensemble_init_rho_all(kslb_ensemble* E, const double* rho, int 
     for (int i = 0; i < E->count; i++)
         if (E->cls[i] < 0) return fail(KSLB_ESTATE, "set the coefficients of instance %d before init", i);
     DeviceGuard g(E->device);
-    // descriptors grouped by (scheme, storage), one launch per group
-    std::vector<int> order(E->count);
-    for (int i = 0; i < E->count; i++) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return E->q[a] != E->q[b] ? E->q[a] < E->q[b] : E->prec[a] < E->prec[b];
-    });
-    std::vector<InitDesc> dv((size_t)E->count);
-    std::vector<int64_t> rho_off((size_t)E->count);
     int64_t total = 0;
-    for (int i = 0; i < E->count; i++) {
-        rho_off[i] = total;
-        total += E->n[i];
-    }
-    for (int k = 0; k < E->count; k++) {
-        const int i = order[k];
-        dv[k] = InitDesc{(int64_t)E->off[i], rho_off[i], E->n[i], state_pitch(E->n[i]), E->cls[i], 0};
-    }
-    const size_t coef_at = sizeof(InitDesc) * dv.size();
-    const size_t bytes = coef_at + sizeof(Coef) * E->sets.size();
-    int e = 0;
-    if (E->init_pending) {   // the staging may still feed the previous upload
-        e = hipEventSynchronize(E->init_ev);
-        if (e) return hip_fail(e, "init table event");
-        E->init_pending = false;
-    }
-    if (E->init_cap < bytes) {
-        if (E->d_init) {
-            (void)hipStreamSynchronize(E->stream);
-            (void)hipFree(E->d_init);
-        }
-        if (E->h_init) (void)hipHostFree(E->h_init);
-        E->d_init = E->h_init = nullptr;
-        E->init_cap = 0;
-        void* dp = nullptr;
-        void* hp = nullptr;
-        if (hipMalloc(&dp, bytes)) return fail(KSLB_ENOMEM, "init table of %zu bytes", bytes);
-        if (hipHostMalloc(&hp, bytes, hipHostMallocDefault)) {
-            (void)hipFree(dp);
-            return fail(KSLB_ENOMEM, "pinned init table of %zu bytes", bytes);
-        }
-        E->d_init = (char*)dp;
-        E->h_init = (char*)hp;
-        E->init_cap = bytes;
-    }
-    if (!E->init_ev && hipEventCreateWithFlags(&E->init_ev, hipEventDisableTiming))
-        return fail(KSLB_EDEVICE, "event creation failed");
-    std::memcpy(E->h_init, dv.data(), coef_at);
+    std::vector<InstGroup> groups;
+    const std::vector<InstDesc> dv = ens_inst_table(E, [](int) { return 0; }, &total, &groups);
+    // one upload: the instance table, then the coefficient sets
+    const size_t coef_at = sizeof(InstDesc) * dv.size();
+    std::vector<char> blob(coef_at + sizeof(Coef) * E->sets.size());
+    std::memcpy(blob.data(), dv.data(), coef_at);
     for (size_t j = 0; j < E->sets.size(); j++)
-        std::memcpy(E->h_init + coef_at + j * sizeof(Coef), &E->sets[j].cf, sizeof(Coef));
+        std::memcpy(blob.data() + coef_at + j * sizeof(Coef), &E->sets[j].cf, sizeof(Coef));
     const double* src = rho;
     if (!on_device) {
         if (auto st = ens_staging(E, total)) return st;
-        e = hipMemcpyAsync(E->staging, rho, sizeof(double) * (size_t)total, hipMemcpyHostToDevice, E->stream);
+        int e = hipMemcpyAsync(E->staging, rho, sizeof(double) * (size_t)total, hipMemcpyHostToDevice, E->stream);
         if (e) return hip_fail(e, "hipMemcpyAsync(rho)");
         src = E->staging;
     }
-    e = hipMemcpyAsync(E->d_init, E->h_init, bytes, hipMemcpyHostToDevice, E->stream);
-    if (!e) e = hipEventRecord(E->init_ev, E->stream);
-    if (e) return hip_fail(e, "init table upload");
-    E->init_pending = true;
-    const InitDesc* dd = reinterpret_cast<const InitDesc*>(E->d_init);
-    const Coef* dc = reinterpret_cast<const Coef*>(E->d_init + coef_at);
-    for (int k0 = 0; k0 < E->count;) {
-        const int i0 = order[k0];
-        int k1 = k0;
-        int64_t max_n = 0;
-        while (k1 < E->count && E->q[order[k1]] == E->q[i0] && E->prec[order[k1]] == E->prec[i0])
-            max_n = std::max(max_n, E->n[order[k1++]]);
-        e = launch_init_many(E->q[i0], E->prec[i0], E->buf, dd + k0, k1 - k0, max_n, dc, src, E->stream);
+    char* dev = nullptr;
+    if (auto st = ens_upload(E, E->init_tab, blob.data(), blob.size(), &dev)) return st;
+    const InstDesc* dd = reinterpret_cast<const InstDesc*>(dev);
+    const Coef* dc = reinterpret_cast<const Coef*>(dev + coef_at);
+    for (const InstGroup& gr : groups) {
+        int e = launch_init_many(gr.q, gr.prec, E->buf, dd + gr.begin, gr.end - gr.begin, gr.max_n, dc, src,
+                                 E->stream);
         if (e) return hip_fail(e, "init kernel");
-        k0 = k1;
     }
     if (!on_device) {
-        e = hipStreamSynchronize(E->stream);
+        int e = hipStreamSynchronize(E->stream);
         if (e) return hip_fail(e, "hipStreamSynchronize");
     }
     for (int i = 0; i < E->count; i++) {
@@ -1501,6 +1546,36 @@ kslb_status kslb_ensemble_read_rho(kslb_ensemble* E, int idx, double* out, int o
     if (e) return hip_fail(e, "readout kernel");
     if (!on_device) {
         e = hipMemcpyAsync(out, dst, sizeof(double) * (size_t)E->n[idx], hipMemcpyDeviceToHost, E->stream);
+        if (!e) e = hipStreamSynchronize(E->stream);
+        if (e) return hip_fail(e, "readout copy");
+    }
+    return KSLB_OK;
+}
+
+kslb_status kslb_ensemble_read_rho_all(kslb_ensemble* E, double* out, int on_device)
+{
+    if (!E) return fail(KSLB_EINVAL, "null ensemble");
+    if (!out) return fail(KSLB_EINVAL, "out must not be NULL");
+    for (int i = 0; i < E->count; i++)
+        if (!E->have_state[i]) return fail(KSLB_ESTATE, "instance %d has no state", i);
+    DeviceGuard g(E->device);
+    int64_t total = 0;
+    std::vector<InstGroup> groups;
+    const std::vector<InstDesc> dv = ens_inst_table(E, [&](int i) { return E->cur[i]; }, &total, &groups);
+    double* dst = out;
+    if (!on_device) {
+        if (auto st = ens_staging(E, total)) return st;
+        dst = E->staging;
+    }
+    char* dev = nullptr;
+    if (auto st = ens_upload(E, E->read_tab, dv.data(), sizeof(InstDesc) * dv.size(), &dev)) return st;
+    const InstDesc* dd = reinterpret_cast<const InstDesc*>(dev);
+    for (const InstGroup& gr : groups) {
+        int e = launch_read_many(gr.q, gr.prec, E->buf, dd + gr.begin, gr.end - gr.begin, gr.max_n, dst, E->stream);
+        if (e) return hip_fail(e, "readout kernel");
+    }
+    if (!on_device) {
+        int e = hipMemcpyAsync(out, dst, sizeof(double) * (size_t)total, hipMemcpyDeviceToHost, E->stream);
         if (!e) e = hipStreamSynchronize(E->stream);
         if (e) return hip_fail(e, "readout copy");
     }
@@ -1614,9 +1689,8 @@ kslb_status kslb_ensemble_destroy(kslb_ensemble* E)
     if (E->d_pairs) (void)hipFree(E->d_pairs);
     if (E->h_pairs) (void)hipHostFree(E->h_pairs);
     if (E->pairs_ev) (void)hipEventDestroy(E->pairs_ev);
-    if (E->d_init) (void)hipFree(E->d_init);
-    if (E->h_init) (void)hipHostFree(E->h_init);
-    if (E->init_ev) (void)hipEventDestroy(E->init_ev);
+    ens_table_free(E->init_tab);
+    ens_table_free(E->read_tab);
     delete E;
     return KSLB_OK;
 }

@@ -116,16 +116,18 @@ struct SegDesc {
     int32_t lane_lo;    // first lane of the segment
     int32_t valid;      // sites written back, from slot H * steps on
 };
-// Equilibrium init of one ensemble instance: byte offset of its state copy
-// from the ensemble base, offset of its densities in the input array, sites,
-// row pitch and coefficient set.
-struct InitDesc {
+// One ensemble instance in a batched init or readout: byte offset of its
+// state copy from the ensemble base, offset of its densities in the packed
+// density array, sites, row pitch and coefficient set (init only).
+struct InstDesc {
     int64_t state_off, rho_off, n, pitch;
     int32_t coef, pad;
 };
 // Instances desc[0 .. count) of one scheme and storage; max_n bounds their sizes.
-int launch_init_many(int q, int prec, char* base, const InitDesc* desc, int count, int64_t max_n,
+int launch_init_many(int q, int prec, char* base, const InstDesc* desc, int count, int64_t max_n,
                      const Coef* coefs, const double* rho, void* stream);
+int launch_read_many(int q, int prec, const char* base, const InstDesc* desc, int count, int64_t max_n,
+                     double* rho, void* stream);
 
 // coefs: device table of coefficient sets, indexed by WinHdr::coef
 int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegDesc* seg, int nwin,

@@ -528,11 +528,11 @@ __global__ __launch_bounds__(256) void k_init(char* st, int64_t n, int64_t p, co
 // instance d[y] (its descriptor and coefficient set are uniform over the
 // block), block column x its sites [256 x, 256 x + 256).
 template <int Q, int P>
-__global__ __launch_bounds__(256) void k_init_many(char* base, const InitDesc* __restrict__ d,
+__global__ __launch_bounds__(256) void k_init_many(char* base, const InstDesc* __restrict__ d,
                                                    const Coef* __restrict__ coefs, const double* __restrict__ rho)
 {
     using PL = Pol<Q, P>;
-    const InitDesc e = d[blockIdx.y];
+    const InstDesc e = d[blockIdx.y];
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j < e.n) PL::store(base + e.state_off, e.pitch, j, PL::equilibrium(rho[e.rho_off + j], coefs[e.coef]));
 }
@@ -1298,6 +1298,17 @@ __global__ __launch_bounds__(256) void k_read_rho(const char* __restrict__ st, i
     if (j < n) out[j] = PL::density(PL::load(st, p, j));
 }
 
+// Density readout of many lattices in one launch (block row y: instance d[y]).
+template <int Q, int P>
+__global__ __launch_bounds__(256) void k_read_many(const char* __restrict__ base, const InstDesc* __restrict__ d,
+                                                   double* __restrict__ rho)
+{
+    using PL = Pol<Q, P>;
+    const InstDesc e = d[blockIdx.y];
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < e.n) rho[e.rho_off + j] = PL::density(PL::load(base + e.state_off, e.pitch, j));
+}
+
 // out is dense Q x n
 template <int Q, int P>
 __global__ __launch_bounds__(256) void k_read_f(const char* __restrict__ st, int64_t n, int64_t p,
@@ -1452,7 +1463,21 @@ int launch_init(int q, int prec, void* state, int64_t n, const double* rho0, con
     return (int)hipGetLastError();
 }
 
-int launch_init_many(int q, int prec, char* base, const InitDesc* desc, int count, int64_t max_n,
+int launch_read_many(int q, int prec, const char* base, const InstDesc* desc, int count, int64_t max_n,
+                     double* rho, void* stream)
+{
+    constexpr int kMaxRows = 65535;   // grid y limit
+    for (int y0 = 0; y0 < count; y0 += kMaxRows) {
+        const dim3 grid(blocks_for(max_n), (unsigned)std::min(kMaxRows, count - y0));
+        KSLB_DISPATCH_QP(q, prec, (k_read_many<Q_, P_><<<grid, 256, 0, (hipStream_t)stream>>>(
+                                      base, desc + y0, rho)));
+        int e = (int)hipGetLastError();
+        if (e) return e;
+    }
+    return 0;
+}
+
+int launch_init_many(int q, int prec, char* base, const InstDesc* desc, int count, int64_t max_n,
                      const Coef* coefs, const double* rho, void* stream)
 {
     constexpr int kMaxRows = 65535;   // grid y limit

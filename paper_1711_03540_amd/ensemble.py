@@ -120,6 +120,19 @@ class Ensemble:
         call("kslb_ensemble_read_rho", self._h, int(idx), ctypes.c_void_p(out.data_ptr()), 1)
         return out
 
+    def rho_all(self, out=None):
+        """Densities of every instance back to back in instance order: into the
+        float64 device tensor `out` (enqueued), or returned as a host array."""
+        import torch
+        total = int(np.sum(self.n))
+        if out is not None:
+            assert out.is_cuda and out.numel() >= total and out.dtype == torch.float64 and out.is_contiguous()
+            call("kslb_ensemble_read_rho_all", self._h, ctypes.c_void_p(out.data_ptr()), 1)
+            return out
+        host = np.zeros(total)
+        call("kslb_ensemble_read_rho_all", self._h, _dptr(host), 0)
+        return host
+
     def status(self, idx: int):
         s, f = ctypes.c_int64(), ctypes.c_int()
         call("kslb_ensemble_status", self._h, int(idx), ctypes.byref(s), ctypes.byref(f))

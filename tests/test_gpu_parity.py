@@ -446,7 +446,8 @@ def test_ensemble_per_instance_errors():
 
 def test_ensemble_init_all_equals_per_instance_init():
     # one launch per (scheme, storage) gives the states per-instance inits give,
-    # from device and from host densities, after a resize too
+    # from device and from host densities, after a resize too; the batched
+    # readout returns the per-instance densities
     import torch
     say("case ensemble init all")
     sizes = [m[0] for m in MIXED]
@@ -473,6 +474,12 @@ def test_ensemble_init_all_equals_per_instance_init():
         ra = a.rho(i)
         assert np.array_equal(ra, b.rho(i)) and np.array_equal(ra, c.rho(i)), i
         assert b.status(i) == (steps[i], False)
+    # batched readout, to the device and to the host: the per-instance densities back to back
+    want = np.concatenate([a.rho(i) for i in range(len(MIXED))])
+    dev = torch.full((want.size + 5,), -1.0, dtype=torch.float64, device="cuda")
+    b.rho_all(dev)
+    assert np.array_equal(dev[: want.size].cpu().numpy(), want) and float(dev[-1]) == -1.0
+    assert np.array_equal(c.rho_all(), want)
 
 
 def test_renormalize_pairs_of_both_schemes_in_one_call():

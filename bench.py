@@ -61,6 +61,7 @@ WORKLOADS = {
     "stats": (None, None),
     "taumin": (None, None),
     "lyapunov": (None, None),
+    "profiles": (None, None),
 }
 
 
@@ -325,6 +326,46 @@ def bench_table3(args):
     print(json.dumps({"workload": "table3_fixed_ends", "T_end": T_end, "runs": runs, "matched": matched}), flush=True)
 
 
+def bench_profiles(args):
+    """The Table 3 travelling wave at dX = 0.2 for both schemes (the comparison of
+    the paper's Fig. 4): density profiles at several times against the analytic
+    solution, with G and the largest pointwise error.  dT is each scheme's
+    matched-accuracy step of the Table 3 study (D1Q5 1e-4, D1Q7 2e-4); tau is
+    the paper's fit, raised by the stability guard where needed."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03540_amd import inputs
+    from paper_1711_03540_amd.lattice import Lattice
+
+    dev = torch.device("cuda:0")
+    dX = 0.2
+    n = inputs.table3_sites(dX)
+    X = np.arange(n) * dX
+    lo, hi = inputs.table3_ends()
+    times = [0.5, 1.0, 2.0, 4.0, 8.0]
+    sample = list(range(0, n, 25))        # X = 0, 5, ..., 60
+    out = {"workload": "profiles_table3_dx0.2", "dX": dX, "times": times, "X": [float(X[j]) for j in sample],
+           "exact": {str(t): [float(v) for v in inputs.table3_profile(X[sample], t)] for t in times}, "schemes": {}}
+    for q, dT in ((5, 1e-4), (7, 2e-4)):
+        lat = Lattice(n, q, "fp64", device=dev).set_physical(dX, dT, 0.0, guard="raise", rho_max=4.5)
+        lat.set_fixed_ends(lo, hi).init_rho(torch.tensor(inputs.table3_profile(X, 0.0), device=dev))
+        done, rows = 0, []
+        for t in times:
+            steps = int(round(t / dT))
+            lat.advance(steps - done)
+            done = steps
+            rho = lat.rho()
+            exact = inputs.table3_profile(X, t)
+            rows.append({"T": t, "steps": steps,
+                         "G": float(np.sum(np.abs(rho - exact)) / np.sum(np.abs(exact))),
+                         "max_abs_err": float(np.max(np.abs(rho - exact))),
+                         "rho": [float(rho[j]) for j in sample]})
+        out["schemes"]["D1Q%d" % q] = {"dT": dT, "tau": lat.coefficients()["tau"], "kernel": lat.kernel()["kernel"],
+                                       "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def bench_taumin(args):
     """Minimum stable tau on the Table 3 problem (the left panels of the
     paper's Figs. 1-3, section 3): for dX in {0.2, 0.1, 0.05}, both schemes and
@@ -579,6 +620,9 @@ def main():
         return
     if args.workload == "stats":
         bench_stats(args)
+        return
+    if args.workload == "profiles":
+        bench_profiles(args)
         return
     if args.workload == "taumin":
         bench_taumin(args)

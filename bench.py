@@ -62,6 +62,7 @@ WORKLOADS = {
     "taumin": (None, None),
     "lyapunov": (None, None),
     "profiles": (None, None),
+    "lyapunov_spectrum": (None, None),
 }
 
 
@@ -534,6 +535,62 @@ def bench_lyapunov(args):
                       "glups_including_readouts": site_updates / wall / 1e9}), flush=True)
 
 
+def bench_lyapunov_spectrum(args):
+    """The 8 leading Lyapunov exponents of the scheme's KS dynamics for L = N dX,
+    N in {112, 256, 512} (L about 22, 50, 100): D1Q7 FP64, dX = pi/16, dT = 1e-4,
+    fitted tau; per L one reference trajectory (16 random modes of amplitude 0.1,
+    seed 300 + L-index) and 8 perturbed copies (1e-8 times seeded fields), all in
+    one ensemble; every unit of time the perturbations are orthonormalised (QR)
+    and rescaled to delta = 1e-8 on the GPU; lambda_m = sum of ln(R_mm / delta)
+    over T in [T0, T] / (T - T0), T0 = 200, T = --stats-t (1000).  Also the
+    Kaplan-Yorke dimension where the 8 exponents bracket it."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03540_amd.ensemble import Ensemble
+    from paper_1711_03540_amd.inputs import random_modes_ic
+
+    dev = torch.device("cuda:0")
+    sizes_L = [112, 256, 512]
+    k = 8
+    dX, dT = math.pi / 16, 1e-4
+    per = int(round(1.0 / dT))
+    T0, T = 200, args.stats_t
+    delta = 1e-8
+    sizes, ref, pert = [], [], []
+    for li, n in enumerate(sizes_L):
+        ref.append(len(sizes)); sizes.append(n)
+        pert.append(list(range(len(sizes), len(sizes) + k))); sizes += [n] * k
+    ens = Ensemble(sizes, 7, "fp64", device=dev).set_physical(dX, dT, 0.0)
+    for li, n in enumerate(sizes_L):
+        rho0 = random_modes_ic(n, n * dX, seed=300 + li)
+        ens.init_rho(ref[li], rho0)
+        for m in range(k):
+            ens.init_rho(pert[li][m], rho0 + 1e-8 * random_modes_ic(n, n * dX, seed=7000 + 10 * li + m, amplitude=1.0))
+    acc = torch.zeros(len(sizes_L) * k, dtype=torch.float64, device=dev)
+    acc_T0 = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(1, T + 1):
+        ens.advance(per)
+        ens.orthonormalize(ref, pert, delta, acc)
+        if t == T0:
+            acc_T0 = acc.clone()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lam = ((acc - acc_T0) / (T - T0)).cpu().numpy().reshape(len(sizes_L), k)
+    out = []
+    for li, n in enumerate(sizes_L):
+        l = lam[li]
+        c = np.cumsum(l)
+        j = int(np.max(np.nonzero(c >= 0)[0])) + 1 if c[0] >= 0 else 0
+        dky = float(j + c[j - 1] / abs(l[j])) if 0 < j < k else None
+        out.append({"N": n, "L": n * dX, "lambda": l.tolist(), "kaplan_yorke_dimension": dky})
+        print(json.dumps(out[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "lyapunov_spectrum_d1q7", "dX": dX, "dT": dT, "tau": ens.tau, "T0": T0, "T": T,
+                      "delta": delta, "k": k, "results": out, "wall_s": wall}), flush=True)
+
+
 def bench_stats(args):
     """Reduced-precision error on long-time statistics: the D1Q7 N = 4096 lattice
     (L = 256 pi, dT = 1e-4, fitted tau, 16 random modes) run to T = 1000 in FP64,
@@ -623,6 +680,9 @@ def main():
         return
     if args.workload == "profiles":
         bench_profiles(args)
+        return
+    if args.workload == "lyapunov_spectrum":
+        bench_lyapunov_spectrum(args)
         return
     if args.workload == "taumin":
         bench_taumin(args)

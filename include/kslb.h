@@ -325,6 +325,21 @@ kslb_status kslb_ensemble_read_rho_all(kslb_ensemble* ens, double* out, int on_d
 kslb_status kslb_ensemble_renormalize(kslb_ensemble* ens, int npairs, const int* ref, const int* pert,
                                       double delta, double* log_accum);
 
+/* Lyapunov spectrum: renormalisation of ngroups groups, each a reference
+ * trajectory ref[g] and k perturbed copies pert[g k + m], m = 0..k-1
+ * (1 <= k <= 8; host arrays of FP64 instances of one scheme with equal
+ * sites and steps, no instance used twice).  With v_m = S_pert[m] - S_ref
+ * over the Q x n stored populations, V = U R (U orthonormal, R upper
+ * triangular with positive diagonal, from the Cholesky factor of the Gram
+ * matrix of the v_m), S_pert[m] <- S_ref + delta u_m and
+ * log_accum[g k + m] += ln(R_mm / delta) (device array of ngroups k doubles,
+ * owned by the caller, which zeroes it first).  The time averages of these
+ * sums are the k leading Lyapunov exponents (Benettin et al. 1980, with a QR
+ * step in place of Gram-Schmidt).  A group whose R is not positive definite
+ * is left unchanged and gets NaN.  Enqueued on the ensemble's stream.      */
+kslb_status kslb_ensemble_orthonormalize(kslb_ensemble* ens, int ngroups, int k, const int* ref, const int* pert,
+                                         double delta, double* log_accum);
+
 /* Step counter and non-finite flag of instance idx (synchronises). */
 kslb_status kslb_ensemble_status(kslb_ensemble* ens, int idx, int64_t* step, int* nonfinite);
 

@@ -74,6 +74,7 @@ SIGNATURES = {
     "kslb_ensemble_init_rho": (_st, [_vp, _i, _vp, _i]),
     "kslb_ensemble_init_rho_all": (_st, [_vp, _vp, _i]),
     "kslb_ensemble_read_rho_all": (_st, [_vp, _vp, _i]),
+    "kslb_ensemble_orthonormalize": (_st, [_vp, _i, _i, _vp, _vp, _d, _vp]),
     "kslb_ensemble_advance": (_st, [_vp, _vp]),
     "kslb_ensemble_read_rho": (_st, [_vp, _i, _vp, _i]),
     "kslb_ensemble_status": (_st, [_vp, _i, _vp, _vp]),

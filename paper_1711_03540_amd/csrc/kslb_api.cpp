@@ -841,7 +841,7 @@ struct kslb_ensemble {
         hipEvent_t ev = nullptr;
         bool pending = false;
     };
-    Table init_tab, read_tab;
+    Table init_tab, read_tab, group_tab;
     // trajectory pairs: device table and its pinned staging
     char* d_pairs = nullptr;
     char* h_pairs = nullptr;
@@ -1673,6 +1673,60 @@ kslb_status kslb_ensemble_renormalize(kslb_ensemble* E, int npairs, const int* r
     return KSLB_OK;
 }
 
+kslb_status kslb_ensemble_orthonormalize(kslb_ensemble* E, int ngroups, int k, const int* ref, const int* pert,
+                                         double delta, double* log_accum)
+{
+    if (!E) return fail(KSLB_EINVAL, "null ensemble");
+    if (ngroups < 0 || k < 1 || k > kGroupMaxK || (ngroups > 0 && (!ref || !pert || !log_accum)))
+        return fail(KSLB_EINVAL, "bad group arguments (1 <= k <= %d)", kGroupMaxK);
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(KSLB_EINVAL, "delta must be positive and finite");
+    if (ngroups == 0) return KSLB_OK;
+    std::vector<char> used((size_t)E->count, 0);
+    int nq5 = 0;
+    for (int g = 0; g < ngroups; g++) {
+        const int a = ref[g];
+        for (int m = -1; m < k; m++) {
+            const int i = m < 0 ? a : pert[(size_t)g * k + m];
+            if (i < 0 || i >= E->count) return fail(KSLB_EINVAL, "group %d: instance %d out of range", g, i);
+            if (used[i]) return fail(KSLB_EINVAL, "group %d: instance %d appears twice", g, i);
+            used[i] = 1;
+            if (E->prec[i] != kFP64) return fail(KSLB_EINVAL, "group %d: trajectories need FP64 storage", g);
+            if (!E->have_state[i]) return fail(KSLB_ESTATE, "group %d: instance %d has no state", g, i);
+            if (E->q[i] != E->q[a] || E->n[i] != E->n[a] || E->step[i] != E->step[a])
+                return fail(KSLB_EINVAL, "group %d: instances differ in scheme, sites or steps", g);
+        }
+        nq5 += E->q[a] == 5;
+    }
+    // table: group descriptors (D1Q5 groups first), then the perturbed-state offsets
+    std::vector<GroupDesc> gv((size_t)ngroups);
+    std::vector<int64_t> offs((size_t)ngroups * k);
+    int at5 = 0, at7 = nq5;
+    for (int g = 0; g < ngroups; g++) {
+        const int a = ref[g];
+        const int row = E->q[a] == 5 ? at5++ : at7++;
+        gv[row] = GroupDesc{(int64_t)(E->off[a] + (size_t)E->cur[a] * E->copy[a]), E->n[a], state_pitch(E->n[a]),
+                            row * k, k, g * k, 0};
+        for (int m = 0; m < k; m++) {
+            const int i = pert[(size_t)g * k + m];
+            offs[(size_t)row * k + m] = (int64_t)(E->off[i] + (size_t)E->cur[i] * E->copy[i]);
+        }
+    }
+    const size_t off_at = sizeof(GroupDesc) * gv.size();
+    std::vector<char> blob(off_at + sizeof(int64_t) * offs.size());
+    std::memcpy(blob.data(), gv.data(), off_at);
+    std::memcpy(blob.data() + off_at, offs.data(), sizeof(int64_t) * offs.size());
+    DeviceGuard dg(E->device);
+    char* dev = nullptr;
+    if (auto st = ens_upload(E, E->group_tab, blob.data(), blob.size(), &dev)) return st;
+    const GroupDesc* dd = reinterpret_cast<const GroupDesc*>(dev);
+    const int64_t* doff = reinterpret_cast<const int64_t*>(dev + off_at);
+    int e = 0;
+    if (nq5) e = launch_group_orth(5, k, E->buf, dd, doff, nq5, delta, log_accum, E->stream);
+    if (!e && ngroups > nq5) e = launch_group_orth(7, k, E->buf, dd + nq5, doff, ngroups - nq5, delta, log_accum, E->stream);
+    if (e) return hip_fail(e, "group orthonormalisation kernel");
+    return KSLB_OK;
+}
+
 kslb_status kslb_ensemble_destroy(kslb_ensemble* E)
 {
     if (!E) return KSLB_OK;
@@ -1691,6 +1745,7 @@ kslb_status kslb_ensemble_destroy(kslb_ensemble* E)
     if (E->pairs_ev) (void)hipEventDestroy(E->pairs_ev);
     ens_table_free(E->init_tab);
     ens_table_free(E->read_tab);
+    ens_table_free(E->group_tab);
     delete E;
     return KSLB_OK;
 }

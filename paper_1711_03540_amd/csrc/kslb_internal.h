@@ -80,6 +80,17 @@ struct PairDesc {
 };
 int launch_pair_renorm(int q, char* base, const PairDesc* desc, int npairs, double delta, double* log_accum,
                        void* stream);
+// A reference and k perturbed copies of an FP64 ensemble: byte offset of the
+// reference's current state copy, sites, row pitch, the index of the group's
+// first perturbed-state offset in a separate int64 array, k, and the first of
+// its k accumulator slots.
+constexpr int kGroupMaxK = 8;
+struct GroupDesc {
+    int64_t ref_off, n, pitch;
+    int32_t first, k, slot, pad;
+};
+int launch_group_orth(int q, int k, char* base, const GroupDesc* desc, const int64_t* pert_off, int ngroups,
+                      double delta, double* log_accum, void* stream);
 // fixed-end boundary values (NULL / absent = periodic)
 struct Ends {
     double rho_l, rho_r;

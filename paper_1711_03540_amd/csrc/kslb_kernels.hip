@@ -1287,6 +1287,120 @@ int launch_pair_renorm(int q, char* base, const PairDesc* desc, int npairs, doub
     return (int)hipGetLastError();
 }
 
+// Lyapunov spectrum: renormalisation of a reference trajectory and K
+// perturbed copies (one workgroup per group).  With v_m = S_pert[m] - S_ref
+// over the Q x n post-collision populations, the Gram matrix G_ab = v_a . v_b
+// (fixed-order sums: strided per thread, then a tree over the workgroup) is
+// factored G = R^T R (Cholesky, R upper triangular with positive diagonal),
+// so V = U R with orthonormal U; then S_pert[m] <- S_ref + delta u_m and
+// log_accum[slot + m] += ln(R_mm / delta).  If R is not positive definite and
+// finite the group is left unchanged and NaN is stored.
+template <int Q, int K>
+__global__ __launch_bounds__(kPairLD) void k_group_orth(char* __restrict__ base, const GroupDesc* __restrict__ gd,
+                                                       const int64_t* __restrict__ pert_off, double delta,
+                                                       double* __restrict__ log_accum)
+{
+    constexpr int NP = K * (K + 1) / 2;
+    __shared__ double red[kPairLD];
+    __shared__ double gram[NP];
+    __shared__ double rm[K][K];
+    __shared__ int ok_sh;
+    const GroupDesc g = gd[blockIdx.x];
+    const double* r = reinterpret_cast<const double*>(base + g.ref_off);
+    double* x[K];
+    unroll<K>([&](auto M) { x[M] = reinterpret_cast<double*>(base + pert_off[g.first + M]); });
+    const int t = threadIdx.x;
+    const int64_t total = (int64_t)Q * g.n;
+    double acc[NP];
+    unroll<NP>([&](auto P) { acc[P] = 0.0; });
+    for (int64_t e = t; e < total; e += kPairLD) {
+        const int64_t i = e / g.n, idx = i * g.pitch + (e - i * g.n);
+        const double rv = r[idx];
+        double v[K];
+        unroll<K>([&](auto M) { v[M] = x[M][idx] - rv; });
+        unroll<K>([&](auto A) {
+            unroll<K>([&](auto B) {
+                constexpr int a = A, b = B;
+                if constexpr (b >= a) {
+                    constexpr int P = a * K - a * (a - 1) / 2 + (b - a);   // packed upper triangle
+                    acc[P] = __builtin_fma(v[a], v[b], acc[P]);
+                }
+            });
+        });
+    }
+    unroll<NP>([&](auto P) {
+        red[t] = acc[P];
+        __syncthreads();
+        for (int h = kPairLD / 2; h > 0; h >>= 1) {
+            if (t < h) red[t] += red[t + h];
+            __syncthreads();
+        }
+        if (t == 0) gram[P] = red[0];
+        __syncthreads();
+    });
+    if (t == 0) {
+        // packed index of (a, b), a <= b, in the row-major upper triangle
+        auto at = [](int a, int b) { return a * K - a * (a - 1) / 2 + (b - a); };
+        bool ok = true;
+        for (int m = 0; m < K && ok; m++) {
+            double d = gram[at(m, m)];
+            for (int l = 0; l < m; l++) d -= rm[l][m] * rm[l][m];
+            const double rmm = d > 0.0 ? sqrt(d) : 0.0;
+            ok = rmm > 0.0 && __builtin_isfinite(rmm);
+            rm[m][m] = rmm;
+            for (int c = m + 1; c < K && ok; c++) {
+                double o = gram[at(m, c)];
+                for (int l = 0; l < m; l++) o -= rm[l][m] * rm[l][c];
+                rm[m][c] = o / rmm;
+            }
+        }
+        for (int m = 0; m < K; m++)
+            log_accum[g.slot + m] = ok ? log_accum[g.slot + m] + log(rm[m][m] / delta) : __builtin_nan("");
+        ok_sh = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!ok_sh) return;
+    double rr[K][K];
+    unroll<K>([&](auto A) { unroll<K>([&](auto B) { rr[A][B] = (B >= A) ? rm[A][B] : 0.0; }); });
+    for (int64_t e = t; e < total; e += kPairLD) {
+        const int64_t i = e / g.n, idx = i * g.pitch + (e - i * g.n);
+        const double rv = r[idx];
+        double u[K];
+        unroll<K>([&](auto M) {
+            double v = x[M][idx] - rv;
+            unroll<K>([&](auto L) { if constexpr (L < M) v -= u[L] * rr[L][M]; });
+            u[M] = v / rr[M][M];
+        });
+        unroll<K>([&](auto M) { x[M][idx] = __builtin_fma(delta, u[M], rv); });
+    }
+}
+
+template <int Q>
+static int group_orth_q(int k, char* base, const GroupDesc* desc, const int64_t* pert_off, int ngroups,
+                        double delta, double* log_accum, hipStream_t st)
+{
+    switch (k) {
+    case 1: k_group_orth<Q, 1><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
+    case 2: k_group_orth<Q, 2><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
+    case 3: k_group_orth<Q, 3><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
+    case 4: k_group_orth<Q, 4><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
+    case 5: k_group_orth<Q, 5><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
+    case 6: k_group_orth<Q, 6><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
+    case 7: k_group_orth<Q, 7><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
+    case 8: k_group_orth<Q, 8><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_group_orth(int q, int k, char* base, const GroupDesc* desc, const int64_t* pert_off, int ngroups,
+                      double delta, double* log_accum, void* stream)
+{
+    if (ngroups <= 0) return 0;
+    if (q == 5) return group_orth_q<5>(k, base, desc, pert_off, ngroups, delta, log_accum, (hipStream_t)stream);
+    return group_orth_q<7>(k, base, desc, pert_off, ngroups, delta, log_accum, (hipStream_t)stream);
+}
+
 // ---------------------------------------------------------------- readout and diagnostics
 
 template <int Q, int P>

@@ -149,6 +149,18 @@ class Ensemble:
              p.ctypes.data_as(ctypes.c_void_p), float(delta), ctypes.c_void_p(log_accum.data_ptr()))
         return self
 
+    def orthonormalize(self, ref, pert, delta: float, log_accum):
+        """Lyapunov-spectrum step on groups (ref[g], pert[g][0..k-1]): QR of the
+        perturbations, each rescaled to delta; adds ln(R_mm / delta) to
+        log_accum[g * k + m], a float64 device tensor."""
+        r = np.ascontiguousarray(np.asarray(ref, dtype=np.int32))
+        p = np.ascontiguousarray(np.asarray(pert, dtype=np.int32).reshape(r.size, -1))
+        k = p.shape[1]
+        assert log_accum.numel() >= r.size * k and log_accum.is_cuda
+        call("kslb_ensemble_orthonormalize", self._h, int(r.size), int(k), r.ctypes.data_as(ctypes.c_void_p),
+             p.ctypes.data_as(ctypes.c_void_p), float(delta), ctypes.c_void_p(log_accum.data_ptr()))
+        return self
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             fn("kslb_ensemble_destroy")(self._h)

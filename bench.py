@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--kernel", default=None, choices=["span", "resident", "tiled", "plain"])
     ap.add_argument("--tile-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the kernel class and steps per launch (lattice workloads) or the ensemble "
+                         "tiling with the autotuner before timing (no cache)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--instances", type=int, default=4096, help="ensemble workload: instances")
     ap.add_argument("--lb-steps", type=int, default=20000, help="ensemble workload: LB steps per instance")
@@ -165,6 +168,12 @@ def bench_ensemble(args):
     dX, dT = math.pi / 16, 1e-4
     ens = Ensemble(sizes, 7, args.precision, device=dev).set_physical(dX, dT, 0.0)
     ens.set_tiling(0, args.segments, args.chunk)
+    tuned = None
+    if args.autotune:
+        from paper_1711_03540_amd import tune
+        tuned = tune.tune_ensemble(sizes, 7, args.precision, cache=None)
+        tune.apply_ensemble(ens, tuned)
+        print("bench: autotuned ensemble tiling %s" % tuned["best"], file=sys.stderr, flush=True)
     rho0 = [torch.tensor(inputs.random_modes_ic(int(n), n * dX, seed=1000 + i), device=dev)
             for i, n in enumerate(sizes)]
     rho_all = torch.cat(rho0)          # every instance's density, resident in HBM
@@ -217,7 +226,7 @@ def bench_ensemble(args):
            "unit": "GLUPS", "ms_per_solve": 1e3 * sum(times) / len(times), "site_updates_per_solve": su,
            "instances": len(sizes), "mean_n": float(np.mean(sizes)), "lb_steps": args.lb_steps,
            "plain_one_instance_glups": plain, "speedup_vs_plain": value / plain, "tau": ens.tau,
-           "errors": errors,
+           "errors": errors, "autotuned": tuned["best"] if tuned else None,
            # algorithmic flops of the site updates (halo re-computation not
            # counted) over the solve time, against the chip's FP64 vector peak
            "roofline": {"bound": "alu", "achieved": flops_per_site_update(7, args.precision) * value / 1e3,
@@ -709,6 +718,13 @@ def main():
     lat = Lattice(w.n, w.q, args.precision, device=dev)
     lat.set_physical(w.dX, w.dT, 0.0)
     lat.set_kernel(kernel, args.tile_steps)
+    tuned = None
+    if args.autotune and args.kernel is None:
+        from paper_1711_03540_amd import tune
+        tuned = tune.tune_lattice(w.n, w.q, args.precision, steps=min(w.steps, 2000), dX=w.dX, dT=w.dT, cache=None)
+        tune.apply_lattice(lat, tuned)
+        kernel = tuned["best"]["kernel"]
+        print("bench: autotuned %s" % tuned["best"], file=sys.stderr, flush=True)
     tau = lat.coefficients()["tau"]
     stream = lat.stream
 
@@ -803,6 +819,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "min": float(lat_ms.min())},
         "roofline": roof,
+        "autotuned": tuned["best"] if tuned else None,
     }
 
     if not args.no_plain and kernel != "plain":

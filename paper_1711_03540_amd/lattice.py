@@ -74,6 +74,7 @@ class Lattice:
                      guard: str = "refuse", rho_max: float = 3.0) -> "Lattice":
         g = {"refuse": _lib.GUARD_REFUSE, "raise": _lib.GUARD_RAISE_TAU, "off": _lib.GUARD_OFF}[guard]
         call("kslb_set_physical", self._h, dX, dT, tau, dm_variant, g, rho_max)
+        self._phys = (dX, dT, dm_variant, guard, rho_max)
         return self
 
     def set_coefficients(self, E, G, omega: float) -> "Lattice":
@@ -129,6 +130,43 @@ class Lattice:
 
     def advance(self, steps: int) -> "Lattice":
         call("kslb_advance", self._h, int(steps))
+        return self
+
+    def advance_guarded(self, steps: int, chunk: int = 1000, tau_step: float = 0.02, max_raises: int = 50,
+                        bound: float = None) -> "Lattice":
+        """Advance `steps` steps in chunks, saving the state before each chunk.  A
+        chunk that ends with a non-finite state (the library's flag) or, if
+        `bound` is given, with max |rho| above it, is rolled back and run again
+        with tau raised by `tau_step` (the minimum stable tau of section 3 grows
+        with dT; raising tau is how its scans restore stability).  Each recovery
+        is recorded as (step, old tau, new tau) in `self.recoveries`.  FP64 and
+        FP32 storage (split storage encodes the state against the coefficients;
+        the rho-only storage is tied to tau = 1)."""
+        if self.precision not in (_lib.PRECISIONS["fp64"], _lib.PRECISIONS["fp32"]):
+            raise ValueError("advance_guarded needs fp64 or fp32 storage")
+        if getattr(self, "_phys", None) is None:
+            raise ValueError("set_physical first")
+        dX, dT, dm, guard, rho_max = self._phys
+        self.recoveries = []
+        left = int(steps)
+        raises = 0
+        while left > 0:
+            n = min(int(chunk), left)
+            ckpt, step0 = self.save_state(), self.step
+            self.advance(n)
+            _, bad = self.diagnostics()
+            if not bad and bound is not None:
+                bad = not (np.max(np.abs(self.rho())) <= bound)
+            if not bad:
+                left -= n
+                continue
+            if raises >= max_raises:
+                raise FloatingPointError("unstable after %d raises of tau" % raises)
+            old = self.coefficients()["tau"]
+            self.load_state(ckpt, step0)
+            call("kslb_set_physical", self._h, dX, dT, old + tau_step, dm, _lib.GUARD_OFF, rho_max)
+            self.recoveries.append((step0, old, self.coefficients()["tau"]))
+            raises += 1
         return self
 
     def read_rho(self, out=None):

@@ -796,3 +796,35 @@ def test_tuner_choices_give_identical_results():
         ens.advance([100, 100, 100])
     for i in range(len(sizes)):
         assert np.array_equal(a.rho(i), b.rho(i)), i
+
+
+def test_guarded_advance_rolls_back_and_raises_tau():
+    # the Table 3 case D1Q5, dX = 0.2, dT = 1e-3 at the fitted tau blows up
+    # (the guard flags it); the guarded advance rolls each failing chunk back
+    # to its checkpoint and reruns it with a larger tau until the run is stable
+    from paper_1711_03540_amd.inputs import table3_ends, table3_profile, table3_sites
+    say("case guarded advance")
+    q, dX, dT, steps = 5, 0.2, 1e-3, 500
+    n = table3_sites(dX)
+    X = np.arange(n) * dX
+    lo, hi = table3_ends()
+
+    def fresh():
+        lat = Lattice(n, q, "fp64").set_physical(dX, dT, 0.0, guard="off").set_fixed_ends(lo, hi)
+        return lat.init_rho(table3_profile(X, 0.0))
+    plain = fresh().advance(steps)
+    rho = plain.rho()
+    assert plain.diagnostics()[1] or not np.max(np.abs(rho)) < 1e3      # unguarded: blows up
+    tau0 = plain.coefficients()["tau"]
+    lat = fresh().advance_guarded(steps, chunk=50, bound=1e3)
+    say("  recoveries %s" % lat.recoveries)
+    assert lat.recoveries and lat.step == steps
+    assert lat.coefficients()["tau"] > tau0
+    assert not lat.diagnostics()[1] and np.max(np.abs(lat.rho())) < 1e3
+    # the rollback restores the checkpoint exactly: the same run replayed
+    # without failures (the fitted tau up to the last rolled-back checkpoint,
+    # the final tau after it) gives the same bits
+    step0, _, tau_final = lat.recoveries[-1]
+    replay = fresh().advance(step0)
+    replay.set_physical(dX, dT, tau_final, guard="off").advance(steps - step0)
+    assert np.array_equal(replay.f(), lat.f())

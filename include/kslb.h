@@ -36,6 +36,11 @@
  *     calling thread.  Work enqueued on the stream is asynchronous; a device
  *     fault surfaces at the next synchronising call.
  *   - An object is not thread-safe; distinct objects are independent.
+ *   - Failure-path testing: with the environment variable
+ *     KSLB_SPAN_INJECT_ABORT=1, every SPAN launch starts with its abort word
+ *     raised; it stops at its first edge exchange and kslb_diagnostics then
+ *     reports KSLB_EDEVICE, as after a timed-out wait, until the state is
+ *     replaced (kslb_init_rho, kslb_write_f, kslb_load_state).
  */
 #ifndef KSLB_H
 #define KSLB_H

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -598,10 +599,14 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
         const int64_t cap = std::min<int64_t>(kMaxStepsPerLaunch, (slots + 1) * sp);
         const int64_t nl = (n_steps + cap - 1) / cap;
         const int64_t chunk = std::min(cap, ((n_steps + nl - 1) / nl + sp - 1) / sp * sp);
+        // failure-path testing: KSLB_SPAN_INJECT_ABORT=1 starts every launch
+        // with its abort word raised
+        const char* inj = std::getenv("KSLB_SPAN_INJECT_ABORT");
+        const bool inject = inj && inj[0] == '1';
         for (int64_t done = 0; done < n_steps; done += chunk) {
             const int64_t s = std::min(chunk, n_steps - done);
             e = launch_span(L->q, L->prec, L->state(), L->other(), L->n, nwg, s, sp, ebase, ecopy, slots, ctl,
-                            L->ph.cf, L->stream, L->fixed ? &L->ends : nullptr);
+                            L->ph.cf, L->stream, L->fixed ? &L->ends : nullptr, inject);
             if (e) return hip_fail(e, "multi-workgroup kernel");
             L->cur ^= 1;
         }

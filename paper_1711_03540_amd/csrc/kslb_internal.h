@@ -95,8 +95,11 @@ int launch_group_orth(int q, int k, char* base, const GroupDesc* desc, const int
 struct Ends {
     double rho_l, rho_r;
 };
+// inject_abort: start with the abort word raised (every owner stops at its
+// first exchange and the sticky error word is set), for failure-path tests.
 int launch_span(int q, int prec, const void* src, void* dst, int64_t n, int nwg, int64_t steps, int s, char* ebase,
-                int64_t ecopy, int64_t slots, int* ctl, const Coef& cf, void* stream, const Ends* ends);
+                int64_t ecopy, int64_t slots, int* ctl, const Coef& cf, void* stream, const Ends* ends,
+                bool inject_abort = false);
 int launch_plain_fixed(int q, int prec, const void* src, void* dst, int64_t n, const Coef& cf, const Ends& ends,
                        void* stream);
 int launch_init_fixed(int q, int prec, void* state, int64_t n, const double* rho0, const Coef& cf, const Ends& ends,

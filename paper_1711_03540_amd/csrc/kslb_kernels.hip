@@ -1180,15 +1180,17 @@ __global__ __launch_bounds__(kSpanLD) void k_span(const char* __restrict__ src, 
             const int ab = __hip_atomic_load(ctl + kCtlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             bool ready = true;
             unroll<B>([&](auto Bi) { ready = ready && (got[Bi] || !want[Bi]); });
-            if (__builtin_amdgcn_ballot_w64(!ready) == 0) {
+            const bool all_ready = __builtin_amdgcn_ballot_w64(!ready) == 0;
+            // an abort raised anywhere stops every owner at its next poll
+            if (__builtin_amdgcn_readfirstlane(ab) || (!all_ready && spin >= kSpinLimit)) {
+                span_raise_abort(ctl, lane);
+                return;
+            }
+            if (all_ready) {
                 unroll<B>([&](auto Bi) {
                     if (want[Bi]) x[Bi] = y[Bi];
                 });
                 break;
-            }
-            if (__builtin_amdgcn_readfirstlane(ab) || spin >= kSpinLimit) {
-                span_raise_abort(ctl, lane);
-                return;
             }
             __builtin_amdgcn_s_sleep(1);
         }
@@ -1708,7 +1710,8 @@ int launch_span_set_ctl(int* ctl, int index, int value, void* stream)
 int span_ctl_error_index() { return kCtlSticky; }
 
 int launch_span(int q, int prec, const void* src, void* dst, int64_t n, int nwg, int64_t steps, int s, char* ebase,
-                int64_t ecopy, int64_t slots, int* ctl, const Coef& cf, void* stream, const Ends* ends)
+                int64_t ecopy, int64_t slots, int* ctl, const Coef& cf, void* stream, const Ends* ends,
+                bool inject_abort)
 {
     hipStream_t st = (hipStream_t)stream;
     const int h = halo_of(q);
@@ -1724,6 +1727,7 @@ int launch_span(int q, int prec, const void* src, void* dst, int64_t n, int nwg,
     if (ecopy < (int64_t)state_copy_bytes(epitch, q, prec)) return (int)hipErrorInvalidValue;
     const int64_t copies = std::min<int64_t>(slots, (steps + s - 1) / s - 1) * nwg;
     k_span_prep<<<1, 64, 0, st>>>(ctl);
+    if (inject_abort) k_span_set_ctl<<<1, 64, 0, st>>>(ctl, kCtlAbort, 1);   // failure-path testing
     if (copies > 0) {
         const unsigned fill_blocks = (unsigned)std::min<int64_t>(4096, (copies * mmax + 255) / 256);
         KSLB_DISPATCH_QP(q, prec, (k_span_fill<Q_, P_><<<fill_blocks, 256, 0, st>>>(ebase, ecopy, epitch, copies,

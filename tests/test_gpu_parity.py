@@ -828,3 +828,29 @@ def test_guarded_advance_rolls_back_and_raises_tau():
     replay = fresh().advance(step0)
     replay.set_physical(dX, dT, tau_final, guard="off").advance(steps - step0)
     assert np.array_equal(replay.f(), lat.f())
+
+
+def test_span_abort_path_reports_and_recovers(monkeypatch):
+    # failure path of the multi-workgroup kernel, forced from the host: every
+    # launch starts with its abort word raised (KSLB_SPAN_INJECT_ABORT=1), so
+    # every owner stops at its first exchange and the kernel exits normally;
+    # the sticky error word makes kslb_diagnostics report KSLB_EDEVICE until
+    # the state is replaced, after which the lattice computes correctly again
+    from paper_1711_03540_amd import KslbError
+    say("case span abort path")
+    n, dX, dT = 4096, math.pi / 16, 1e-4
+    rho0 = random_modes_ic(n, n * dX, seed=1)
+    lat = Lattice(n, 7, "fp64").set_physical(dX, dT, 0.0).set_kernel("span")
+    lat.init_rho(rho0)
+    assert lat.diagnostics()[1] is False
+    monkeypatch.setenv("KSLB_SPAN_INJECT_ABORT", "1")
+    lat.advance(200)                                   # several exchanges
+    with pytest.raises(KslbError):
+        lat.diagnostics()
+    with pytest.raises(KslbError):
+        lat.diagnostics()                              # sticky
+    monkeypatch.delenv("KSLB_SPAN_INJECT_ABORT")
+    lat.init_rho(rho0).advance(200)
+    lat.diagnostics()
+    ref = Lattice(n, 7, "fp64").set_physical(dX, dT, 0.0).set_kernel("plain").init_rho(rho0).advance(200)
+    assert np.array_equal(lat.f(), ref.f())

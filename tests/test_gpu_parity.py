@@ -854,3 +854,38 @@ def test_span_abort_path_reports_and_recovers(monkeypatch):
     lat.diagnostics()
     ref = Lattice(n, 7, "fp64").set_physical(dX, dT, 0.0).set_kernel("plain").init_rho(rho0).advance(200)
     assert np.array_equal(lat.f(), ref.f())
+
+
+def test_beyond_32_bit_offsets():
+    # a lattice of 2^29 + 5 sites: population rows start beyond 2^31 elements
+    # and 2^34 bytes into the state; plain and tiled kernels agree bit for bit
+    # and sampled sites (both ends, the middle, random) match the oracle on
+    # their light cones
+    import torch
+    n, q, dX, dT, steps = (1 << 29) + 5, 7, math.pi / 128, 2e-8, 20
+    free, _ = torch.cuda.mem_get_info()
+    if free < 100e9:
+        pytest.skip("needs about 75 GB of device memory")
+    say("case beyond 32-bit offsets: n = %d" % n)
+    x = torch.arange(n, dtype=torch.float64, device="cuda") * (2 * math.pi / n)
+    rho0 = 1.0 + 0.1 * torch.sin(3 * x) + 0.05 * torch.cos(17 * x + 0.3)
+    del x
+    outs = []
+    for kernel in ("plain", "tiled"):
+        lat = Lattice(n, q, "fp64").set_physical(dX, dT, 1.0).set_kernel(kernel)
+        lat.init_rho(rho0).advance(steps)
+        assert not lat.diagnostics()[1]
+        outs.append(lat.read_rho())
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    assert torch.equal(outs[0], outs[1])
+    half = 3 * steps + 8
+    rng = np.random.default_rng(5)
+    sites = [0, 1, n - 1, n // 2, (1 << 28) + 3] + [int(v) for v in rng.integers(0, n, 3)]
+    for j in sites:
+        idx = torch.tensor(np.arange(j - half, j + half + 1) % n, device="cuda")
+        window = rho0[idx].cpu().numpy()
+        ref = oracle.solve_periodic(q, window, dX, dT, 1.0, steps)[half]
+        got = float(outs[1][j])
+        assert abs(got - ref) <= TOL64 * np.max(np.abs(window)), (j, got, ref)

@@ -289,8 +289,8 @@ def test_reduced_precision_error(prec, bound):
 
 def test_ensemble_matches_oracle_and_single_lattices():
     say("case ensemble ragged")
-    sizes = [3, 64, 500, 777, 1024, 2049, 4096, 5000, 9999, 20000]
-    steps = [0, 1, 17, 64, 100, 333, 250, 16, 170, 50]
+    sizes = [1, 2, 3, 64, 500, 777, 1024, 2049, 4096, 5000, 9999, 20000]
+    steps = [5, 9, 0, 1, 17, 64, 100, 333, 250, 16, 170, 50]
     dX, dT = math.pi / 16, 1e-4
     ens = Ensemble(sizes, 7, "fp64").set_physical(dX, dT, 0.0)
     tau = ens.tau

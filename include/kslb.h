@@ -201,15 +201,19 @@ kslb_status kslb_get_kernel(const kslb_lattice* lat, int* kernel, int* steps_per
 enum { KSLB_PERIODIC = 0, KSLB_FIXED_ENDS = 1 };
 kslb_status kslb_set_boundary(kslb_lattice* lat, int mode, double rho_left, double rho_right);
 
-/* f := feq(rho) at every site, step counter := 0.  rho: n_sites doubles on
- * the device (rho_on_device = 1) or the host.  Host input synchronises.    */
+/* f := feq(rho) at every site (Eq. (feq); the paper does not state the
+ * initial populations, and the equilibrium of the initial density is the
+ * reading taken), step counter := 0.  rho: n_sites doubles on the device
+ * (rho_on_device = 1) or the host.  Host input synchronises.               */
 kslb_status kslb_init_rho(kslb_lattice* lat, const double* rho, int rho_on_device);
 
 /* Enqueue n_steps >= 0 steps of Eq. (2) on the stream (asynchronous).      */
 kslb_status kslb_advance(kslb_lattice* lat, int64_t n_steps);
 
-/* rho_j = sum_i f_i(j) into n_sites doubles (device or host).  Host output
- * synchronises the stream; device output is enqueued.                      */
+/* rho_j = sum_i f_i(j), the density of section 2 (collision conserves it,
+ * so the stored post-collision state gives the same rho), into n_sites
+ * doubles (device or host).  Host output synchronises the stream; device
+ * output is enqueued.                                                      */
 kslb_status kslb_read_rho(kslb_lattice* lat, double* out, int out_on_device);
 
 /* Populations as Q x n_sites doubles.  pre_collision = 0: the stored state
@@ -225,17 +229,22 @@ kslb_status kslb_read_f(kslb_lattice* lat, double* out, int out_on_device, int p
 kslb_status kslb_write_f(kslb_lattice* lat, const double* in, int in_on_device, int64_t step);
 
 /* Raw state copy for bitwise checkpoints: state_size bytes (see
- * kslb_state_size) copied device-to-device on the stream.                  */
+ * kslb_state_size) copied device-to-device on the stream, into / from a
+ * caller-owned device buffer.  load_state also sets the step counter and
+ * clears the error word of the multi-workgroup kernel.                     */
 size_t kslb_state_size(const kslb_lattice* lat);
 kslb_status kslb_save_state(kslb_lattice* lat, void* dev_dst);
 kslb_status kslb_load_state(kslb_lattice* lat, const void* dev_src, int64_t step);
 
+/* Steps advanced since the state was set (init, write_f or load_state).  */
 kslb_status kslb_step_count(const kslb_lattice* lat, int64_t* step);
 
 /* Diagnostics (synchronises): mass = sum_j rho_j in double, accumulated in a
  * fixed order; *nonfinite = 1 if any stored value is NaN or infinite.      */
 kslb_status kslb_diagnostics(kslb_lattice* lat, double* mass, int* nonfinite);
 
+/* Releases the library's own buffers (staging, exchange area), after
+ * synchronising the stream when it holds any; never the caller's buffer.   */
 kslb_status kslb_destroy(kslb_lattice* lat);
 
 /* ---------------------------------------------------------------------- */
@@ -291,8 +300,8 @@ kslb_status kslb_ensemble_get_tau(const kslb_ensemble* ens, int idx, double* tau
  * size given at create).  Its state is dropped; init it again.             */
 kslb_status kslb_ensemble_resize(kslb_ensemble* ens, int idx, int64_t n_sites);
 
-/* Initialise instance idx from its current number of densities (device or
- * host).                                                                    */
+/* As kslb_init_rho for instance idx: f := feq(rho) from its current number
+ * of densities (device or host), step counter := 0.                        */
 kslb_status kslb_ensemble_init_rho(kslb_ensemble* ens, int idx, const double* rho, int on_device);
 
 /* Initialise every instance at once, as kslb_ensemble_init_rho for each:
@@ -308,6 +317,7 @@ kslb_status kslb_ensemble_init_rho_all(kslb_ensemble* ens, const double* rho, in
  * chunks.                                                                  */
 kslb_status kslb_ensemble_advance(kslb_ensemble* ens, const int64_t* steps);
 
+/* As kslb_read_rho for instance idx (its current number of sites).      */
 kslb_status kslb_ensemble_read_rho(kslb_ensemble* ens, int idx, double* out, int on_device);
 
 /* The densities of every instance back to back in instance order (sum over
@@ -330,7 +340,8 @@ kslb_status kslb_ensemble_read_rho_all(kslb_ensemble* ens, double* out, int on_d
 kslb_status kslb_ensemble_renormalize(kslb_ensemble* ens, int npairs, const int* ref, const int* pert,
                                       double delta, double* log_accum);
 
-/* Lyapunov spectrum: renormalisation of ngroups groups, each a reference
+/* Lyapunov spectrum of the scheme's dynamics (the chaotic dynamics section 4
+ * names as the next subject): renormalisation of ngroups groups, each a reference
  * trajectory ref[g] and k perturbed copies pert[g k + m], m = 0..k-1
  * (1 <= k <= 8; host arrays of FP64 instances of one scheme with equal
  * sites and steps, no instance used twice).  With v_m = S_pert[m] - S_ref

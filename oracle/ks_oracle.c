@@ -24,7 +24,10 @@
  *   - the state handed between steps is the pre-collision f of Eq. (2), and the
  *     step is collide-then-push exactly in the order Eq. (2) is written.
  *
- * Parity pins live in tests/test_oracle_pins.py.
+ * Parity pins live in tests/test_oracle_pins.py.  Parity unpinned: the A
+ * constants of the tau fit (ko_tau_fit, Eqs. (A_B_fit_D1Q5/Q7)): the paper
+ * prints no tau value to check them against (its B constants are pinned by
+ * the printed stability limits at tau = 1).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -129,7 +132,7 @@ int ko_coefficients(int q, double dX, double dT, double tau, int dm_variant, dou
 
 /* ------------------------------------------------------------------------ */
 /* Minimum stable tau, Eq. (general_tau_formula) with the fits of           */
-/* Eqs. (A_B_fit_D1Q5) and (A_B_fit_D1Q7).                                  */
+/* Eqs. (A_B_fit_D1Q5) and (A_B_fit_D1Q7).  A: parity unpinned (see top).   */
 /* ------------------------------------------------------------------------ */
 
 double ko_tau_fit(int q, double dX, double dT)

@@ -503,6 +503,29 @@ def test_renormalize_pairs_of_both_schemes_in_one_call():
         assert np.array_equal(mixed.rho(2 * slot + 1), one.rho(1)), q
 
 
+@pytest.mark.parametrize("q", [5, 7])
+def test_rho_only_ensemble_16_sites_per_lane(q):
+    # the rho-only storage (tau = 1) in ensembles, 16 and 8 sites per lane:
+    # each instance equals a rho-only lattice on the plain kernel bitwise
+    say("case rho-only ensemble q=%d" % q)
+    sizes = [1, 5, 100, 777, 2048, 3001, 9000]
+    steps = [7, 64, 90, 33, 128, 16, 200]
+    dX, dT = 0.3, 2e-4
+    rho0s = [ic(n, dX, 60 + i) for i, n in enumerate(sizes)]
+    outs = []
+    for B, segs, chunk in ((16, 16, 32), (16, 1, 80), (8, 16, 32)):
+        ens = Ensemble(sizes, q, "rho").set_physical(dX, dT, 1.0).set_tiling(B, segs, chunk)
+        ens.init_rho_all(np.concatenate(rho0s))
+        ens.advance(steps)
+        outs.append([ens.rho(i) for i in range(len(sizes))])
+    for i, n in enumerate(sizes):
+        lat = Lattice(n, q, "rho").set_physical(dX, dT, 1.0).set_kernel("plain")
+        lat.init_rho(rho0s[i]).advance(steps[i])
+        want = lat.rho()
+        for o in outs:
+            assert np.array_equal(o[i], want), (i, n)
+
+
 def test_served_results_equal_solo_solves():
     # continuous batching: requests of both schemes and precisions arrive while
     # others run; each result equals the same solve run alone (bitwise)

@@ -587,6 +587,25 @@ def test_fixed_ends_table3_parity(q, dX):
     assert G < 1e-3
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split", "rho"])
+def test_fixed_ends_reduced_storage_bitwise(prec):
+    # the fixed-end boundary in the reduced storage modes: the plain and
+    # multi-workgroup kernels give the same bits
+    from paper_1711_03540_amd.inputs import table3_ends, table3_profile, table3_sites
+    say("case fixed ends %s" % prec)
+    q, dX, dT, tau, steps = 7, 0.1, 2e-6, 1.0, 1500
+    n = table3_sites(dX)
+    X = np.arange(n) * dX
+    lo, hi = table3_ends()
+    outs = []
+    for kernel in ("plain", "span"):
+        lat = Lattice(n, q, prec).set_physical(dX, dT, tau).set_kernel(kernel).set_fixed_ends(lo, hi)
+        lat.init_rho(table3_profile(X, 0.0)).advance(steps)
+        outs.append(lat.rho())
+    assert np.array_equal(outs[0], outs[1])
+    assert np.all(np.isfinite(outs[0]))
+
+
 @pytest.mark.parametrize("q", [5, 7])
 @pytest.mark.parametrize("n", [3, 256, 1000, 4096, 70001])
 def test_rho_only_mode_at_tau1(q, n):

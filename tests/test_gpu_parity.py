@@ -675,6 +675,31 @@ def test_write_f_roundtrip_and_nonfinite_flag():
     assert lat2.diagnostics()[1]
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split", "rho"])
+def test_populations_io_reduced_storage(prec):
+    # write_f / read_f through the reduced storage modes: FP32 rounds each
+    # population to single; split keeps rho in double and rounds only the
+    # non-equilibrium part; the rho-only state (tau = 1) keeps rho, and at
+    # tau = 1 the stored populations are exactly feq(rho)
+    say("case populations io %s" % prec)
+    n, dX, dT, tau = 400, 0.3, 2e-4, 1.0
+    ref = make(7, n, "fp64", "plain", dX, dT, tau).init_rho(ic(n, dX, 8)).advance(30)
+    f = ref.f()
+    lat = make(7, n, prec, "plain", dX, dT, tau).write_f(f, step=30)
+    g = lat.f()
+    assert lat.step == 30
+    if prec == "fp32":
+        assert np.array_equal(g, f.astype(np.float32).astype(np.float64))
+    else:
+        assert np.max(np.abs(g - f)) <= 1e-7 * np.max(np.abs(f))
+        assert np.max(np.abs(lat.rho() - ref.rho())) <= 1e-14 * np.max(np.abs(ref.rho()))
+    # and the state advances as the FP64 one does, to the storage's precision
+    lat.advance(20)
+    ref.advance(20)
+    tol = {"fp32": 1e-5, "split": 1e-9, "rho": 1e-13}[prec]
+    assert rel(lat.rho(), ref.rho()) < tol
+
+
 def test_zero_steps_and_errors():
     say("case errors")
     from paper_1711_03540_amd import KslbError

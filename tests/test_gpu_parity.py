@@ -930,6 +930,9 @@ def test_beyond_32_bit_offsets():
     # their light cones
     import torch
     n, q, dX, dT, steps = (1 << 29) + 5, 7, math.pi / 128, 2e-8, 20
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
     if free < 100e9:
         pytest.skip("needs about 75 GB of device memory")

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "kslb_internal.h"
@@ -623,11 +624,22 @@ struct Engine {
     // on each side, not the 12 (6) populations
     static constexpr bool kR = (P == kRHO);
     static constexpr int NX = kR ? 2 * H : nx_of(Q);
-    static constexpr int SLOT = NX * LD;     // doubles per exchange buffer
+    static constexpr int SLOT = NX * LD;     // exchanged values per buffer
     static_assert(B >= H, "a lane must hold at least max|c| sites");
+    // Exchanged value: FP32 populations travel as stored (widening them to
+    // double is exact, so the receiver widens them instead); every other
+    // state sends the double population (or density) its update reads.
+    static constexpr bool kF = (P == kFP32);
+    using XV = typename std::conditional<kF, float, double>::type;
+    template <int i>
+    __device__ static __forceinline__ XV xval(const Site& s, const Coef& cf)
+    {
+        if constexpr (kF) return s.s[i];
+        else return PL::template pop<i>(s, cf);
+    }
 
     // write the values the neighbours pull (column `lane` of slot)
-    __device__ static __forceinline__ void publish(const Site (&x)[B], double* slot, const Coef& cf)
+    __device__ static __forceinline__ void publish(const Site (&x)[B], XV* slot, const Coef& cf)
     {
         if constexpr (kR) {
             unroll<H>([&](auto T) {
@@ -642,7 +654,7 @@ struct Engine {
                 unroll<iabs(c)>([&](auto T) {
                     constexpr int t = T;
                     constexpr int src = (c > 0) ? (B - c + t) : t;
-                    slot[(k0 + t) * LD] = PL::template pop<i>(x[src], cf);
+                    slot[(k0 + t) * LD] = xval<i>(x[src], cf);
                 });
             });
         }
@@ -653,7 +665,7 @@ struct Engine {
     // sites whose sources all lie in this lane (H <= b < B - H) first, so the
     // neighbours' values have time to arrive; then the edge sites
     template <bool INTERIOR>
-    __device__ static __forceinline__ void step_sites(const Site (&x)[B], Site (&y)[B], const double (&hv)[NX],
+    __device__ static __forceinline__ void step_sites(const Site (&x)[B], Site (&y)[B], const XV (&hv)[NX],
                                                       const Coef& cf)
     {
         unroll<B>([&](auto Bi) {
@@ -666,14 +678,14 @@ struct Engine {
                 constexpr int sb = b - c;
                 if constexpr (sb >= 0 && sb < B) g[i] = PL::template pop<i>(x[sb], cf);
                 else if constexpr (kR) g[i] = PL::template pop<i>(Site{hv[sb < 0 ? H + sb : H + sb - B]}, cf);
-                else if constexpr (c > 0) g[i] = hv[koff(i) + b];
-                else g[i] = hv[koff(i) + sb - B];
+                else if constexpr (c > 0) g[i] = (double)hv[koff(i) + b];
+                else g[i] = (double)hv[koff(i) + sb - B];
             });
             PL::update(g, y[b], cf);
         });
     }
 
-    __device__ static __forceinline__ void step_hv(const Site (&x)[B], Site (&y)[B], const double (&hv)[NX],
+    __device__ static __forceinline__ void step_hv(const Site (&x)[B], Site (&y)[B], const XV (&hv)[NX],
                                                    const Coef& cf)
     {
         step_sites<true>(x, y, hv, cf);
@@ -681,10 +693,10 @@ struct Engine {
     }
 
     // one step x -> y: left/right point at the neighbours' columns of the slot
-    __device__ static __forceinline__ void step(const Site (&x)[B], Site (&y)[B], const double* left,
-                                                const double* right, const Coef& cf)
+    __device__ static __forceinline__ void step(const Site (&x)[B], Site (&y)[B], const XV* left,
+                                                const XV* right, const Coef& cf)
     {
-        double hv[NX];
+        XV hv[NX];
         if constexpr (kR) {
             unroll<H>([&](auto T) {
                 hv[T] = left[T * LD];
@@ -722,10 +734,16 @@ struct Engine {
         }
         return __hiloint2double(rhi, rlo);
     }
+    __device__ static __forceinline__ float from_lane(float v, bool from_left)
+    {
+        const int u = __float_as_int(v);
+        return __int_as_float(from_left ? __builtin_amdgcn_mov_dpp(u, 0x13C, 0xF, 0xF, true)     // wave_ror:1
+                                        : __builtin_amdgcn_mov_dpp(u, 0x134, 0xF, 0xF, true));   // wave_rol:1
+    }
 
     __device__ static __forceinline__ void step_dpp(const Site (&x)[B], Site (&y)[B], const Coef& cf)
     {
-        double hv[NX];
+        XV hv[NX];
         if constexpr (kR) {
             unroll<H>([&](auto T) {
                 hv[T] = from_lane(x[B - H + T].rho, true);
@@ -739,7 +757,7 @@ struct Engine {
                 unroll<iabs(c)>([&](auto T) {
                     constexpr int t = T;
                     constexpr int src = (c > 0) ? (B - c + t) : t;
-                    hv[k0 + t] = from_lane(PL::template pop<i>(x[src], cf), c > 0);
+                    hv[k0 + t] = from_lane(xval<i>(x[src], cf), c > 0);
                 });
             });
         }
@@ -776,25 +794,26 @@ struct Engine {
             }
             return;
         }
+        XV* xb = reinterpret_cast<XV*>(xch);   // the exchange area, in exchanged values
         for (; st + 1 < steps; st += 2) {
-            if (active) publish(x, xch + lane, cf);
+            if (active) publish(x, xb + lane, cf);
             __syncthreads();
             if (active) {
-                step(x, y, xch + left, xch + right, cf);
+                step(x, y, xb + left, xb + right, cf);
                 fix(y);
-                publish(y, xch + SLOT + lane, cf);
+                publish(y, xb + SLOT + lane, cf);
             }
             __syncthreads();
             if (active) {
-                step(y, x, xch + SLOT + left, xch + SLOT + right, cf);
+                step(y, x, xb + SLOT + left, xb + SLOT + right, cf);
                 fix(x);
             }
         }
         if (st < steps) {
-            if (active) publish(x, xch + lane, cf);
+            if (active) publish(x, xb + lane, cf);
             __syncthreads();
             if (active) {
-                step(x, y, xch + left, xch + right, cf);
+                step(x, y, xb + left, xb + right, cf);
                 unroll<B>([&](auto Bi) { x[Bi] = y[Bi]; });
                 fix(x);
             }

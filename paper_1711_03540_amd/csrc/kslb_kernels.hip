@@ -906,13 +906,18 @@ __global__ __launch_bounds__(kTileLD) void k_tile(const char* __restrict__ src, 
     window_lane<Q, P, B>(src, dst, n, p, ws + kl0, kl0, (int64_t)H * s, T, s, xch, cf);
 }
 
+// Waves per SIMD the ensemble kernel is compiled for: three (the LDS
+// exchange areas of three workgroups fit a CU) where that costs at most a few
+// spills outside the step loop; split storage needs too many registers.
+constexpr int ens_waves_per_simd(int p) { return p == kSPLIT ? 1 : 3; }
+
 // Ensemble: workgroup w runs window hdr[w], whose segments seg[first ..
 // first + nseg) occupy consecutive lane ranges; each segment is one tile of
 // one instance with its own halo, so several small instances share a window.
 // Lanes past the last segment's tile carry junk that is never stored.  The
 // window's coefficient set is uniform over the workgroup (scalar loads).
 template <int Q, int P, int B>
-__global__ __launch_bounds__(kTileLD) void k_ens(char* base, const WinHdr* __restrict__ hdr,
+__global__ __launch_bounds__(kTileLD) __attribute__((amdgpu_waves_per_eu(ens_waves_per_simd(P)))) void k_ens(char* base, const WinHdr* __restrict__ hdr,
                                                  const SegDesc* __restrict__ seg, const Coef* __restrict__ coefs)
 {
     extern __shared__ double xch[];

@@ -132,6 +132,51 @@ def test_tau_fit_d1q7_needs_larger_tau():
                 assert t7 > t5
 
 
+def _table3_bounded(q, dX, dT, tau):
+    # the Table 3 run with fixed ends to T = 0.5 stays finite and |rho| < 100
+    # (its solution lies in [0.6, 5.4])
+    rho = oracle.solve_tanh_fixed(q, dX, dT, tau, int(round(0.5 / dT)))
+    return bool(np.all(np.isfinite(rho)) and np.max(np.abs(rho)) < 100.0)
+
+
+def _fit_with(A, B, dT):
+    l = math.log10(dT)
+    return A * (l + B) ** 2 + 1.0 if l >= -B else 1.0
+
+
+TAU_FIT_CASES = [(q, dT) for q in (5, 7) for dT in (5e-4, 1e-3)]
+
+
+def _band_holds(q, dT, fit):
+    return _table3_bounded(q, 0.2, dT, fit + 0.04) and not _table3_bounded(q, 0.2, dT, fit - 0.06)
+
+
+def test_tau_fit_tracks_the_blow_up_threshold_at_dx02():
+    # Figs. 1-3 (left panels): the fit of Eq. (general_tau_formula) with the
+    # A, B of Eqs. (A_B_fit_*) is the smallest stable tau of the Table 3
+    # problem.  At dX = 0.2, where its A-dependent branch is active for these
+    # dT, the oracle's run (pinned elsewhere) stays bounded at fit + 0.04 and
+    # blows up at fit - 0.06 (its threshold lies 0.01-0.02 above the fit).
+    for q, dT in TAU_FIT_CASES:
+        fit = oracle.tau_fit(q, 0.2, dT)
+        assert fit > 1.05
+        assert _band_holds(q, dT, fit), (q, dT, fit)
+
+
+def test_tau_fit_band_rejects_plausible_mistakes_in_A():
+    # the band above would catch a mistyped A: the dX power dropped, its sign
+    # flipped, or the prefactor off by ten each fail at least one case
+    dX = 0.2
+    coeffs = {5: (0.103, -0.381, -13.2 * dX + 6.56), 7: (0.0886, -0.472, -12.5 * dX + 6.64)}
+    for mutate in (lambda a, e: a, lambda a, e: a * dX ** -e, lambda a, e: 10 * a * dX ** e):
+        ok = []
+        for q, dT in TAU_FIT_CASES:
+            a, e, B = coeffs[q]
+            assert _fit_with(a * dX ** e, B, dT) == pytest.approx(oracle.tau_fit(q, dX, dT), rel=1e-14)
+            ok.append(_band_holds(q, dT, _fit_with(mutate(a, e), B, dT)))
+        assert not all(ok)
+
+
 # ---------------------------------------------------------------- tau = 1: textbook finite differences
 
 def _fd_step(q, rho, dX, dT):

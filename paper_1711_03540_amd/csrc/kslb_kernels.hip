@@ -942,7 +942,11 @@ constexpr int kSpanLD = 64;      // one wave per workgroup: lanes trade values b
 // often, which measures as the better trade for the lattices SPAN serves.
 __host__ __device__ constexpr int span_b_of(int q) { return halo_of(q); }
 constexpr int kSpinLimit = 1 << 21;
-constexpr int kFirstPollDelay = 6;   // units of 64 clocks before the first poll of an exchange
+// Wait before the first poll of an exchange, in units of 64 clocks: about as
+// long as the neighbours' stores take to become visible, which grows with
+// the words an owner publishes (D1Q7: 21 per lane, D1Q5: 10).  Shorter waits
+// spend memory traffic on polls that find sentinels, longer ones idle.
+__host__ __device__ constexpr int first_poll_delay(int q) { return q == 7 ? 12 : 6; }
 
 // Control words of the multi-workgroup kernel (device memory, kept by the
 // lattice across launches): the abort word of the current launch and a
@@ -1196,7 +1200,7 @@ __global__ __launch_bounds__(kSpanLD) void k_span(const char* __restrict__ src, 
         // wanted word holds the sentinel.  The neighbours' stores leave at the
         // same time as ours, so a first poll issued at once mostly reaches
         // memory before them: wait a little first.
-        __builtin_amdgcn_s_sleep(kFirstPollDelay);
+        __builtin_amdgcn_s_sleep(first_poll_delay(Q));
         for (int spin = 0;; spin++) {
             Site y[B];
             bool got[B];

@@ -24,8 +24,11 @@
  *   - the state handed between steps is the pre-collision f of Eq. (2), and the
  *     step is collide-then-push exactly in the order Eq. (2) is written.
  *
- * Parity pins live in tests/test_oracle_pins.py.  Partly pinned: the A
- * constants of the tau fit (ko_tau_fit, Eqs. (A_B_fit_D1Q5/Q7)).  The paper
+ * Parity pins live in tests/test_oracle_pins.py.  Every function below is
+ * pinned there (G of section 3 on a hand-worked case; the collision alone by
+ * collide-then-shift equalling one step, conservation and relaxation by
+ * 1/tau), except in part the A constants of the tau fit (ko_tau_fit,
+ * Eqs. (A_B_fit_D1Q5/Q7)).  The paper
  * prints no tau value; its B constants are pinned by the printed stability
  * limits at tau = 1, and A only at dX = 0.2, where the fit must lie within
  * -0.04 / +0.06 of the blow-up threshold of the Table 3 run (Figs. 1-3, left

@@ -424,3 +424,43 @@ def test_d1q7_more_accurate_than_d1q5_at_fitted_tau():
     g7 = _G(7, dX, dT, oracle.tau_fit(7, dX, dT), T)
     assert g7 < 0.5 * g5
     assert g5 < 1e-2
+
+
+# ---------------------------------------------------------------- G and the collision on their own
+
+def test_global_error_hand_worked():
+    # G of section 3: sum_x |rho^N - rho^A| / sum_x |rho^A|.  Worked by hand:
+    # |diff| = 0.5, 0, 1, 1, 0.25 -> 2.75; |rho^A| = 1.5, 2, 2, 2, 0.25 -> 7.75.
+    num = np.array([1.0, 2.0, 3.0, -1.0, 0.0])
+    ana = np.array([1.5, 2.0, 2.0, -2.0, 0.25])
+    assert oracle.global_error(num, ana) == 2.75 / 7.75
+    # plausible slips give other values: normalising by sum |rho^N| (7),
+    # dropping the absolute value of a negative rho^A (3.75), squaring
+    assert 2.75 / 7.0 != 2.75 / 7.75 and 2.75 / 3.75 != 2.75 / 7.75
+    # swapping the arguments changes only the denominator
+    assert oracle.global_error(ana, num) == 2.75 / 7.0
+    # exact agreement gives zero; scaling both arrays leaves G unchanged
+    assert oracle.global_error(ana, ana) == 0.0
+    assert oracle.global_error(4.0 * num, 4.0 * ana) == 2.75 / 7.75
+
+
+@pytest.mark.parametrize("q", [5, 7])
+@pytest.mark.parametrize("tau", [1.0, 1.3])
+def test_collide_then_push_equals_one_step(q, tau):
+    # Eq. (2) is collision at x followed by a move to x + c_i: the oracle's
+    # collision alone, then a periodic shift of population i by c_i (numpy),
+    # is bitwise its one-step advance.
+    n, dX, dT = 97, 0.2, 1e-4
+    c = C5 if q == 5 else C7
+    coef = oracle.coefficients(q, dX, dT, tau)
+    rng = np.random.default_rng(11)
+    f = oracle.init(q, coef, random_modes_ic(n, n * dX, seed=4, amplitude=0.8))
+    f = f + 1e-3 * rng.standard_normal(f.shape)          # off equilibrium
+    post = oracle.collide(q, coef, tau, f)
+    pushed = np.stack([np.roll(post[i], int(c[i])) for i in range(q)])
+    assert np.array_equal(pushed, oracle.advance(q, coef, tau, f, 1))
+    # the collision conserves the density of every site (section 2, rho = sum_i f_i)
+    np.testing.assert_allclose(post.sum(axis=0), f.sum(axis=0), rtol=0, atol=1e-14)
+    # it relaxes by 1/tau: post - feq = (1 - 1/tau)(f - feq), feq of the site's density
+    eq = np.stack([oracle.feq(q, coef, r) for r in f.sum(axis=0)], axis=1)
+    np.testing.assert_allclose(post - eq, (1.0 - 1.0 / tau) * (f - eq), rtol=0, atol=1e-14)

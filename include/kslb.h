@@ -26,21 +26,30 @@
  *     is rho_j = sum_i f_i(j) of the paper's f at time n.
  *   - Device memory and HIP streams belong to the caller.  The library never
  *     frees a caller buffer.  It allocates only small descriptor tables, the
- *     exchange area of the SPAN kernel (a 256-byte control block and, for
- *     each exchange of one launch, one copy of every workgroup's own sites;
- *     at most 256 MiB, a longer advance being split into several launches)
- *     and, when a host pointer is passed to a transfer call, one device
- *     staging buffer of Q * n_sites doubles; all live until destroy.
+ *     exchange area of the SPAN kernel (for each exchange of one launch, one
+ *     copy of every workgroup's own sites; at most 256 MiB, a longer advance
+ *     being split into several launches) and, when a host pointer is passed
+ *     to a transfer call, one device staging buffer of Q * n_sites doubles;
+ *     all live until destroy.  The SPAN kernel's control words (abort word,
+ *     sticky error word, count of aborted launches) sit in the diagnostics
+ *     area of the lattice's own buffer.
  *   - Every function returns a kslb_status (0 = OK, < 0 = error) and never
  *     aborts or throws; kslb_last_error() describes the last failure of the
  *     calling thread.  Work enqueued on the stream is asynchronous; a device
  *     fault surfaces at the next synchronising call.
- *   - An object is not thread-safe; distinct objects are independent.
+ *   - An object is not thread-safe; distinct objects are independent and may
+ *     be used from different threads at once (the library's process-wide
+ *     caches, per-kernel LDS limits and device occupancy, are locked).
+ *   - A SPAN launch whose wait for a neighbour's edge times out (or that is
+ *     aborted) stops early without writing its result.  From then until the
+ *     state is replaced (kslb_init_rho, kslb_write_f, kslb_load_state) the
+ *     lattice's sticky error word is set: later SPAN launches return at
+ *     once, readouts into device memory write NaN, and readouts into host
+ *     memory, kslb_save_state and kslb_diagnostics return KSLB_EDEVICE.
+ *     kslb_aborted_launches counts such launches over the lattice's life.
  *   - Failure-path testing: with the environment variable
  *     KSLB_SPAN_INJECT_ABORT=1, every SPAN launch starts with its abort word
- *     raised; it stops at its first edge exchange and kslb_diagnostics then
- *     reports KSLB_EDEVICE, as after a timed-out wait, until the state is
- *     replaced (kslb_init_rho, kslb_write_f, kslb_load_state).
+ *     raised; it stops at its first edge exchange, as after a timed-out wait.
  */
 #ifndef KSLB_H
 #define KSLB_H
@@ -103,8 +112,15 @@ enum { KSLB_GUARD_REFUSE = 0, KSLB_GUARD_RAISE_TAU = 1, KSLB_GUARD_OFF = 2 };
  *              other workgroups publish in a library-owned exchange area (a
  *              halo may reach past the nearest neighbour).  s is the
  *              steps_per_launch of kslb_set_kernel; by default the largest
- *              with 3 W >= 8 max|c| s (24 for both schemes).  For lattices
- *              of 2 to 2048 such slices.
+ *              with 3 W >= 8 max|c| s (24 for both schemes).  Every owner
+ *              waits on its neighbours, so all must be resident at once: a
+ *              plan uses at least 2 and at most half of the owners the
+ *              device keeps resident (its occupancy for the kernel times
+ *              its compute units; 1024 on MI355X), leaving the rest for
+ *              other work.  SPAN lattices advanced at the same time on
+ *              other streams, or other work holding every compute unit,
+ *              can still starve a launch; its waits are bounded and it then
+ *              stops with the error described above.
  * All classes give bitwise identical results.                              */
 enum { KSLB_KERNEL_AUTO = 0, KSLB_KERNEL_PLAIN = 1, KSLB_KERNEL_RESIDENT = 2,
        KSLB_KERNEL_TILED = 3, KSLB_KERNEL_SPAN = 4 };
@@ -191,6 +207,17 @@ kslb_status kslb_set_kernel(kslb_lattice* lat, int kernel, int steps_per_launch)
 kslb_status kslb_get_kernel(const kslb_lattice* lat, int* kernel, int* steps_per_launch,
                             int* exchange_steps, int64_t* workgroups, int* lanes_per_workgroup);
 
+/* The kernel class and launch shape kslb_get_kernel would report for a
+ * lattice of this shape, boundary (KSLB_PERIODIC / KSLB_FIXED_ENDS) and
+ * kslb_set_kernel request, on a device that keeps span_owners SPAN
+ * workgroups resident (a plan uses at most half) and gives one workgroup
+ * lds_bytes of LDS; 0 for either queries the current device.  Host only:
+ * the planning step of kslb_advance, exposed so that it can be checked
+ * without a device.  EINVAL when an explicit request cannot be met.       */
+kslb_status kslb_plan_kernel(int64_t n_sites, int q, int precision, int boundary, int kernel, int steps_per_launch,
+                             int64_t span_owners, int lds_bytes, int* kernel_out, int* steps_per_launch_out,
+                             int* exchange_steps, int64_t* workgroups, int* lanes_per_workgroup);
+
 /* Boundary of the lattice.  KSLB_PERIODIC (default) or KSLB_FIXED_ENDS: the
  * problem of the paper's Table 3, sites 0 and n_sites-1 held at the
  * equilibrium of rho_left / rho_right, and a population streamed from beyond
@@ -240,8 +267,14 @@ kslb_status kslb_load_state(kslb_lattice* lat, const void* dev_src, int64_t step
 kslb_status kslb_step_count(const kslb_lattice* lat, int64_t* step);
 
 /* Diagnostics (synchronises): mass = sum_j rho_j in double, accumulated in a
- * fixed order; *nonfinite = 1 if any stored value is NaN or infinite.      */
+ * fixed order; *nonfinite = 1 if any stored value is NaN or infinite.
+ * KSLB_EDEVICE (after filling both) while the sticky error word is set.    */
 kslb_status kslb_diagnostics(kslb_lattice* lat, double* mass, int* nonfinite);
+
+/* SPAN launches of this lattice that stopped early (a timed-out or aborted
+ * edge exchange) since it was created; replacing the state does not reset
+ * it.  Synchronises.                                                       */
+kslb_status kslb_aborted_launches(kslb_lattice* lat, int64_t* count);
 
 /* Releases the library's own buffers (staging, exchange area), after
  * synchronising the stream when it holds any; never the caller's buffer.   */

@@ -52,6 +52,7 @@ SIGNATURES = {
     "kslb_get_coefficients": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "kslb_set_kernel": (_st, [_vp, _i, _i]),
     "kslb_get_kernel": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "kslb_plan_kernel": (_st, [_i64, _i, _i, _i, _i, _i, _i64, _i, _vp, _vp, _vp, _vp, _vp]),
     "kslb_set_boundary": (_st, [_vp, _i, _d, _d]),
     "kslb_init_rho": (_st, [_vp, _vp, _i]),
     "kslb_advance": (_st, [_vp, _i64]),
@@ -63,6 +64,7 @@ SIGNATURES = {
     "kslb_load_state": (_st, [_vp, _vp, _i64]),
     "kslb_step_count": (_st, [_vp, _vp]),
     "kslb_diagnostics": (_st, [_vp, _vp, _vp]),
+    "kslb_aborted_launches": (_st, [_vp, _vp]),
     "kslb_destroy": (_st, [_vp]),
     "kslb_ensemble_bytes": (_sz, [_i, _vp, _vp, _vp]),
     "kslb_ensemble_create": (_st, [_vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),

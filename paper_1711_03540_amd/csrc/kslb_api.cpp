@@ -53,7 +53,11 @@ struct DeviceGuard {
     }
 };
 
-constexpr size_t kDiagBytes = 4096;   // 256 partial sums + mass + flag
+// Diagnostics area at the end of a lattice's (or ensemble's) buffer: 256
+// partial sums, the mass, the non-finite flag and, from kCtlOffset, the
+// control words of the multi-workgroup kernel.
+constexpr size_t kDiagBytes = 4096;
+constexpr size_t kCtlOffset = 2304;
 
 bool valid_shape(int64_t n, int q, int prec)
 {
@@ -144,14 +148,17 @@ struct kslb_lattice {
     int tile_steps = 0;
     int64_t step = 0;
     double* staging = nullptr;         // Q x n doubles, only for host transfers
-    char* span_scratch = nullptr;      // edges + flags of the multi-workgroup kernel
+    char* span_scratch = nullptr;      // edge slots of the multi-workgroup kernel
     size_t span_bytes = 0;
+    bool ctl_ready = false;            // control words set up (first multi-workgroup advance)
     bool fixed = false;                // fixed-end boundary (Table 3 problem)
     Ends ends{0.0, 0.0};
 
     char* state() { return buf + (size_t)cur * copy; }
     char* other() { return buf + (size_t)(1 - cur) * copy; }
     double* diag() { return reinterpret_cast<double*>(buf + 2 * copy); }
+    int* ctl() { return reinterpret_cast<int*>(buf + 2 * copy + kCtlOffset); }
+    const int* sticky() { return ctl_ready ? ctl() + span_ctl_error_index() : nullptr; }
 };
 
 namespace {
@@ -169,9 +176,9 @@ kslb_status ensure_staging(kslb_lattice* L)
 
 // ring kernel: B in {8, 4} dividing n, at most ring_max_lanes() lanes, and
 // the exchange area in LDS
-int ring_sites_per_lane(int64_t n, int q)
+int ring_sites_per_lane(int64_t n, int q, int lds_bytes)
 {
-    if (ring_lds_bytes(q) > max_lds_bytes()) return 0;
+    if (ring_lds_bytes(q) > lds_bytes) return 0;
     const int Bs[2] = {8, 4};
     for (int B : Bs) {
         if (n % B) continue;
@@ -183,20 +190,38 @@ int ring_sites_per_lane(int64_t n, int q)
 }
 
 constexpr int kTileB = 8;
-constexpr int kSpanMaxOwners = 2048;
 int tile_sites_per_lane(int prec) { return prec == kRHO ? 16 : kTileB; }
+
+// Device limits a plan assumes: SPAN owners that may run at once, and the
+// dynamic LDS one workgroup may use.
+struct Limits {
+    int64_t span_owners;
+    int lds_bytes;
+};
+
+// Every SPAN owner spins on its neighbours' edges, so all of a launch's
+// owners must be resident together.  A plan takes at most half of what the
+// device keeps resident (one owner per SIMD where the occupancy allows two),
+// leaving room for other work on the device, and never more than this.
+constexpr int64_t kSpanMaxOwners = 2048;
+
+Limits device_limits(int q, int prec, bool fixed)
+{
+    return Limits{std::min<int64_t>(kSpanMaxOwners, span_device_owners(q, prec, fixed) / 2), max_lds_bytes()};
+}
+
 // Multi-workgroup plan: nwg single-wave owners of about n / nwg sites each,
 // every window (own sites + 2 H s halo, a halo possibly spanning several
 // owners) within span_lanes() x span_sites_per_lane(q) slots.  Returns nwg,
-// or 0 when the shape cannot use it.
-int span_plan(int64_t n, int q, int s)
+// or 0 when the shape cannot use it or needs more than max_owners owners.
+int span_plan(int64_t n, int q, int s, int64_t max_owners)
 {
     const int64_t W = (int64_t)span_lanes() * span_sites_per_lane(q);
     const int64_t hs = (int64_t)halo(q) * s;
     const int64_t own = W - 2 * hs;
     if (s < 1 || own < 1) return 0;
     const int64_t nwg = (n + own - 1) / own;
-    if (nwg < 2 || nwg > kSpanMaxOwners) return 0;
+    if (nwg < 2 || nwg > std::min(max_owners, kSpanMaxOwners)) return 0;
     return (int)nwg;
 }
 
@@ -206,23 +231,25 @@ int span_plan(int64_t n, int q, int s)
 // measured on D1Q7 N = 4096: s = 21, 24, 28, 31 (63, 86, 171, 683 owners) ran
 // 26.7, 25.1, 26.1, 57 ms per 10^5 steps; s = 22, 23, 25, 26, 27 ran 26.7,
 // 26.3, 26.2, 26.4, 26.6 ms.
-int span_default_steps(int64_t n, int q)
+int span_default_steps(int64_t n, int q, int64_t max_owners)
 {
     const int64_t W = (int64_t)span_lanes() * span_sites_per_lane(q);
     for (int s = (int)((3 * W) / (8 * halo(q))); s >= 1; s--)
-        if (span_plan(n, q, s)) return s;
+        if (span_plan(n, q, s, max_owners)) return s;
     return 0;
 }
 
-// Device scratch of the SPAN kernel: a control block sized for the most
-// owners, then the edge slots of one launch, at most kSpanSlotBytes of them
-// (a longer advance is split into launches of (slots + 1) s steps).
-constexpr size_t kSpanCtlBytes = 256;
+// Device scratch of the SPAN kernel: the edge slots of one launch, at most
+// kSpanSlotBytes of them (a longer advance is split into launches of
+// (slots + 1) s steps).  Its control words live in the lattice's own buffer.
 constexpr size_t kSpanSlotBytes = size_t(256) << 20;
 
 // AUTO: one lattice small enough for a few hundred single-wave owners runs
-// on SPAN; otherwise RESIDENT when it fits one workgroup, else TILED.
+// on SPAN, provided its owners fit the device with an exchange at most every
+// kSpanAutoMinSteps steps (shorter intervals spend most of a launch waiting on
+// exchanges); otherwise RESIDENT when it fits one workgroup, else TILED.
 constexpr int64_t kSpanAutoMaxSites = 65536;
+constexpr int kSpanAutoMinSteps = 12;
 
 // Steps per tiled launch, a multiple of 8 so that every window starts on an
 // 8-site boundary.  Longer launches re-read the state less often but
@@ -259,73 +286,74 @@ struct KernelChoice {
     int steps;
 };
 
-KernelChoice resolve_kernel(const kslb_lattice* L)
+// The kernel class an advance runs for this shape, boundary and request
+// (AUTO resolved) under the device limits lim, with its step parameter.
+// AUTO takes SPAN only when all its owners fit lim.span_owners.
+KernelChoice plan_kernel(int64_t n, int q, int prec, bool fixed, int req, int req_steps, const Limits& lim)
 {
-    int kernel = L->kernel;
+    int kernel = req;
     if (kernel == KSLB_KERNEL_AUTO) {
-        if (L->n <= kSpanAutoMaxSites && span_default_steps(L->n, L->q) > 0) kernel = KSLB_KERNEL_SPAN;
-        else if (L->fixed) kernel = KSLB_KERNEL_PLAIN;
-        else kernel = ring_sites_per_lane(L->n, L->q) ? KSLB_KERNEL_RESIDENT : KSLB_KERNEL_TILED;
+        if (n <= kSpanAutoMaxSites && span_default_steps(n, q, lim.span_owners) >= kSpanAutoMinSteps)
+            kernel = KSLB_KERNEL_SPAN;
+        else if (fixed) kernel = KSLB_KERNEL_PLAIN;
+        else kernel = ring_sites_per_lane(n, q, lim.lds_bytes) ? KSLB_KERNEL_RESIDENT : KSLB_KERNEL_TILED;
     }
     int steps = 0;
     if (kernel == KSLB_KERNEL_SPAN)
-        steps = (L->kernel == KSLB_KERNEL_SPAN && L->tile_steps > 0) ? L->tile_steps : span_default_steps(L->n, L->q);
+        steps = (req == KSLB_KERNEL_SPAN && req_steps > 0) ? req_steps : span_default_steps(n, q, lim.span_owners);
     else if (kernel == KSLB_KERNEL_TILED)
-        steps = L->tile_steps > 0 ? L->tile_steps : default_tile_steps(L->q, L->prec);
+        steps = req_steps > 0 ? req_steps : default_tile_steps(q, prec);
     return KernelChoice{kernel, steps};
 }
 
 }  // namespace
 
-// Bytes of one SPAN edge copy (one owner's own sites in state format).
-int64_t span_copy_bytes(const kslb_lattice* L, int nwg, int s)
+namespace {
+
+// Edge slots one SPAN launch can use (within slot_bytes), and the steps such
+// a launch covers.
+int64_t span_slot_capacity(int64_t per_exchange, int s, size_t slot_bytes)
 {
-    return span_edge_copy_bytes(L->q, L->prec, L->n, nwg, s);
+    return std::max<int64_t>(1, std::min<int64_t>((int64_t)slot_bytes / per_exchange, kMaxStepsPerLaunch / s));
 }
 
-// Edge slots one SPAN launch can use, and the steps such a launch covers.
-int64_t span_slot_capacity(const kslb_lattice* L, int nwg, int s)
+int64_t span_steps_per_launch(int64_t per_exchange, int s, size_t slot_bytes)
 {
-    const int64_t per = (int64_t)nwg * span_copy_bytes(L, nwg, s);
-    return std::max<int64_t>(1, std::min<int64_t>((int64_t)kSpanSlotBytes / per, kMaxStepsPerLaunch / s));
+    return std::min<int64_t>(kMaxStepsPerLaunch, (span_slot_capacity(per_exchange, s, slot_bytes) + 1) * s);
 }
 
-int64_t span_steps_per_launch(const kslb_lattice* L, int nwg, int s)
+// Control words of the multi-workgroup kernel, in the lattice's buffer: set
+// up once, before its first multi-workgroup launch.
+kslb_status span_ctl_setup(kslb_lattice* L)
 {
-    return std::min<int64_t>(kMaxStepsPerLaunch, (span_slot_capacity(L, nwg, s) + 1) * s);
+    if (L->ctl_ready) return KSLB_OK;
+    int e = launch_span_ctl_init(L->ctl(), span_ctl_ints(), L->stream);
+    if (e) return hip_fail(e, "SPAN control init");
+    L->ctl_ready = true;
+    return KSLB_OK;
 }
 
-// Scratch for a SPAN advance of n_steps: the control block and the edge
-// slots of (up to) one launch; *slots_out is every slot the area holds in
+// Edge slots for a SPAN advance of n_steps from the library's exchange area:
+// those of (up to) one launch; *slots_out is every slot the area holds in
 // this geometry.  Each launch refills the slots it uses with the sentinel.
-kslb_status span_prepare(kslb_lattice* L, int nwg, int s, int64_t n_steps, int64_t* slots_out)
+kslb_status span_prepare(kslb_lattice* L, int64_t per, int s, int64_t n_steps, int64_t* slots_out)
 {
-    const int64_t per = (int64_t)nwg * span_copy_bytes(L, nwg, s);
-    const int64_t exchanges = (std::min(n_steps, span_steps_per_launch(L, nwg, s)) + s - 1) / s - 1;
-    const int64_t want = std::max<int64_t>(1, std::min(span_slot_capacity(L, nwg, s), exchanges));
-    int64_t have = L->span_scratch ? (int64_t)(L->span_bytes - kSpanCtlBytes) / per : 0;
+    const int64_t exchanges = (std::min(n_steps, span_steps_per_launch(per, s, kSpanSlotBytes)) + s - 1) / s - 1;
+    const int64_t want = std::max<int64_t>(1, std::min(span_slot_capacity(per, s, kSpanSlotBytes), exchanges));
+    int64_t have = L->span_scratch ? (int64_t)L->span_bytes / per : 0;
     if (have < want) {
-        const size_t need = kSpanCtlBytes + (size_t)want * (size_t)per;
-        int sticky = 0;
-        int e = 0;
         if (L->span_scratch) {
-            // keep the error word across the reallocation
-            e = hipMemcpyAsync(&sticky, reinterpret_cast<int*>(L->span_scratch) + span_ctl_error_index(), sizeof sticky,
-                               hipMemcpyDeviceToHost, L->stream);
-            if (!e) e = hipStreamSynchronize(L->stream);
-            if (e) return hip_fail(e, "SPAN control copy");
+            int e = hipStreamSynchronize(L->stream);   // earlier launches may still read the slots
+            if (e) return hip_fail(e, "hipStreamSynchronize");
             (void)hipFree(L->span_scratch);
             L->span_scratch = nullptr;
             L->span_bytes = 0;
         }
+        const size_t need = (size_t)want * (size_t)per;
         void* p = nullptr;
         if (hipMalloc(&p, need)) return fail(KSLB_ENOMEM, "exchange area of %zu bytes failed", need);
         L->span_scratch = (char*)p;
         L->span_bytes = need;
-        int* ctl = reinterpret_cast<int*>(L->span_scratch);
-        e = launch_span_ctl_init(ctl, (int)(kSpanCtlBytes / sizeof(int)), L->stream);
-        if (!e && sticky) e = launch_span_set_ctl(ctl, span_ctl_error_index(), 1, L->stream);
-        if (e) return hip_fail(e, "SPAN control init");
         have = want;
     }
     *slots_out = have;
@@ -335,10 +363,27 @@ kslb_status span_prepare(kslb_lattice* L, int nwg, int s, int64_t n_steps, int64
 // A new state: forget SPAN timeouts of the previous one.
 kslb_status span_clear_error(kslb_lattice* L)
 {
-    if (!L->span_scratch) return KSLB_OK;
-    int e = launch_span_set_ctl(reinterpret_cast<int*>(L->span_scratch), span_ctl_error_index(), 0, L->stream);
+    if (!L->ctl_ready) return KSLB_OK;
+    int e = launch_span_set_ctl(L->ctl(), span_ctl_error_index(), 0, L->stream);
     return e ? hip_fail(e, "SPAN control") : KSLB_OK;
 }
+
+// After a synchronising transfer: EDEVICE while the sticky error word is set
+// (a SPAN launch stopped early and the state is not valid).  Synchronises.
+kslb_status span_check_error(kslb_lattice* L)
+{
+    if (!L->ctl_ready) return KSLB_OK;
+    int err = 0;
+    int e = hipMemcpyAsync(&err, L->ctl() + span_ctl_error_index(), sizeof err, hipMemcpyDeviceToHost, L->stream);
+    if (!e) e = hipStreamSynchronize(L->stream);
+    if (e) return hip_fail(e, "SPAN control copy");
+    if (err)
+        return fail(KSLB_EDEVICE, "a multi-workgroup launch stopped early (a neighbour's edge never arrived or "
+                                  "the launch was aborted); the state is not valid until it is replaced");
+    return KSLB_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -461,17 +506,19 @@ kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
     if (auto s = check_lat(L)) return s;
     if (kernel < KSLB_KERNEL_AUTO || kernel > KSLB_KERNEL_SPAN) return fail(KSLB_EINVAL, "bad kernel %d", kernel);
     if (steps_per_launch < 0) return fail(KSLB_EINVAL, "steps_per_launch must be >= 0");
-    if (kernel == KSLB_KERNEL_RESIDENT) {
+    if (kernel == KSLB_KERNEL_RESIDENT || kernel == KSLB_KERNEL_SPAN) {
         DeviceGuard g(L->device);
-        if (!ring_sites_per_lane(L->n, L->q))
+        const Limits lim = device_limits(L->q, L->prec, L->fixed);
+        if (kernel == KSLB_KERNEL_RESIDENT && !ring_sites_per_lane(L->n, L->q, lim.lds_bytes))
             return fail(KSLB_EINVAL, "n=%lld cannot use the resident kernel (needs n = B*L, B in {4,8}, L <= 512)",
                         (long long)L->n);
-    }
-    if (kernel == KSLB_KERNEL_SPAN) {
-        const int sp = steps_per_launch > 0 ? steps_per_launch : span_default_steps(L->n, L->q);
-        if (!sp || !span_plan(L->n, L->q, sp))
-            return fail(KSLB_EINVAL, "n=%lld cannot be split over workgroups with %d steps between exchanges",
-                        (long long)L->n, sp);
+        if (kernel == KSLB_KERNEL_SPAN) {
+            const int sp = steps_per_launch > 0 ? steps_per_launch : span_default_steps(L->n, L->q, lim.span_owners);
+            if (!sp || !span_plan(L->n, L->q, sp, lim.span_owners))
+                return fail(KSLB_EINVAL,
+                            "n=%lld cannot be split over at most %lld resident workgroups with %d steps between "
+                            "exchanges", (long long)L->n, (long long)lim.span_owners, sp);
+        }
     }
     if (kernel == KSLB_KERNEL_TILED && steps_per_launch > 0) {
         if (tile_lanes() * tile_sites_per_lane(L->prec) - 2 * halo(L->q) * steps_per_launch <= 0)
@@ -482,31 +529,38 @@ kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
     return KSLB_OK;
 }
 
-kslb_status kslb_get_kernel(const kslb_lattice* L, int* kernel, int* steps_per_launch, int* exchange_steps,
-                            int64_t* workgroups, int* lanes_per_workgroup)
+}  // extern "C"
+
+namespace {
+
+// Launch shape of a planned class: the most steps one launch advances, the
+// steps between edge exchanges (SPAN), the workgroups of one launch and the
+// lanes of each.
+void describe(const KernelChoice& kc, int64_t n, int q, int prec, const Limits& lim, int* kernel,
+              int* steps_per_launch, int* exchange_steps, int64_t* workgroups, int* lanes_per_workgroup)
 {
-    if (auto s = check_lat(L)) return s;
-    const KernelChoice kc = resolve_kernel(L);
     int per_launch = 1, exch = 0, lanes = 256;
-    int64_t wg = (L->n + 255) / 256;
+    int64_t wg = (n + 255) / 256;
     switch (kc.kernel) {
     case KSLB_KERNEL_RESIDENT: {
-        const int rb = ring_sites_per_lane(L->n, L->q);
+        const int rb = ring_sites_per_lane(n, q, lim.lds_bytes);
         per_launch = (int)kMaxStepsPerLaunch;
         wg = 1;
-        lanes = rb ? (int)(L->n / rb) : 0;
+        lanes = rb ? (int)(n / rb) : 0;
         break;
     }
     case KSLB_KERNEL_SPAN:
         exch = kc.steps;
-        wg = kc.steps ? span_plan(L->n, L->q, kc.steps) : 0;
-        per_launch = wg ? (int)span_steps_per_launch(L, (int)wg, kc.steps) : 0;
+        wg = kc.steps ? span_plan(n, q, kc.steps, lim.span_owners) : 0;
+        per_launch = wg ? (int)span_steps_per_launch(wg * span_edge_copy_bytes(q, prec, n, (int)wg, kc.steps),
+                                                     kc.steps, kSpanSlotBytes)
+                        : 0;
         lanes = span_lanes();
         break;
     case KSLB_KERNEL_TILED: {
         per_launch = kc.steps;
-        const int64_t T = (int64_t)tile_lanes() * tile_sites_per_lane(L->prec) - 2 * (int64_t)halo(L->q) * kc.steps;
-        wg = T > 0 ? (L->n + T - 1) / T : 0;
+        const int64_t T = (int64_t)tile_lanes() * tile_sites_per_lane(prec) - 2 * (int64_t)halo(q) * kc.steps;
+        wg = T > 0 ? (n + T - 1) / T : 0;
         break;
     }
     default:
@@ -517,6 +571,49 @@ kslb_status kslb_get_kernel(const kslb_lattice* L, int* kernel, int* steps_per_l
     if (exchange_steps) *exchange_steps = exch;
     if (workgroups) *workgroups = wg;
     if (lanes_per_workgroup) *lanes_per_workgroup = lanes;
+}
+
+}  // namespace
+
+extern "C" {
+
+kslb_status kslb_get_kernel(const kslb_lattice* L, int* kernel, int* steps_per_launch, int* exchange_steps,
+                            int64_t* workgroups, int* lanes_per_workgroup)
+{
+    if (auto s = check_lat(L)) return s;
+    DeviceGuard g(L->device);
+    const Limits lim = device_limits(L->q, L->prec, L->fixed);
+    const KernelChoice kc = plan_kernel(L->n, L->q, L->prec, L->fixed, L->kernel, L->tile_steps, lim);
+    describe(kc, L->n, L->q, L->prec, lim, kernel, steps_per_launch, exchange_steps, workgroups,
+             lanes_per_workgroup);
+    return KSLB_OK;
+}
+
+kslb_status kslb_plan_kernel(int64_t n_sites, int q, int precision, int boundary, int kernel, int steps_per_launch,
+                             int64_t span_owners, int lds_bytes, int* kernel_out, int* steps_per_launch_out,
+                             int* exchange_steps, int64_t* workgroups, int* lanes_per_workgroup)
+{
+    if (!valid_shape(n_sites, q, precision)) return fail(KSLB_EINVAL, "bad shape");
+    if (kernel < KSLB_KERNEL_AUTO || kernel > KSLB_KERNEL_SPAN) return fail(KSLB_EINVAL, "bad kernel %d", kernel);
+    if (boundary != KSLB_PERIODIC && boundary != KSLB_FIXED_ENDS) return fail(KSLB_EINVAL, "bad boundary %d", boundary);
+    if (steps_per_launch < 0 || span_owners < 0 || lds_bytes < 0) return fail(KSLB_EINVAL, "negative argument");
+    const bool fixed = boundary == KSLB_FIXED_ENDS;
+    Limits lim{std::min(kSpanMaxOwners, span_owners / 2), lds_bytes};
+    if (span_owners == 0 || lds_bytes == 0) {
+        const Limits dev = device_limits(q, precision, fixed);
+        if (span_owners == 0) lim.span_owners = dev.span_owners;
+        if (lds_bytes == 0) lim.lds_bytes = dev.lds_bytes;
+    }
+    const KernelChoice kc = plan_kernel(n_sites, q, precision, fixed, kernel, steps_per_launch, lim);
+    if (kc.kernel == KSLB_KERNEL_SPAN && !span_plan(n_sites, q, kc.steps, lim.span_owners))
+        return fail(KSLB_EINVAL, "n=%lld cannot be split over at most %lld resident workgroups", (long long)n_sites,
+                    (long long)lim.span_owners);
+    if (kc.kernel == KSLB_KERNEL_RESIDENT && !ring_sites_per_lane(n_sites, q, lim.lds_bytes))
+        return fail(KSLB_EINVAL, "n=%lld cannot use the resident kernel", (long long)n_sites);
+    if (fixed && kc.kernel != KSLB_KERNEL_PLAIN && kc.kernel != KSLB_KERNEL_SPAN)
+        return fail(KSLB_EINVAL, "fixed ends run on the PLAIN and SPAN kernels only");
+    describe(kc, n_sites, q, precision, lim, kernel_out, steps_per_launch_out, exchange_steps, workgroups,
+             lanes_per_workgroup);
     return KSLB_OK;
 }
 
@@ -569,9 +666,10 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
     if (!L->have_state) return fail(KSLB_ESTATE, "advance before init_rho/write_f");
     if (n_steps == 0) return KSLB_OK;
     DeviceGuard g(L->device);
-    const KernelChoice kc = resolve_kernel(L);
+    const Limits lim = device_limits(L->q, L->prec, L->fixed);
+    const KernelChoice kc = plan_kernel(L->n, L->q, L->prec, L->fixed, L->kernel, L->tile_steps, lim);
     const int kernel = kc.kernel;
-    const int ringB = ring_sites_per_lane(L->n, L->q);
+    const int ringB = ring_sites_per_lane(L->n, L->q, lim.lds_bytes);
     if (L->fixed && kernel != KSLB_KERNEL_PLAIN && kernel != KSLB_KERNEL_SPAN)
         return fail(KSLB_EINVAL, "fixed ends run on the PLAIN and SPAN kernels only");
     int e = 0;
@@ -589,13 +687,16 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
         }
     } else if (kernel == KSLB_KERNEL_SPAN) {
         const int sp = kc.steps;
-        const int nwg = sp ? span_plan(L->n, L->q, sp) : 0;
-        if (!nwg) return fail(KSLB_EINVAL, "shape cannot use the multi-workgroup kernel");
+        const int nwg = sp ? span_plan(L->n, L->q, sp, lim.span_owners) : 0;
+        if (!nwg)
+            return fail(KSLB_EINVAL, "shape cannot use the multi-workgroup kernel (at most %lld resident workgroups)",
+                        (long long)lim.span_owners);
+        const int64_t ecopy = span_edge_copy_bytes(L->q, L->prec, L->n, nwg, sp);
         int64_t slots = 0;
-        if (auto st = span_prepare(L, nwg, sp, n_steps, &slots)) return st;
-        const int64_t ecopy = span_copy_bytes(L, nwg, sp);
-        int* ctl = reinterpret_cast<int*>(L->span_scratch);
-        char* ebase = L->span_scratch + kSpanCtlBytes;
+        if (auto st = span_prepare(L, (int64_t)nwg * ecopy, sp, n_steps, &slots)) return st;
+        if (auto st = span_ctl_setup(L)) return st;
+        int* ctl = L->ctl();
+        char* ebase = L->span_scratch;
         // launches of equal length (to a multiple of sp), each within the slots
         const int64_t cap = std::min<int64_t>(kMaxStepsPerLaunch, (slots + 1) * sp);
         const int64_t nl = (n_steps + cap - 1) / cap;
@@ -646,13 +747,14 @@ kslb_status kslb_read_rho(kslb_lattice* L, double* out, int out_on_device)
         if (auto s = ensure_staging(L)) return s;
         dst = L->staging;
     }
-    int e = launch_read_rho(L->q, L->prec, L->state(), L->n, dst, L->stream);
+    int e = launch_read_rho(L->q, L->prec, L->state(), L->n, dst, L->stream, L->sticky());
     if (e) return hip_fail(e, "readout kernel");
     if (!out_on_device) {
         e = hipMemcpyAsync(out, dst, sizeof(double) * (size_t)L->n, hipMemcpyDeviceToHost, L->stream);
         if (e) return hip_fail(e, "hipMemcpyAsync(rho)");
         e = hipStreamSynchronize(L->stream);
         if (e) return hip_fail(e, "hipStreamSynchronize");
+        return span_check_error(L);
     }
     return KSLB_OK;
 }
@@ -669,7 +771,8 @@ kslb_status kslb_read_f(kslb_lattice* L, double* out, int out_on_device, int pre
         if (auto s = ensure_staging(L)) return s;
         dst = L->staging;
     }
-    int e = launch_read_f(L->q, L->prec, L->state(), L->n, dst, pre_collision ? 1 : 0, L->ph.cf, L->stream);
+    int e = launch_read_f(L->q, L->prec, L->state(), L->n, dst, pre_collision ? 1 : 0, L->ph.cf, L->stream,
+                          L->sticky());
     if (e) return hip_fail(e, "read_f kernel");
     if (!out_on_device) {
         e = hipMemcpyAsync(out, dst, sizeof(double) * (size_t)L->q * (size_t)L->n, hipMemcpyDeviceToHost,
@@ -677,6 +780,7 @@ kslb_status kslb_read_f(kslb_lattice* L, double* out, int out_on_device, int pre
         if (e) return hip_fail(e, "hipMemcpyAsync(f)");
         e = hipStreamSynchronize(L->stream);
         if (e) return hip_fail(e, "hipStreamSynchronize");
+        return span_check_error(L);
     }
     return KSLB_OK;
 }
@@ -717,6 +821,8 @@ kslb_status kslb_save_state(kslb_lattice* L, void* dev_dst)
     if (!dev_dst) return fail(KSLB_EINVAL, "null destination");
     if (!L->have_state) return fail(KSLB_ESTATE, "no state");
     DeviceGuard g(L->device);
+    // a checkpoint of a state a multi-workgroup launch left invalid is refused
+    if (auto st = span_check_error(L)) return st;
     int e = hipMemcpyAsync(dev_dst, L->state(), L->copy, hipMemcpyDeviceToDevice, L->stream);
     if (e) return hip_fail(e, "hipMemcpyAsync(save)");
     return KSLB_OK;
@@ -763,14 +869,21 @@ kslb_status kslb_diagnostics(kslb_lattice* L, double* mass, int* nonfinite)
     if (e) return hip_fail(e, "diagnostics copy");
     if (mass) *mass = m;
     if (nonfinite) *nonfinite = f;
-    if (L->span_scratch) {
-        int err = 0;
-        e = hipMemcpyAsync(&err, reinterpret_cast<const int*>(L->span_scratch) + span_ctl_error_index(), sizeof err,
-                           hipMemcpyDeviceToHost, L->stream);
-        if (!e) e = hipStreamSynchronize(L->stream);
-        if (e) return hip_fail(e, "SPAN control copy");
-        if (err) return fail(KSLB_EDEVICE, "a multi-workgroup launch timed out waiting for a neighbour");
-    }
+    return span_check_error(L);
+}
+
+kslb_status kslb_aborted_launches(kslb_lattice* L, int64_t* count)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!count) return fail(KSLB_EINVAL, "count must not be NULL");
+    *count = 0;
+    if (!L->ctl_ready) return KSLB_OK;
+    DeviceGuard g(L->device);
+    int c = 0;
+    int e = hipMemcpyAsync(&c, L->ctl() + span_ctl_aborts_index(), sizeof c, hipMemcpyDeviceToHost, L->stream);
+    if (!e) e = hipStreamSynchronize(L->stream);
+    if (e) return hip_fail(e, "SPAN control copy");
+    *count = c;
     return KSLB_OK;
 }
 

@@ -63,12 +63,16 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
 // steps through `slots` edge slots per launch (slots * nwg copies of ecopy
 // bytes from ebase, each holding one owner's own sites in state format; see
 // span_edge_copy_bytes).  ctl holds
-// span_ctl_ints() ints (abort word, sticky error word), set up by
-// launch_span_ctl_init.  The state is read from src and written to dst.
+// span_ctl_ints() ints (abort word, sticky error word, abort claim, count of
+// aborted launches), set up by launch_span_ctl_init.  The state is read from
+// src and written to dst.
 int span_lanes();
 int span_sites_per_lane(int q);
 int span_ctl_ints();
-int span_ctl_error_index();   // sticky: a launch timed out since the state was set
+int span_ctl_error_index();   // sticky: a launch stopped early since the state was set
+int span_ctl_aborts_index();  // launches that stopped early since the control block was set up
+// owners of this kernel variant the current device keeps resident (0 if unknown)
+int64_t span_device_owners(int q, int prec, bool fixed);
 int64_t span_edge_copy_bytes(int q, int prec, int64_t n, int nwg, int s);   // one slot copy
 int launch_span_ctl_init(int* ctl, int count, void* stream);
 int launch_span_set_ctl(int* ctl, int index, int value, void* stream);
@@ -104,9 +108,12 @@ int launch_plain_fixed(int q, int prec, const void* src, void* dst, int64_t n, c
                        void* stream);
 int launch_init_fixed(int q, int prec, void* state, int64_t n, const double* rho0, const Coef& cf, const Ends& ends,
                       void* stream);
-int launch_read_rho(int q, int prec, const void* state, int64_t n, double* out, void* stream);
+// err: the lattice's sticky error word (or null); while it is set the
+// readouts write NaN
+int launch_read_rho(int q, int prec, const void* state, int64_t n, double* out, void* stream,
+                    const int* err = nullptr);
 int launch_read_f(int q, int prec, const void* state, int64_t n, double* out, int pre,
-                  const Coef& cf, void* stream);
+                  const Coef& cf, void* stream, const int* err = nullptr);
 int launch_write_f(int q, int prec, void* state, int64_t n, const double* in, const Coef& cf,
                    void* stream);
 int launch_diag(int q, int prec, const void* state, int64_t n, double* partial, int* flag,

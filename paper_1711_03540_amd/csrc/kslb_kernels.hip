@@ -24,6 +24,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <utility>
 
@@ -949,9 +952,11 @@ constexpr int kSpinLimit = 1 << 21;
 __host__ __device__ constexpr int first_poll_delay(int q) { return q == 7 ? 12 : 6; }
 
 // Control words of the multi-workgroup kernel (device memory, kept by the
-// lattice across launches): the abort word of the current launch and a
-// sticky error word (set with it, cleared only when the state is replaced).
-constexpr int kCtlAbort = 0, kCtlSticky = 1, kCtlWords = 64;
+// lattice across launches): the abort word of the current launch, a sticky
+// error word (set with it, cleared only when the state is replaced), a word
+// the first owner to raise the abort of a launch claims, and the number of
+// launches that stopped early since the lattice was created (never cleared).
+constexpr int kCtlAbort = 0, kCtlSticky = 1, kCtlRaised = 2, kCtlAborts = 3, kCtlWords = 64;
 
 // Edge slots.  At exchange c owner w stores its own sites, once, into slot
 // (c, w); its left neighbour reads the first H s of them, its right
@@ -1086,8 +1091,12 @@ __host__ __device__ inline SpanSlot span_slot_shape(int b, int64_t hs, int64_t m
 __device__ __forceinline__ void span_raise_abort(int* ctl, int lane)
 {
     if (lane == 0) {
-        __hip_atomic_store(ctl + kCtlAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int expect = 0;
+        if (__hip_atomic_compare_exchange_strong(ctl + kCtlRaised, &expect, 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            __hip_atomic_fetch_add(ctl + kCtlAborts, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(ctl + kCtlSticky, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(ctl + kCtlAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1125,6 +1134,9 @@ __global__ __launch_bounds__(kSpanLD) void k_span(const char* __restrict__ src, 
     const int per = (nwg + 7) / 8;
     const int w = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (w >= nwg) return;
+    // a lattice whose earlier launch stopped early holds no valid state
+    // until it is replaced: leave it (and its error) as it is
+    if (__hip_atomic_load(ctl + kCtlSticky, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const int64_t o = span_first(n, nwg, w);
     const int64_t M = span_first(n, nwg, w + 1) - o;
     const int hs = E::H * s;
@@ -1230,10 +1242,13 @@ __global__ __launch_bounds__(kSpanLD) void k_span(const char* __restrict__ src, 
     });
 }
 
-// Before each launch: clear the abort word.
+// Before each launch: clear the abort word and its claim.
 __global__ void k_span_prep(int* ctl)
 {
-    if (threadIdx.x == 0) ctl[kCtlAbort] = 0;
+    if (threadIdx.x == 0) {
+        ctl[kCtlAbort] = 0;
+        ctl[kCtlRaised] = 0;
+    }
 }
 
 // Sentinel in the words of `copies` edge copies that hold own sites: window
@@ -1433,13 +1448,16 @@ int launch_group_orth(int q, int k, char* base, const GroupDesc* desc, const int
 
 // ---------------------------------------------------------------- readout and diagnostics
 
+// err (may be null): the lattice's sticky error word; while it is set the
+// state is not valid and the readout is NaN.
 template <int Q, int P>
 __global__ __launch_bounds__(256) void k_read_rho(const char* __restrict__ st, int64_t n, int64_t p,
-                                                  double* __restrict__ out)
+                                                  double* __restrict__ out, const int* __restrict__ err)
 {
     using PL = Pol<Q, P>;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j < n) out[j] = PL::density(PL::load(st, p, j));
+    if (j >= n) return;
+    out[j] = (err && *err) ? __builtin_nan("") : PL::density(PL::load(st, p, j));
 }
 
 // Density readout of many lattices in one launch (block row y: instance d[y]).
@@ -1456,14 +1474,16 @@ __global__ __launch_bounds__(256) void k_read_many(const char* __restrict__ base
 // out is dense Q x n
 template <int Q, int P>
 __global__ __launch_bounds__(256) void k_read_f(const char* __restrict__ st, int64_t n, int64_t p,
-                                                double* __restrict__ out, int pre, Coef cf)
+                                                double* __restrict__ out, int pre, Coef cf,
+                                                const int* __restrict__ err)
 {
     using PL = Pol<Q, P>;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
+    const bool bad = err && *err;
     unroll<Q>([&](auto I) {
         const int64_t s = pre ? wrap_site(j - vel(I), n) : j;
-        out[I * n + j] = PL::template pop_g<I>(st, p, s, cf);
+        out[I * n + j] = bad ? __builtin_nan("") : PL::template pop_g<I>(st, p, s, cf);
     });
 }
 
@@ -1549,18 +1569,21 @@ size_t state_copy_bytes(int64_t n, int q, int prec)
     return (b + 255) & ~(size_t)255;
 }
 
+// Host-side caches below are shared by every lattice and ensemble of the
+// process, so each is guarded by its own mutex.
 int max_lds_bytes()
 {
-    static int cached = -1;
-    if (cached < 0) {
-        int dev = 0, v = 65536;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
-            cached = v;
-        else
-            cached = 65536;
-    }
-    return cached;
+    static std::mutex mu;
+    static std::map<int, int> cached;   // device -> bytes
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cached.find(dev);
+    if (it != cached.end()) return it->second;
+    int v = 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+    cached[dev] = v;
+    return v;
 }
 
 int ring_max_lanes() { return kRingLD; }
@@ -1569,28 +1592,23 @@ int ring_lds_bytes(int q) { return 2 * nx_of(q) * kRingLD * (int)sizeof(double);
 int tile_lds_bytes(int q) { return 2 * nx_of(q) * kTileLD * (int)sizeof(double); }
 // (the rho-only engine exchanges fewer values and uses a prefix of these areas)
 
-// Raise a kernel's dynamic LDS limit above 64 KiB, once per kernel and size
-// (the attribute is per function).
+// Raise a kernel's dynamic LDS limit above 64 KiB, once per device, kernel
+// and size (the attribute is per function; the table is process-wide, so it
+// is updated under a mutex and lattices on several threads may launch).
 static int prep_lds_fn(const void* fn, int bytes)
 {
-    static const void* done_fn[64] = {};
-    static int done_bytes[64] = {};
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, int> done;   // (device, kernel) -> bytes set
     if (bytes <= 65536) return 0;
-    int slot = -1;
-    for (int i = 0; i < 64; i++) {
-        if (done_fn[i] == fn) {
-            if (done_bytes[i] >= bytes) return 0;
-            slot = i;
-            break;
-        }
-        if (!done_fn[i] && slot < 0) slot = i;
-    }
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return (int)e;
-    if (slot >= 0) {
-        done_fn[slot] = fn;
-        done_bytes[slot] = bytes;
-    }
+    std::lock_guard<std::mutex> lock(mu);
+    int& have = done[{dev, fn}];
+    if (have >= bytes) return 0;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return (int)e;
+    have = bytes;
     return 0;
 }
 
@@ -1736,6 +1754,36 @@ int launch_span_set_ctl(int* ctl, int index, int value, void* stream)
 }
 
 int span_ctl_error_index() { return kCtlSticky; }
+int span_ctl_aborts_index() { return kCtlAborts; }
+
+// SPAN owners the current device keeps resident at once: the occupancy of the
+// kernel variant (single-wave workgroups, no LDS) times the compute units.
+// Every owner polls for its neighbours, so all must run at once.
+int64_t span_device_owners(int q, int prec, bool fixed)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int>, int64_t> cached;   // (device, q, prec, fixed)
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(dev, q, prec, fixed ? 1 : 0);
+    auto it = cached.find(key);
+    if (it != cached.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) {
+        if (fixed) {
+            KSLB_DISPATCH_QP(q, prec, (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                           &per_cu, reinterpret_cast<const void*>(k_span<Q_, P_, true>), kSpanLD, 0)));
+        } else {
+            KSLB_DISPATCH_QP(q, prec, (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                           &per_cu, reinterpret_cast<const void*>(k_span<Q_, P_, false>), kSpanLD, 0)));
+        }
+    }
+    const int64_t v = (e == hipSuccess && per_cu > 0 && cus > 0) ? (int64_t)per_cu * cus : 0;
+    cached[key] = v;
+    return v;
+}
 
 int launch_span(int q, int prec, const void* src, void* dst, int64_t n, int nwg, int64_t steps, int s, char* ebase,
                 int64_t ecopy, int64_t slots, int* ctl, const Coef& cf, void* stream, const Ends* ends,
@@ -1791,18 +1839,18 @@ int launch_init_fixed(int q, int prec, void* state, int64_t n, const double* rho
     return (int)hipGetLastError();
 }
 
-int launch_read_rho(int q, int prec, const void* state, int64_t n, double* out, void* stream)
+int launch_read_rho(int q, int prec, const void* state, int64_t n, double* out, void* stream, const int* err)
 {
     KSLB_DISPATCH_QP(q, prec, (k_read_rho<Q_, P_><<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(
-                                  (const char*)state, n, state_pitch(n), out)));
+                                  (const char*)state, n, state_pitch(n), out, err)));
     return (int)hipGetLastError();
 }
 
 int launch_read_f(int q, int prec, const void* state, int64_t n, double* out, int pre, const Coef& cf,
-                  void* stream)
+                  void* stream, const int* err)
 {
     KSLB_DISPATCH_QP(q, prec, (k_read_f<Q_, P_><<<blocks_for(n), 256, 0, (hipStream_t)stream>>>(
-                                  (const char*)state, n, state_pitch(n), out, pre, cf)));
+                                  (const char*)state, n, state_pitch(n), out, pre, cf, err)));
     return (int)hipGetLastError();
 }
 

@@ -51,6 +51,20 @@ def _prec(p) -> int:
     return _lib.PRECISIONS[p] if isinstance(p, str) else int(p)
 
 
+def plan_kernel(n: int, q: int = 7, precision="fp64", fixed_ends: bool = False, kernel="auto",
+                steps_per_launch: int = 0, span_owners: int = 0, lds_bytes: int = 0) -> dict:
+    """Kernel class and launch shape an advance would take (host only; 0 for a
+    limit queries the current device)."""
+    k = _lib.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    ko, spl, ex, wg, ln = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64(), ctypes.c_int()
+    call("kslb_plan_kernel", int(n), int(q), _prec(precision), int(bool(fixed_ends)), k, int(steps_per_launch),
+         int(span_owners), int(lds_bytes), ctypes.byref(ko), ctypes.byref(spl), ctypes.byref(ex), ctypes.byref(wg),
+         ctypes.byref(ln))
+    name = {v: nm for nm, v in _lib.KERNELS.items()}[ko.value]
+    return {"kernel": name, "steps_per_launch": spl.value, "exchange_steps": ex.value,
+            "workgroups": wg.value, "lanes": ln.value}
+
+
 class Lattice:
     """One periodic lattice of ``n`` sites, scheme D1Q``q``, on a GPU."""
 
@@ -215,6 +229,12 @@ class Lattice:
         m, f = ctypes.c_double(), ctypes.c_int()
         call("kslb_diagnostics", self._h, ctypes.byref(m), ctypes.byref(f))
         return m.value, bool(f.value)
+
+    def aborted_launches(self) -> int:
+        """Multi-workgroup launches of this lattice that stopped early (synchronises)."""
+        c = ctypes.c_int64()
+        call("kslb_aborted_launches", self._h, ctypes.byref(c))
+        return c.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -70,7 +70,12 @@ def tune_lattice(n: int, q: int = 7, precision: str = "fp64", steps: int = 2000,
             lat.set_kernel(kind, s)
         except Exception:
             continue
+        aborted = lat.aborted_launches()
         t = _time(lambda: lat.advance(steps))
+        if lat.aborted_launches() != aborted:
+            # a multi-workgroup launch stopped early: its time is not a solve's
+            lat.init_rho(rho0)
+            continue
         cands.append({"kernel": kind, "steps_per_launch": s, "glups": n * steps / t / 1e9})
     best = max(cands, key=lambda c: c["glups"])
     out = {"best": best, "candidates": cands}

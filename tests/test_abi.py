@@ -91,3 +91,86 @@ def test_ensemble_bytes_per_instance_shapes():
     assert lib.kslb_ensemble_create(ctypes.byref(h), 4, ptr(sizes), ptr(bad), ptr(precs), None, 0, None) \
         == _lib.KSLB_EINVAL
     assert "instance 2" in _lib.last_error()
+
+
+# ---------------------------------------------------------------- kernel planning (host only)
+
+from paper_1711_03540_amd.lattice import plan_kernel  # noqa: E402
+
+LDS = 160 * 1024   # one gfx950 workgroup may use the CU's 160 KiB
+
+
+def test_plan_takes_span_when_every_owner_fits():
+    # N = 4096 D1Q7: 86 single-wave owners of 48 sites (192-site windows, 24
+    # steps between exchanges) on a device that keeps 2048 owners resident
+    p = plan_kernel(4096, 7, "fp64", span_owners=2048, lds_bytes=LDS)
+    assert p == {"kernel": "span", "steps_per_launch": p["steps_per_launch"], "exchange_steps": 24,
+                 "workgroups": 86, "lanes": 64}
+    assert p["steps_per_launch"] % 24 == 0 and p["steps_per_launch"] > 10_000
+
+
+def test_plan_refuses_span_beyond_half_the_resident_owners():
+    # a plan uses at most half the owners the device keeps resident: 86
+    # owners need 172
+    assert plan_kernel(4096, 7, "fp64", span_owners=172, lds_bytes=LDS)["workgroups"] == 86
+    # with fewer, AUTO shortens the exchange interval so that wider owners fit
+    # (100 resident: at most 50 owners of 192 - 6 s >= 82 sites, s = 18) ...
+    p = plan_kernel(4096, 7, "fp64", span_owners=100, lds_bytes=LDS)
+    assert p["kernel"] == "span" and p["exchange_steps"] == 18 and p["workgroups"] == 49
+    # ... but not below 12 steps between exchanges: then the one-workgroup
+    # kernel takes the lattice (4096 = 8 sites x 512 lanes) ...
+    p = plan_kernel(4096, 7, "fp64", span_owners=60, lds_bytes=LDS)
+    assert p["kernel"] == "resident" and p["workgroups"] == 1 and p["lanes"] == 512
+    # ... or tiles, where it does not fit one workgroup
+    p = plan_kernel(12345, 7, "fp64", span_owners=64, lds_bytes=LDS)
+    assert p["kernel"] == "tiled" and p["steps_per_launch"] == 64
+    # an explicit SPAN request that cannot fit is refused
+    with pytest.raises(_lib.KslbError) as e:
+        plan_kernel(4096, 7, "fp64", kernel="span", steps_per_launch=24, span_owners=171, lds_bytes=LDS)
+    assert e.value.status == _lib.KSLB_EINVAL and "resident" in str(e.value)
+
+
+def test_plan_fixed_ends_and_small_lds():
+    # fixed ends run on SPAN or PLAIN only
+    assert plan_kernel(301, 5, "fp64", fixed_ends=True, span_owners=2048, lds_bytes=LDS)["kernel"] == "span"
+    assert plan_kernel(1201, 7, "fp64", fixed_ends=True, span_owners=8, lds_bytes=LDS)["kernel"] == "plain"
+    with pytest.raises(_lib.KslbError):
+        plan_kernel(1201, 7, "fp64", fixed_ends=True, kernel="tiled", span_owners=8, lds_bytes=LDS)
+    # without room for the one-workgroup kernel's 96 KiB exchange area AUTO tiles instead
+    assert plan_kernel(4096, 7, "fp64", span_owners=8, lds_bytes=64 * 1024)["kernel"] == "tiled"
+    with pytest.raises(_lib.KslbError):
+        plan_kernel(4096, 7, "fp64", kernel="resident", span_owners=8, lds_bytes=64 * 1024)
+
+
+def test_host_functions_from_many_threads():
+    # distinct calls share no unsynchronised state: host-only entry points
+    # give the same answers from 8 threads at once as from one
+    import threading
+
+    import numpy as np
+    from paper_1711_03540_amd.lattice import scheme_coefficients, stability_check
+    cases = [(q, dX, dT, tau) for q in (5, 7) for dX in (0.1, 0.2) for dT in (1e-4, 1e-5) for tau in (1.0, 1.3)]
+    want = []
+    for q, dX, dT, tau in cases:
+        _, E, G = scheme_coefficients(q, dX, dT, tau)
+        want.append((E, stability_check(q, E, G, 1 / tau, dX, dT, 3.0),
+                     plan_kernel(4096 + 97 * q, q, "fp64", span_owners=2048, lds_bytes=LDS)))
+    errors = []
+
+    def work():
+        try:
+            for _ in range(5):
+                for (q, dX, dT, tau), (E0, s0, p0) in zip(cases, want):
+                    _, E, G = scheme_coefficients(q, dX, dT, tau)
+                    assert np.array_equal(E, E0)
+                    assert stability_check(q, E, G, 1 / tau, dX, dT, 3.0) == s0
+                    assert plan_kernel(4096 + 97 * q, q, "fp64", span_owners=2048, lds_bytes=LDS) == p0
+        except Exception as e:   # pragma: no cover - reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work) for _ in range(8)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors

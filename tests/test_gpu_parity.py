@@ -274,7 +274,7 @@ def test_plain_and_tiled_agree_at_large_size():
     assert torch.equal(a.save_state(), b.save_state())
 
 
-@pytest.mark.parametrize("prec,bound", [("split", 1e-8), ("fp32", 1e-3)])
+@pytest.mark.parametrize("prec,bound", [("split", 1e-8), ("fp32", 1e-5)])
 def test_reduced_precision_error(prec, bound):
     w = CFG_RESIDENT_Q7
     rho0 = w.rho0()
@@ -285,6 +285,78 @@ def test_reduced_precision_error(prec, bound):
         err = rel(lat.rho(), oracle.solve_periodic(7, rho0, w.dX, w.dT, tau, steps))
         say("%s error vs FP64 oracle at %d steps: %.3e" % (prec, steps, err))
         assert err < bound
+
+
+def _fma64(a, b, c):
+    """Fused multiply-add in double, correctly rounded (exact rational arithmetic)."""
+    from fractions import Fraction
+    return float(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
+
+
+def _round_f32(x):
+    """Round an exact rational to the nearest float32, ties to even."""
+    from fractions import Fraction
+    c0 = np.float32(float(x))                 # within one float32 ulp of the answer
+    cands = [c0, np.nextafter(c0, np.float32(np.inf)), np.nextafter(c0, np.float32(-np.inf))]
+    key = lambda c: (abs(Fraction(float(c)) - x), int(np.array(c, dtype=np.float32).view(np.uint32)) & 1)
+    return min(cands, key=key)
+
+
+def _fmaf(a, b, c):
+    from fractions import Fraction
+    return _round_f32(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
+
+
+def test_fp32_step_keeps_density_and_rho2_in_double():
+    # One step of the FP32 storage mode against a numpy emulation of its
+    # stated arithmetic: populations widened to double, the density summed in
+    # double in the kernel's fixed pairwise order, rho^2 and the equilibrium in
+    # double (fused multiply-adds, correctly rounded), then the relaxation
+    # (1 - omega) g + feq as one single-precision fused multiply-add.  Every
+    # stored value must match bitwise.  The same step evaluated entirely in
+    # float32 is further from the exact FP64 step (the oracle's collision).
+    say("case fp32 step emulation")
+    q, n, dX, dT, tau = 7, 301, 0.2, 1e-4, 1.3
+    c = np.array([0, 1, -1, 2, -2, 3, -3])
+    coef = oracle.coefficients(q, dX, dT, tau)
+    rng = np.random.default_rng(42)
+    f0 = oracle.init(q, coef, 1.0 + 0.3 * random_modes_ic(n, n * dX, seed=6))
+    S = (f0 + 1e-2 * rng.standard_normal(f0.shape)).astype(np.float32).astype(np.float64)
+    lat = make(q, n, "fp32", "plain", dX, dT, tau).write_f(S, step=0)
+    assert np.array_equal(lat.f(), S)
+    lat.advance(1)
+    got = lat.f()
+    cf = lat.coefficients()
+    A, B, om = cf["omega"] * cf["E"], cf["omega"] * cf["G"], cf["omega"]
+    a1mw_f = np.float32(1.0 - om)
+    g = np.stack([np.roll(S[i], int(c[i])) for i in range(q)])      # streamed, widened floats
+    want = np.empty_like(S)
+    for j in range(n):
+        x = g[:, j]
+        rho = ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + x[6])
+        r2 = rho * rho
+        eq = np.empty(q)
+        eq[0] = A[0] * rho
+        for ip, im in ((1, 2), (3, 4), (5, 6)):
+            a = A[ip] * rho
+            eq[ip] = _fma64(B[ip], r2, a) if ip < 5 else a
+            eq[im] = _fma64(B[im], r2, a) if im < 5 else a
+        for i in range(q):
+            want[i, j] = float(_fmaf(a1mw_f, np.float32(x[i]), np.float32(eq[i])))
+    mism = int(np.sum(got != want))
+    say("fp32 step: %d of %d stored values differ from the emulation" % (mism, want.size))
+    assert mism == 0
+    # the same step in float32 throughout (density, rho^2, equilibrium, relaxation)
+    g32 = g.astype(np.float32)
+    rho32 = ((g32[0] + g32[1]) + (g32[2] + g32[3])) + ((g32[4] + g32[5]) + g32[6])
+    r232 = rho32 * rho32
+    pure = np.float32(1.0 - om) * g32 + (A.astype(np.float32)[:, None] * rho32 + B.astype(np.float32)[:, None] * r232)
+    exact = oracle.collide(q, coef, tau, g)
+    e_lib, e_pure = float(np.max(np.abs(got - exact))), float(np.max(np.abs(pure - exact)))
+    say("one fp32 step: max error vs the exact FP64 step %.3e (library) vs %.3e (all float32)" % (e_lib, e_pure))
+    assert e_lib < e_pure
+    # rounding feq to single, then the single-precision fused step: at most about one ulp
+    assert e_lib <= 1.5 * float(np.spacing(np.float32(np.max(np.abs(exact)))))
 
 
 def test_ensemble_matches_oracle_and_single_lattices():
@@ -901,8 +973,12 @@ def test_span_abort_path_reports_and_recovers(monkeypatch):
     # failure path of the multi-workgroup kernel, forced from the host: every
     # launch starts with its abort word raised (KSLB_SPAN_INJECT_ABORT=1), so
     # every owner stops at its first exchange and the kernel exits normally;
-    # the sticky error word makes kslb_diagnostics report KSLB_EDEVICE until
-    # the state is replaced, after which the lattice computes correctly again
+    # until the state is replaced the sticky error word makes every host
+    # readout, the checkpoint and the diagnostics report KSLB_EDEVICE and
+    # device readouts NaN, and the abort count (never reset) records the
+    # launch; once the state is replaced the lattice computes correctly again
+    import torch
+
     from paper_1711_03540_amd import KslbError
     say("case span abort path")
     n, dX, dT = 4096, math.pi / 16, 1e-4
@@ -910,17 +986,65 @@ def test_span_abort_path_reports_and_recovers(monkeypatch):
     lat = Lattice(n, 7, "fp64").set_physical(dX, dT, 0.0).set_kernel("span")
     lat.init_rho(rho0)
     assert lat.diagnostics()[1] is False
+    assert lat.aborted_launches() == 0
+    lat.advance(100)
+    assert lat.aborted_launches() == 0
     monkeypatch.setenv("KSLB_SPAN_INJECT_ABORT", "1")
     lat.advance(200)                                   # several exchanges
-    with pytest.raises(KslbError):
-        lat.diagnostics()
-    with pytest.raises(KslbError):
-        lat.diagnostics()                              # sticky
     monkeypatch.delenv("KSLB_SPAN_INJECT_ABORT")
+    for read in (lat.diagnostics, lat.rho, lat.f, lambda: lat.f(pre_collision=True), lat.save_state):
+        with pytest.raises(KslbError) as e:
+            read()
+        assert e.value.status == -3                    # KSLB_EDEVICE, every time (sticky)
+    dev = lat.read_rho()                               # device output: enqueued, poisoned
+    assert bool(torch.isnan(dev).all())
+    lat.advance(50)                                    # later launches leave the error in place
+    with pytest.raises(KslbError):
+        lat.rho()
+    assert lat.aborted_launches() == 1                 # the injected launch; the next returned at once
     lat.init_rho(rho0).advance(200)
     lat.diagnostics()
+    assert lat.aborted_launches() == 1                 # replacing the state does not reset the count
     ref = Lattice(n, 7, "fp64").set_physical(dX, dT, 0.0).set_kernel("plain").init_rho(rho0).advance(200)
     assert np.array_equal(lat.f(), ref.f())
+    assert np.array_equal(lat.rho(), ref.rho())
+
+
+def test_lattices_on_several_threads():
+    # distinct lattices driven from different threads at once, each on its own
+    # stream: the first launches of each kernel set process-wide attributes
+    # (under a lock); every result equals the one computed alone
+    import threading
+
+    import torch
+    say("case lattices on four threads")
+    dX, dT = math.pi / 16, 1e-4
+    shapes = [(20000, 7, "tiled"), (12345, 5, "tiled"), (4096, 7, "resident"), (3000, 7, "span")]
+
+    def solve(n, q, kernel, stream=None):
+        lat = Lattice(n, q, "fp64", stream=stream).set_physical(dX, dT, 0.0).set_kernel(kernel)
+        lat.init_rho(random_modes_ic(n, n * dX, seed=n)).advance(500)
+        return lat.rho()
+
+    want = [solve(*sh) for sh in shapes]
+    got = [None] * len(shapes)
+    errors = []
+
+    def work(k):
+        try:
+            with torch.cuda.stream(torch.cuda.Stream()):
+                got[k] = solve(*shapes[k], stream=torch.cuda.current_stream())
+        except Exception as e:   # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(len(shapes))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for w, g in zip(want, got):
+        assert np.array_equal(w, g)
 
 
 def test_beyond_32_bit_offsets():

@@ -237,6 +237,20 @@ kslb_status kslb_init_rho(kslb_lattice* lat, const double* rho, int rho_on_devic
 /* Enqueue n_steps >= 0 steps of Eq. (2) on the stream (asynchronous).      */
 kslb_status kslb_advance(kslb_lattice* lat, int64_t n_steps);
 
+/* As kslb_advance, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * it allocates nothing, host or device.  The one kernel class that needs
+ * scratch, SPAN, takes its edge slots from a static 64 MiB device array the
+ * library holds on each GPU until the process ends (its address is looked up
+ * on a device's first call) instead of the lattice's exchange area; a longer
+ * advance is split into more launches, with bitwise the same result.  Every
+ * call on one GPU shares that array, which keeps the last call's contents
+ * (each launch refills the slots it uses first): calls whose work overlaps on
+ * one GPU (different streams, not ordered by the caller) race.  ENOMEM when
+ * one exchange of the lattice's SPAN plan needs more than 64 MiB (no
+ * lattice AUTO plans on SPAN does).                                        */
+kslb_status kslb_advance_noalloc(kslb_lattice* lat, int64_t n_steps);
+
 /* rho_j = sum_i f_i(j), the density of section 2 (collision conserves it,
  * so the stored post-collision state gives the same rho), into n_sites
  * doubles (device or host).  Host output synchronises the stream; device

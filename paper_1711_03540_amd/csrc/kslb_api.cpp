@@ -659,7 +659,14 @@ kslb_status kslb_init_rho(kslb_lattice* L, const double* rho, int rho_on_device)
     return KSLB_OK;
 }
 
-kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
+}  // extern "C"
+
+namespace {
+
+// Enqueue n_steps steps.  noalloc: the SPAN kernel's edge slots come from the
+// library's static device area instead of the lattice's exchange area, and
+// nothing is allocated.
+kslb_status advance_impl(kslb_lattice* L, int64_t n_steps, bool noalloc)
 {
     if (auto s = check_lat(L)) return s;
     if (n_steps < 0) return fail(KSLB_EINVAL, "n_steps must be >= 0");
@@ -692,11 +699,23 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
             return fail(KSLB_EINVAL, "shape cannot use the multi-workgroup kernel (at most %lld resident workgroups)",
                         (long long)lim.span_owners);
         const int64_t ecopy = span_edge_copy_bytes(L->q, L->prec, L->n, nwg, sp);
+        const int64_t per = (int64_t)nwg * ecopy;    // edge slots of one exchange
         int64_t slots = 0;
-        if (auto st = span_prepare(L, (int64_t)nwg * ecopy, sp, n_steps, &slots)) return st;
+        char* ebase = nullptr;
+        if (noalloc) {
+            if ((size_t)per > kNoAllocScratchBytes)
+                return fail(KSLB_ENOMEM, "one exchange of this lattice needs %lld bytes of edge slots; the static area "
+                            "of the no-allocation advance holds %zu", (long long)per, kNoAllocScratchBytes);
+            char* area = nullptr;
+            if (int e2 = noalloc_scratch(&area)) return hip_fail(e2, "static exchange area");
+            slots = span_slot_capacity(per, sp, kNoAllocScratchBytes);
+            ebase = area;
+        } else {
+            if (auto st = span_prepare(L, per, sp, n_steps, &slots)) return st;
+            ebase = L->span_scratch;
+        }
         if (auto st = span_ctl_setup(L)) return st;
         int* ctl = L->ctl();
-        char* ebase = L->span_scratch;
         // launches of equal length (to a multiple of sp), each within the slots
         const int64_t cap = std::min<int64_t>(kMaxStepsPerLaunch, (slots + 1) * sp);
         const int64_t nl = (n_steps + cap - 1) / cap;
@@ -735,6 +754,14 @@ kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps)
     L->step += n_steps;
     return KSLB_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps) { return advance_impl(L, n_steps, false); }
+
+kslb_status kslb_advance_noalloc(kslb_lattice* L, int64_t n_steps) { return advance_impl(L, n_steps, true); }
 
 kslb_status kslb_read_rho(kslb_lattice* L, double* out, int out_on_device)
 {

@@ -73,6 +73,10 @@ int span_ctl_error_index();   // sticky: a launch stopped early since the state 
 int span_ctl_aborts_index();  // launches that stopped early since the control block was set up
 // owners of this kernel variant the current device keeps resident (0 if unknown)
 int64_t span_device_owners(int q, int prec, bool fixed);
+// Static edge-slot area of the no-allocation advance, and its device address
+// on the current device (looked up on a device's first call).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+int noalloc_scratch(char** ptr);
 int64_t span_edge_copy_bytes(int q, int prec, int64_t n, int nwg, int s);   // one slot copy
 int launch_span_ctl_init(int* ctl, int count, void* stream);
 int launch_span_set_ctl(int* ctl, int index, int value, void* stream);

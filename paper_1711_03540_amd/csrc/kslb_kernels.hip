@@ -24,9 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <map>
 #include <mutex>
-#include <tuple>
 #include <type_traits>
 #include <utility>
 
@@ -1570,18 +1568,20 @@ size_t state_copy_bytes(int64_t n, int q, int prec)
 }
 
 // Host-side caches below are shared by every lattice and ensemble of the
-// process, so each is guarded by its own mutex.
+// process, so each is guarded by its own mutex.  They are fixed-size tables
+// (no heap allocation after load), indexed by device ordinal.
+constexpr int kMaxDevices = 64;
+
 int max_lds_bytes()
 {
     static std::mutex mu;
-    static std::map<int, int> cached;   // device -> bytes
+    static int cached[kMaxDevices] = {};   // 0: not queried yet
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 65536;
     std::lock_guard<std::mutex> lock(mu);
-    auto it = cached.find(dev);
-    if (it != cached.end()) return it->second;
+    if (cached[dev] > 0) return cached[dev];
     int v = 65536;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
     cached[dev] = v;
     return v;
 }
@@ -1597,18 +1597,27 @@ int tile_lds_bytes(int q) { return 2 * nx_of(q) * kTileLD * (int)sizeof(double);
 // is updated under a mutex and lattices on several threads may launch).
 static int prep_lds_fn(const void* fn, int bytes)
 {
+    struct Done {
+        int dev;
+        const void* fn;
+        int bytes;
+    };
     static std::mutex mu;
-    static std::map<std::pair<int, const void*>, int> done;   // (device, kernel) -> bytes set
+    static Done done[512];   // (device, kernel) -> bytes set; a full table only repeats the call
+    static int used = 0;
     if (bytes <= 65536) return 0;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return (int)e;
     std::lock_guard<std::mutex> lock(mu);
-    int& have = done[{dev, fn}];
-    if (have >= bytes) return 0;
+    Done* d = nullptr;
+    for (int i = 0; i < used; i++)
+        if (done[i].dev == dev && done[i].fn == fn) d = &done[i];
+    if (d && d->bytes >= bytes) return 0;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return (int)e;
-    have = bytes;
+    if (!d && used < 512) d = &done[used++];
+    if (d) *d = Done{dev, fn, bytes};
     return 0;
 }
 
@@ -1762,13 +1771,12 @@ int span_ctl_aborts_index() { return kCtlAborts; }
 int64_t span_device_owners(int q, int prec, bool fixed)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int>, int64_t> cached;   // (device, q, prec, fixed)
+    static int64_t cached[kMaxDevices][2][4][2];   // (device, q, prec, fixed); 0: not queried yet
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices || prec < 0 || prec > 3) return 0;
     std::lock_guard<std::mutex> lock(mu);
-    const auto key = std::make_tuple(dev, q, prec, fixed ? 1 : 0);
-    auto it = cached.find(key);
-    if (it != cached.end()) return it->second;
+    int64_t& slot = cached[dev][q == 7][prec][fixed ? 1 : 0];
+    if (slot > 0) return slot;
     int per_cu = 0, cus = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) {
@@ -1781,7 +1789,7 @@ int64_t span_device_owners(int q, int prec, bool fixed)
         }
     }
     const int64_t v = (e == hipSuccess && per_cu > 0 && cus > 0) ? (int64_t)per_cu * cus : 0;
-    cached[key] = v;
+    slot = v;
     return v;
 }
 
@@ -1821,6 +1829,34 @@ int launch_span(int q, int prec, const void* src, void* dst, int64_t n, int nwg,
                                       epitch, slots, ctl, cf, 0.0, 0.0)));
     }
     return (int)hipGetLastError();
+}
+
+// Edge slots for callers that cannot allocate (kslb_advance_noalloc): a
+// file-scope device array each GPU holds until the process ends.  Host code
+// never passes its name to a kernel: in host code the name is a host-side
+// stand-in, so the array's device address is looked up once per device and
+// that address is what kernels receive.  Every caller on one device shares
+// it; calls that overlap on a device race.
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+int noalloc_scratch(char** ptr)
+{
+    static std::mutex mu;
+    static char* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        addr[dev] = static_cast<char*>(p);
+    }
+    *ptr = addr[dev];
+    return 0;
 }
 
 int launch_plain_fixed(int q, int prec, const void* src, void* dst, int64_t n, const Coef& cf, const Ends& ends,

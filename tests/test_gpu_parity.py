@@ -274,7 +274,8 @@ def test_plain_and_tiled_agree_at_large_size():
     assert torch.equal(a.save_state(), b.save_state())
 
 
-@pytest.mark.parametrize("prec,bound", [("split", 1e-8), ("fp32", 1e-5)])
+# measured on MI355X: split 1.8e-10 / 2.6e-10, fp32 6.3e-7 / 8.8e-7 at 1000 / 2000 steps
+@pytest.mark.parametrize("prec,bound", [("split", 2e-9), ("fp32", 3e-6)])
 def test_reduced_precision_error(prec, bound):
     w = CFG_RESIDENT_Q7
     rho0 = w.rho0()

@@ -1,17 +1,24 @@
 """Benchmark of the KS lattice Boltzmann hot path on one MI355X.
 
-One benchmark "step" is one whole solve of the workload: equilibrium init from
-a density already resident in HBM, the configured number of LB steps, and the
-density readout into HBM.  The default workload is the improved D1Q7 scheme,
-FP64, N = 4096 periodic sites on L = 256 pi (dX = pi/16), 16 random Fourier
-modes of amplitude 0.1, dT = 1e-4 with the paper's fitted tau, 10^5 LB steps
-per solve, one instance (the multi-workgroup register-resident kernel: one
-wave per owner, edges exchanged through memory every 24 steps).
+Default run: the largest single-GPU configuration, one D1Q7 lattice (the
+paper's improved scheme) of N = 2^24 periodic sites on L = 32 pi 2^12
+(dX = pi/128), 16 random Fourier modes of amplitude 0.1, dT = 2e-8, tau = 1,
+FP64, 10^3 LB steps per solve on the halo-tiled kernel.  One benchmark step is
+one whole solve: equilibrium init from a density already resident in HBM, the
+LB steps, and the density readout into HBM.
 
-Prints one JSON line: throughput in site-updates/s (GLUPS), per-solve p50/p99
-latency, the plain one-step-per-launch kernel on the same workload (bitwise
-identical results), the roofline of the dominant kernel, and the CPU oracle
-timed on the host.
+The one JSON line also carries, for that lattice, the one-step (s = 1) kernel
+and its fraction of the HBM roofline, the measured device peaks (a STREAM copy
+and an LDS read microbenchmark) and the FP64 CPU oracle timed on a bounded
+sample; and, as sub-objects under "configs", the other configurations, each
+with its throughput, latency, roofline and CPU-oracle baseline: D1Q5 N = 256
+and D1Q7 N = 4096 single lattices (the multi-workgroup kernel), the ragged
+4096-instance ensemble in FP64 and FP32, and the served request stream at
+2000 requests/s with a sweep of offered loads.
+
+Other --workload values print their own JSON: a single configuration, or one
+of the studies (table3, taumin, profiles, stats, lyapunov, lyapunov_spectrum,
+serve_sweep).
 """
 from __future__ import annotations
 
@@ -26,10 +33,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "GLUPS vs plain kernel at matched error; % HBM/LDS peak; p50/p99 solve latency"
+
 # Published MI355X peaks.
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 N_CU = 256
+N_SIMD = 4 * N_CU
+CLOCK_GHZ = 2.4
+TARGET_HBM_FRAC = 0.70      # the one-step kernel on the large lattice
+
 
 # Algorithmic flops of one site update (an FMA counts 2).  Population
 # storage: density Q-1 adds; rho^2 1 mul; A_i rho 1 mul for c = 0 and one per
@@ -45,6 +58,18 @@ def flops_per_site_update(q: int, precision: str = "fp64") -> int:
     return (q - 1) + (2 + (q - 1) // 2) + 2 * (with_g + q)
 
 
+# FP64 VALU instructions of one site update (each add, mul or FMA one issue):
+# D1Q7 6 + 5 + 11 = 22, D1Q5 4 + 4 + 9 = 17.  A wave64 FP64 instruction issues
+# in 4 clocks on a 16-lane SIMD, so one SIMD retires 16 / 22 D1Q7 updates per
+# clock: 1024 SIMDs x 2.4 GHz x 16 / 22 = 1.79e12 updates/s is the VALU ceiling.
+def valu_per_site_update(q: int) -> int:
+    return {7: 22, 5: 17}[q]
+
+
+def valu_ceiling_glups(q: int, simds: int = N_SIMD) -> float:
+    return simds * CLOCK_GHZ * 16.0 / valu_per_site_update(q)
+
+
 # Algorithmic HBM bytes of one s = 1 step per site: read Q populations and
 # write Q populations of the storage format.
 def bytes_per_site_update(q: int, precision: str) -> int:
@@ -52,11 +77,13 @@ def bytes_per_site_update(q: int, precision: str) -> int:
 
 
 WORKLOADS = {
+    "all": (None, None),
+    "d1q7_n16m": ("CFG_LARGE_Q7", "tiled"),
     "d1q7_n4096": ("CFG_RESIDENT_Q7", "span"),
     "d1q5_n256": ("CFG_SMALL_Q5", "span"),
-    "d1q7_n16m": ("CFG_LARGE_Q7", "tiled"),
     "ensemble": (None, None),
     "serve": (None, None),
+    "serve_sweep": (None, None),
     "table3": (None, None),
     "stats": (None, None),
     "taumin": (None, None),
@@ -69,9 +96,9 @@ WORKLOADS = {
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100, help="timed solves (p50/p99 latency over them)")
+    ap.add_argument("--steps", type=int, default=20, help="timed solves of the headline lattice (p50/p99 over them)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed solves")
-    ap.add_argument("--workload", default="d1q7_n4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="all", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "split", "rho"])
     ap.add_argument("--kernel", default=None, choices=["span", "resident", "tiled", "plain"])
     ap.add_argument("--tile-steps", type=int, default=0)
@@ -80,11 +107,16 @@ def parse():
                     help="pick the kernel class and steps per launch (lattice workloads) or the ensemble "
                          "tiling with the autotuner before timing (no cache)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the device-peak microbenchmarks")
     ap.add_argument("--instances", type=int, default=4096, help="ensemble workload: instances")
     ap.add_argument("--lb-steps", type=int, default=20000, help="ensemble workload: LB steps per instance")
     ap.add_argument("--chunk", type=int, default=0, help="ensemble/serve: steps per launch (0 = default)")
     ap.add_argument("--segments", type=int, default=0, help="ensemble: instance tiles per window (0 = default)")
     ap.add_argument("--requests", type=int, default=2000, help="serve workload: requests")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve workload: offered requests per second")
+    ap.add_argument("--rates", default="250,500,1000,2000", help="serve_sweep: offered requests per second")
+    ap.add_argument("--sweep-requests", type=int, default=1000, help="serve_sweep: requests per offered load")
+    ap.add_argument("--budget-gib", type=float, default=4.0, help="serve: device-memory budget of admitted state")
     ap.add_argument("--round-steps", type=int, default=0, help="serve workload: steps per scheduling round (0 = default)")
     ap.add_argument("--serve-fp32", default="fp32", choices=["fp32", "split"],
                     help="serve workload: storage of the FP32 requests")
@@ -92,6 +124,10 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (reference kernel for HBM counters)")
     return ap.parse_args()
+
+
+def log(msg: str) -> None:
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def calibrate_copy():
@@ -128,34 +164,255 @@ def measured_traffic(kname: str, workload: str, precision: str):
     return e["fetch_bytes"] + e["write_bytes"]
 
 
-def cpu_baseline(w, tau):
-    """The FP64 CPU oracle on one full solve of the workload (single thread)."""
+# ---------------------------------------------------------------- CPU oracle baselines
+
+def host_info() -> dict:
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def cpu_threads() -> int:
+    """Worker threads for the multi-instance oracle legs: the host's cores, at
+    most 16 (one GPU's share of a GPU host)."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_lattice(w, tau, budget_s: float = 10.0):
+    """The FP64 CPU oracle on one lattice of the workload (single thread): the full
+    solve, or its first steps when that would take longer than about budget_s."""
     import numpy as np
 
     import oracle
     rho0 = w.rho0()
     steps = w.steps
     sample = "one full solve: %d sites x %d steps" % (w.n, steps)
-    if w.n * steps > 6e8:      # bound the CPU leg to roughly 10-20 s
-        steps = max(1, int(4e8 // w.n))
-        sample = "%d sites x %d of the %d steps" % (w.n, steps, w.steps)
-    # the median of up to 5 trials, stopping once 15 s of CPU work is done
+    est_rate = 6e7                             # site updates per second of one core (planning figure)
+    if w.n * steps > budget_s * est_rate:
+        steps = max(1, int(budget_s * est_rate // w.n))
+        sample = "%d sites x the first %d of %d steps" % (w.n, steps, w.steps)
     times = []
-    while len(times) < 5 and sum(times) < 15.0:
+    while len(times) < 5 and sum(times) < budget_s:
         t0 = time.perf_counter()
         oracle.solve_periodic(w.q, rho0, w.dX, w.dT, tau, steps)
         times.append(time.perf_counter() - t0)
     dt = float(np.median(times))
     return {"value": w.n * steps / dt / 1e9, "unit": "GLUPS", "cores": 1, "kind": "oracle",
-            "sample": sample + ", plain C FP64 oracle, median of %d trials: %.2f s" % (len(times), dt),
-            "trials_s": times}
+            "sample": sample + ", plain C FP64 oracle, median of %d trials: %.2f s (initialisation included)"
+            % (len(times), dt), "trials_s": times, "host": host_info()}
 
 
-def bench_ensemble(args):
-    """Ragged ensemble: D1Q7 instances, N log-uniform in [512, 8192], dX = pi/16, dT = 1e-4,
-    fitted tau, `--lb-steps` steps each; one solve = batched init from densities in
-    HBM, the steps, batched density readout into HBM; throughput against the plain
-    one-step kernel."""
+def cpu_many(jobs, budget_s: float = 10.0):
+    """The FP64 CPU oracle on independent solves (q, rho0, dX, dT, tau, steps),
+    spread over cpu_threads() threads (the oracle releases the interpreter while
+    it runs); the steps of every job are scaled down together when the whole
+    sample would take longer than about budget_s.  Returns the rate and the
+    scale applied."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    threads = cpu_threads()
+    su = sum(len(j[1]) * j[5] for j in jobs)
+    est = su / (6e7 * threads)
+    scale = min(1.0, budget_s / est) if est > 0 else 1.0
+    jobs = [(q, r, dX, dT, tau, max(1, int(steps * scale))) for q, r, dX, dT, tau, steps in jobs]
+    su = sum(len(j[1]) * j[5] for j in jobs)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        list(pool.map(lambda j: oracle.solve_periodic(j[0], j[1], j[2], j[3], j[4], j[5]), jobs))
+    dt = time.perf_counter() - t0
+    return {"value": su / dt / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle", "seconds": dt,
+            "site_updates": su, "step_scale": scale, "host": host_info()}
+
+
+# ---------------------------------------------------------------- device peaks
+
+def device_peaks() -> dict:
+    """Measured HBM copy bandwidth and LDS read bytes per clock per CU
+    (libkslb_probe), beside the published figures."""
+    from paper_1711_03540_amd import probe
+    hbm = probe.hbm_copy(4 << 30, reps=10)
+    lds = probe.lds_bandwidth()
+    log("peaks: copy %.0f GB/s, LDS %.1f B/clk/CU at %.2f GHz" %
+        (hbm["best_gb_s"], lds["bytes_per_clk_per_cu"], lds["shader_ghz"]))
+    return {"hbm_copy": hbm, "hbm_published_gb_s": PEAK_HBM_GBS, "lds": lds,
+            "fp64_vector_published_tflops": PEAK_FP64_VECTOR_TFLOPS}
+
+
+# ---------------------------------------------------------------- one lattice
+
+def run_lattice(w, precision, kernel, solves, warmup, tile_steps=0, autotune=False, plain=True, cpu=True,
+                peaks=None):
+    """Time `solves` whole solves of one lattice (init from rho0 in HBM, w.steps LB
+    steps, readout into HBM) and describe the dominant kernel against its roofline."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03540_amd.lattice import Lattice
+
+    dev = torch.device("cuda:0")
+    log("workload %s q=%d n=%d steps/solve=%d precision=%s kernel=%s" %
+        (w.name, w.q, w.n, w.steps, precision, kernel))
+    rho0 = torch.tensor(w.rho0(), dtype=torch.float64, device=dev)
+    rho_out = torch.empty(w.n, dtype=torch.float64, device=dev)
+    lat = Lattice(w.n, w.q, precision, device=dev)
+    lat.set_physical(w.dX, w.dT, 0.0)
+    lat.set_kernel(kernel, tile_steps)
+    tuned = None
+    if autotune:
+        from paper_1711_03540_amd import tune
+        tuned = tune.tune_lattice(w.n, w.q, precision, steps=min(w.steps, 2000), dX=w.dX, dT=w.dT, cache=None)
+        tune.apply_lattice(lat, tuned)
+        kernel = tuned["best"]["kernel"]
+        log("autotuned %s" % tuned["best"])
+    tau = lat.coefficients()["tau"]
+    stream = lat.stream
+
+    def solve(ev=None):
+        lat.init_rho(rho0)
+        if ev is not None:
+            ev[0].record(stream)
+        lat.advance(w.steps)
+        if ev is not None:
+            ev[1].record(stream)
+        lat.read_rho(rho_out)
+
+    for _ in range(warmup):
+        solve()
+    torch.cuda.synchronize()
+    aborted0 = lat.aborted_launches()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(solves)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(solves)]
+    kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(solves)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(solves):
+        starts[k].record(stream)
+        solve(kev[k])
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    # every timed solve must have run to completion: no multi-workgroup launch
+    # may have stopped early, and the last readout must be finite
+    if lat.aborted_launches() != aborted0:
+        raise SystemExit("bench: a multi-workgroup launch stopped early during the timed solves")
+    if not bool(torch.isfinite(rho_out).all()):
+        raise SystemExit("bench: non-finite density")
+    lat_ms = np.array([starts[k].elapsed_time(ends[k]) for k in range(solves)])
+    adv_ms = np.array([kev[k][0].elapsed_time(kev[k][1]) for k in range(solves)])
+    site_updates = w.n * w.steps
+    value = site_updates * solves / total / 1e9
+    mass, bad = lat.diagnostics()
+    if bad:
+        raise SystemExit("bench: non-finite state")
+
+    # launches per advance and the dominant kernel's average duration, from
+    # the launch shape the library resolved for this lattice
+    shape = lat.kernel()
+    assert shape["kernel"] == kernel, shape
+    launches = math.ceil(w.steps / shape["steps_per_launch"])
+    units = w.n * w.steps / launches
+    kname = {"resident": "k_ring", "span": "k_span", "tiled": "k_tile", "plain": "k_plain"}[kernel]
+    kernel_ms = float(np.mean(adv_ms)) / launches
+    if kernel == "plain":
+        ach = bytes_per_site_update(w.q, precision) * units / (kernel_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None}
+    else:
+        ach = flops_per_site_update(w.q, precision) * units / (kernel_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": None}
+        glups_kernel = units / (kernel_ms * 1e-3) / 1e9
+        roof["valu_ceiling_glups"] = valu_ceiling_glups(w.q)
+        roof["frac_of_valu_ceiling"] = glups_kernel / valu_ceiling_glups(w.q)
+        if kernel in ("resident", "span"):
+            # execution resources the launch can use: one workgroup of 8 waves
+            # on one CU (4 SIMDs) for resident; one single-wave owner per SIMD
+            # for span
+            simds = 4 if kernel == "resident" else shape["workgroups"]
+            if kernel == "span":
+                roof["steps_between_exchanges"] = shape["exchange_steps"]
+                roof["workgroups"] = simds
+            roof["simds_used"] = simds
+            roof["frac_of_used_simds"] = ach / (PEAK_FP64_VECTOR_TFLOPS * simds / N_SIMD)
+            roof["frac_of_used_simds_valu_ceiling"] = glups_kernel / valu_ceiling_glups(w.q, simds)
+            roof["ns_per_step"] = kernel_ms * 1e6 / (w.steps / launches)
+    roof["traffic"] = measured_traffic(kname, w.name, precision)
+    roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    roof["traffic_algorithmic"] = bytes_per_site_update(w.q, precision) * w.n
+    roof["kernel"] = kname
+    roof["launch_shape"] = shape
+    roof["kernel_ms_avg"] = kernel_ms
+    roof["algorithmic_per_site_update"] = (flops_per_site_update(w.q, precision) if kernel != "plain"
+                                           else bytes_per_site_update(w.q, precision))
+    roof["units_per_launch"] = units
+
+    out = {
+        "value": value, "unit": "GLUPS", "solves": solves, "warmup": warmup,
+        "ms_per_solve": total / solves * 1e3,
+        "config": {"workload": w.name, "scheme": "D1Q%d" % w.q, "n_sites": w.n, "lb_steps_per_solve": w.steps,
+                   "dX": w.dX, "dT": w.dT, "tau": tau, "precision": precision, "kernel": kernel, "instances": 1},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "min": float(lat_ms.min())},
+        "roofline": roof,
+        "autotuned": tuned["best"] if tuned else None,
+    }
+    if plain and kernel != "plain":
+        # plain one-step-per-launch kernel on the same lattice; bitwise identical results
+        chk = min(w.steps, 2000 if w.n < (1 << 20) else 130)
+        ref = Lattice(w.n, w.q, precision, device=dev).set_physical(w.dX, w.dT, 0.0).set_kernel("plain")
+        ref.init_rho(rho0).advance(chk)
+        lat.init_rho(rho0).advance(chk)
+        same = bool(torch.equal(ref.save_state(), lat.save_state()))
+        psteps = min(w.steps, 5000 if w.n < (1 << 20) else 200)
+        ref.advance(psteps)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ref.stream)
+        ref.advance(psteps)
+        e1.record(ref.stream)
+        torch.cuda.synchronize()
+        pg = w.n * psteps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        hbm = pg * bytes_per_site_update(w.q, precision)     # GB/s, algorithmic bytes
+        pk = {"kernel": "k_plain", "glups": pg, "timed_lb_steps": psteps, "speedup": value / pg,
+              "bitwise_identical_state_after_%d_steps" % chk: same,
+              "hbm_gb_s": hbm, "hbm_frac": hbm / PEAK_HBM_GBS}
+        if w.n >= (1 << 20):
+            pk["hbm_frac_target"] = TARGET_HBM_FRAC
+            pk["meets_target"] = hbm / PEAK_HBM_GBS >= TARGET_HBM_FRAC
+            if peaks:
+                pk["hbm_frac_of_measured_copy"] = hbm / peaks["hbm_copy"]["best_gb_s"]
+        out["plain_kernel"] = pk
+        ref.close()
+        del ref
+    # the one-step HBM roofline (2 Q b bytes per site update at 8 TB/s) that
+    # temporal blocking lifts the solve above
+    s1 = PEAK_HBM_GBS / bytes_per_site_update(w.q, precision)
+    out["s1_hbm_roofline_glups"] = s1
+    out["vs_s1_hbm_roofline"] = value / s1
+    lat.close()
+    del lat
+    torch.cuda.synchronize()
+    if cpu:
+        out["cpu_baseline"] = cpu_lattice(w, tau)
+        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    return out
+
+
+# ---------------------------------------------------------------- ragged ensemble
+
+def run_ensemble(precision, instances, lb_steps, solves=3, warmup=1, chunk=0, segments=0, autotune=False,
+                 cpu=True):
+    """Ragged ensemble: D1Q7 instances, N log-uniform in [512, 8192], dX = pi/16,
+    dT = 1e-4, fitted tau, lb_steps steps each; one solve = batched init from
+    densities in HBM, the steps, batched density readout into HBM; throughput
+    against the plain one-step kernel on one instance of the mean size."""
     import numpy as np
     import torch
 
@@ -164,81 +421,121 @@ def bench_ensemble(args):
     from paper_1711_03540_amd.lattice import Lattice
 
     dev = torch.device("cuda:0")
-    sizes = inputs.ensemble_shapes(args.instances, seed=2)
+    sizes = inputs.ensemble_shapes(instances, seed=2)
     dX, dT = math.pi / 16, 1e-4
-    ens = Ensemble(sizes, 7, args.precision, device=dev).set_physical(dX, dT, 0.0)
-    ens.set_tiling(0, args.segments, args.chunk)
+    log("ensemble %d instances %s, %d steps" % (instances, precision, lb_steps))
+    ens = Ensemble(sizes, 7, precision, device=dev).set_physical(dX, dT, 0.0)
+    ens.set_tiling(0, segments, chunk)
     tuned = None
-    if args.autotune:
+    if autotune:
         from paper_1711_03540_amd import tune
-        tuned = tune.tune_ensemble(sizes, 7, args.precision, cache=None)
+        tuned = tune.tune_ensemble(sizes, 7, precision, cache=None)
         tune.apply_ensemble(ens, tuned)
-        print("bench: autotuned ensemble tiling %s" % tuned["best"], file=sys.stderr, flush=True)
-    rho0 = [torch.tensor(inputs.random_modes_ic(int(n), n * dX, seed=1000 + i), device=dev)
-            for i, n in enumerate(sizes)]
-    rho_all = torch.cat(rho0)          # every instance's density, resident in HBM
+        log("autotuned ensemble tiling %s" % tuned["best"])
+    ics = [inputs.random_modes_ic(int(n), n * dX, seed=1000 + i) for i, n in enumerate(sizes)]
+    rho_all = torch.tensor(np.concatenate(ics), device=dev)       # every instance's density, in HBM
     rho_out = torch.empty_like(rho_all)
-    steps = np.full(len(sizes), args.lb_steps, dtype=np.int64)
-    su = float(np.sum(sizes)) * args.lb_steps
+    steps = np.full(len(sizes), lb_steps, dtype=np.int64)
+    su = float(np.sum(sizes)) * lb_steps
+    stream = ens.stream
 
     def solve():
         ens.init_rho_all(rho_all)       # one init launch for the whole ensemble
         ens.advance(steps)
         ens.rho_all(rho_out)            # one readout launch, into HBM
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         solve()
     torch.cuda.synchronize()
-    times = []
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(solves)]
+    t0 = time.perf_counter()
+    for k in range(solves):
+        ev[k][0].record(stream)
         solve()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    value = su * args.steps / sum(times) / 1e9
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    if not bool(torch.isfinite(rho_out).all()):
+        raise SystemExit("bench: non-finite ensemble density")
+    sol_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    value = su * solves / total / 1e9
+    tau = ens.tau
     # reduced storage: error of the smallest, median and largest instance
     # after the last solve against the same instances in GPU FP64 (norm-wise,
     # max |rho - rho_64| / max |rho_64|; FP64 itself is pinned to the oracle
     # by the parity tests)
     errors = None
-    if args.precision != "fp64":
+    if precision != "fp64":
         order = np.argsort(sizes, kind="stable")
         pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
         ref = Ensemble([int(sizes[i]) for i in pick], 7, "fp64", device=dev).set_physical(dX, dT, 0.0)
         for k, i in enumerate(pick):
-            ref.init_rho(k, rho0[i])
-        ref.advance(args.lb_steps)
+            ref.init_rho(k, torch.tensor(ics[i], device=dev))
+        ref.advance(lb_steps)
         errors = {}
+        out_host = rho_out.cpu().numpy()
+        offs = np.concatenate([[0], np.cumsum(sizes)])
         for tag, k, i in zip(("smallest", "median", "largest"), range(3), pick):
-            r64, got = ref.rho(k), ens.rho(i)
+            r64, got = ref.rho(k), out_host[offs[i]:offs[i + 1]]
             errors[tag] = {"instance": i, "n": int(sizes[i]),
                            "rel_err_vs_gpu_fp64": float(np.max(np.abs(got - r64)) / np.max(np.abs(r64)))}
+        ref.close()
     # plain one-step kernel, one instance of the mean size (bitwise-identical arithmetic)
     nm = int(np.mean(sizes))
-    lat = Lattice(nm, 7, args.precision, device=dev).set_physical(dX, dT, 0.0).set_kernel("plain")
+    lat = Lattice(nm, 7, precision, device=dev).set_physical(dX, dT, 0.0).set_kernel("plain")
     lat.init_rho(inputs.random_modes_ic(nm, nm * dX, seed=7)).advance(200)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat.advance(2000)
     torch.cuda.synchronize()
     plain = nm * 2000 / (time.perf_counter() - t0) / 1e9
-    out = {"workload": "ensemble_d1q7_%d" % len(sizes), "precision": args.precision, "value": value,
-           "unit": "GLUPS", "ms_per_solve": 1e3 * sum(times) / len(times), "site_updates_per_solve": su,
-           "instances": len(sizes), "mean_n": float(np.mean(sizes)), "lb_steps": args.lb_steps,
-           "plain_one_instance_glups": plain, "speedup_vs_plain": value / plain, "tau": ens.tau,
+    lat.close()
+    fl = flops_per_site_update(7, precision)
+    ach = fl * su / (float(np.mean(sol_ms)) * 1e-3) / 1e12
+    out = {"workload": "ensemble_d1q7_%d" % len(sizes), "precision": precision, "value": value,
+           "unit": "GLUPS", "ms_per_solve": 1e3 * total / solves, "solves": solves, "warmup": warmup,
+           "site_updates_per_solve": su, "instances": len(sizes), "mean_n": float(np.mean(sizes)),
+           "lb_steps": lb_steps, "tau": tau,
+           "latency_ms": {"p50": float(np.percentile(sol_ms, 50)), "p99": float(np.percentile(sol_ms, 99))},
+           "plain_one_instance_glups": plain, "speedup_vs_plain": value / plain,
            "errors": errors, "autotuned": tuned["best"] if tuned else None,
            # algorithmic flops of the site updates (halo re-computation not
-           # counted) over the solve time, against the chip's FP64 vector peak
-           "roofline": {"bound": "alu", "achieved": flops_per_site_update(7, args.precision) * value / 1e3,
-                        "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                        "frac": flops_per_site_update(7, args.precision) * value / 1e3 / PEAK_FP64_VECTOR_TFLOPS}}
-    print(json.dumps(out), flush=True)
+           # counted) over the solve time from HIP events on the ensemble's
+           # stream (init and readout included), against the FP64 vector peak
+           "roofline": {"bound": "alu", "kernel": "k_ens", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS,
+                        "frac_of_valu_ceiling": su / (float(np.mean(sol_ms)) * 1e-3) / 1e9 / valu_ceiling_glups(7),
+                        "traffic": None}}
+    ens.close()
+    if cpu:
+        # a seeded 64-instance subset of the same ensemble, extrapolated
+        from paper_1711_03540_amd.inputs import SplitMix64
+        sm = SplitMix64(64)
+        pick = []
+        while len(pick) < min(64, len(sizes)):
+            i = int(sm.uniform() * len(sizes))
+            if i not in pick:
+                pick.append(i)
+        jobs = [(7, ics[i], dX, dT, tau, lb_steps) for i in pick]
+        cb = cpu_many(jobs)
+        cb["sample"] = ("a seeded subset of %d of the %d instances (N %d..%d), %d of the %d steps each, on %d "
+                        "threads; the whole ensemble extrapolated at that rate" %
+                        (len(pick), len(sizes), int(min(sizes[pick])), int(max(sizes[pick])),
+                         max(1, int(lb_steps * cb["step_scale"])), lb_steps, cb["cores"]))
+        cb["extrapolated_solve_s"] = su / (cb["value"] * 1e9)
+        out["cpu_baseline"] = cb
+        out["gpu_over_cpu"] = value / cb["value"]
+    return out
 
 
-def bench_serve(args):
-    """Served request stream: Poisson arrivals at 2000/s, D1Q5/D1Q7, N log-uniform in
-    [256, 65536], 10^3..10^5 steps, FP32 (FP32 storage by default, `--serve-fp32 split`
-    for the split storage) or FP64, dX = pi/16, dT = 1e-4."""
+# ---------------------------------------------------------------- serving
+
+def run_serve(rate, requests, budget_gib=4.0, chunk=0, round_steps=0, serve_fp32="fp32", cpu=True):
+    """Served request stream: Poisson arrivals at `rate`/s (the seeded stream of
+    2000/s with its arrival times scaled), D1Q5/D1Q7, N log-uniform in [256,
+    65536], 10^3..10^5 steps, FP32 (FP32 storage by default, split with
+    serve_fp32="split") or FP64, dX = pi/16, dT = 1e-4; admission by a device
+    memory budget of budget_gib."""
     import numpy as np
     import torch
 
@@ -247,20 +544,74 @@ def bench_serve(args):
 
     dev = torch.device("cuda:0")
     dX, dT = math.pi / 16, 1e-4
-    reqs = inputs.request_stream(args.requests, seed=3)
+    reqs = inputs.request_stream(requests, seed=3)
+    for r in reqs:                               # the same requests at another offered rate
+        r.arrival *= 2000.0 / rate
+    log("serve %d requests at %.0f/s" % (requests, rate))
     init = [torch.tensor(inputs.random_modes_ic(r.n, r.n * dX, seed=r.seed % (1 << 63)), device=dev)
             for r in reqs]
-    srv = SolveServer(dX, dT, chunk=args.chunk or 64, round_steps=args.round_steps or 256, device=dev,
-                      fp32_storage=args.serve_fp32)
+    srv = SolveServer(dX, dT, budget_bytes=int(budget_gib * (1 << 30)), chunk=chunk or 64,
+                      round_steps=round_steps or 256, device=dev, fp32_storage=serve_fp32)
     warm = inputs.request_stream(8, seed=99, steps_lo=1000, steps_hi=1000)
     srv.serve(warm, [torch.tensor(inputs.random_modes_ic(r.n, r.n * dX, seed=5), device=dev) for r in warm],
               realtime=False)
     st = srv.serve(reqs, init, realtime=True)
-    out = {"workload": "serve_%d_requests" % len(reqs), "fp32_requests_storage": args.serve_fp32,
-           "offered_glups": float(
-        sum(r.n * r.steps for r in reqs) / reqs[-1].arrival / 1e9)}
+    su = {5: 0.0, 7: 0.0}
+    for r in reqs:
+        su[r.q] += r.n * r.steps
+    flops = sum(flops_per_site_update(q) * v for q, v in su.items())
+    out = {"workload": "serve_%d_requests" % len(reqs), "rate_per_s": rate,
+           "fp32_requests_storage": serve_fp32, "budget_bytes": srv.arena.size,
+           "offered_glups": float(sum(r.n * r.steps for r in reqs) / reqs[-1].arrival / 1e9)}
     out.update(st.summary())
-    print(json.dumps(out), flush=True)
+    out["value"] = out["achieved_glups"]
+    out["unit"] = "GLUPS"
+    out["latency_ms"] = {"p50": out["p50_ms"], "p99": out["p99_ms"]}
+    # the ensemble kernel's work (algorithmic flops of the site updates) over
+    # the wall time of the whole served stream
+    ach = flops / st.wall / 1e12
+    out["roofline"] = {"bound": "alu", "kernel": "k_ens", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                       "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": None}
+    if cpu:
+        # the oracle on a seeded sample of 16 of the requests (FP64 arithmetic for all)
+        from paper_1711_03540_amd.inputs import SplitMix64
+        sm = SplitMix64(16)
+        pick = []
+        while len(pick) < min(16, len(reqs)):
+            i = int(sm.uniform() * len(reqs))
+            if i not in pick:
+                pick.append(i)
+        jobs = []
+        for i in pick:
+            r = reqs[i]
+            tau = 1.0 if r.q == 5 else 0.0
+            if tau <= 0.0:
+                from paper_1711_03540_amd.lattice import tau_fit
+                tau = tau_fit(7, dX, dT)
+            jobs.append((r.q, init[i].cpu().numpy(), dX, dT, tau, r.steps))
+        cb = cpu_many(jobs)
+        part = "all" if cb["step_scale"] >= 1.0 else "a fraction %.3g" % cb["step_scale"]
+        cb["sample"] = ("a seeded sample of %d requests, %s of each request's steps, on %d threads, one request "
+                        "per thread at a time (FP64 oracle for every request; latency has no CPU analogue)"
+                        % (len(pick), part, cb["cores"]))
+        out["cpu_baseline"] = cb
+        out["gpu_over_cpu"] = out["value"] / cb["value"]
+    del srv
+    torch.cuda.synchronize()
+    return out
+
+
+def serve_sweep(rates, requests, budget_gib=4.0, serve_fp32="fp32"):
+    """Offered load against achieved throughput, latency and queue depth."""
+    rows = []
+    for rate in rates:
+        o = run_serve(rate, requests, budget_gib, serve_fp32=serve_fp32, cpu=False)
+        rows.append({k: o[k] for k in ("rate_per_s", "offered_glups", "achieved_glups", "p50_ms", "p99_ms",
+                                       "queue_wait_p50_ms", "queue_wait_p99_ms", "queue_depth_max",
+                                       "queue_depth_mean", "active_max", "arena_peak_bytes", "completed",
+                                       "requests", "wall_s")})
+        log("sweep %s" % json.dumps(rows[-1]))
+    return {"workload": "serve_sweep_%d_requests" % requests, "budget_gib": budget_gib, "rows": rows}
 
 
 def bench_table3(args):
@@ -665,6 +1016,64 @@ def bench_stats(args):
     print(json.dumps(out), flush=True)
 
 
+def line(head: dict, steps: int, warmup: int, precision: str) -> dict:
+    """The driver's JSON fields around one lattice result."""
+    return {
+        "metric": METRIC, "value": head["value"], "unit": "GLUPS", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": head["ms_per_solve"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "split": "f64+f32", "rho": "f64"}[precision],
+        "data": "synthetic", "config": head["config"],
+    }
+
+
+def bench_all(args):
+    """The headline lattice plus every other configuration, in one JSON line."""
+    import torch
+
+    from paper_1711_03540_amd import inputs
+
+    torch.cuda.set_device(0)
+    cpu = not args.no_cpu_baseline
+    peaks = None if args.no_peaks else device_peaks()
+    head = run_lattice(inputs.CFG_LARGE_Q7, args.precision, args.kernel or "tiled", args.steps, args.warmup,
+                       args.tile_steps, args.autotune, plain=not args.no_plain, cpu=cpu, peaks=peaks)
+    out = line(head, args.steps, args.warmup, args.precision)
+    out.update({k: head[k] for k in ("latency_ms", "roofline", "autotuned", "s1_hbm_roofline_glups",
+                                     "vs_s1_hbm_roofline") if k in head})
+    if "plain_kernel" in head:
+        out["plain_kernel"] = head["plain_kernel"]
+    if "cpu_baseline" in head:
+        out["cpu_baseline"] = head["cpu_baseline"]
+        out["gpu_over_cpu"] = head["gpu_over_cpu"]
+    out["peaks"] = peaks
+    configs = {}
+    w0, w1 = inputs.CFG_SMALL_Q5, inputs.CFG_RESIDENT_Q7
+    configs[w0.name] = run_lattice(w0, "fp64", "span", 100, 5, plain=not args.no_plain, cpu=cpu)
+    configs[w1.name] = run_lattice(w1, "fp64", "span", 30, 2, plain=not args.no_plain, cpu=cpu)
+    ens64 = run_ensemble("fp64", args.instances, args.lb_steps, cpu=cpu)
+    ens32 = run_ensemble("fp32", args.instances, args.lb_steps, cpu=False)
+    configs[ens64["workload"]] = ens64
+    configs[ens64["workload"] + "_fp32"] = ens32
+    srv = run_serve(2000.0, args.requests, args.budget_gib, serve_fp32=args.serve_fp32, cpu=cpu)
+    configs[srv["workload"]] = srv
+    rates = [float(r) for r in args.rates.split(",") if r]
+    configs["serve_sweep"] = serve_sweep(rates, args.sweep_requests, args.budget_gib, args.serve_fp32)
+    out["configs"] = configs
+    # the targets, in one place: the one-step kernel's HBM fraction on the large
+    # lattice; batched and served throughput over the plain one-instance kernel
+    # at equal accuracy (bitwise-identical arithmetic); served p99 latency
+    pk = head.get("plain_kernel", {})
+    out["targets"] = {
+        "s1_plain_hbm_frac": pk.get("hbm_frac"), "s1_plain_hbm_frac_target": TARGET_HBM_FRAC,
+        "s1_plain_meets_target": pk.get("meets_target"),
+        "tiled_over_plain": pk.get("speedup"),
+        "ensemble_fp64_over_plain": ens64["speedup_vs_plain"],
+        "served_glups": srv["value"], "served_over_plain_one_instance": srv["value"] / ens64["plain_one_instance_glups"],
+        "served_p50_ms": srv["p50_ms"], "served_p99_ms": srv["p99_ms"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -675,184 +1084,38 @@ def main():
               "would shard across GPUs as described in the design notes, but no multi-GPU path is "
               "built." % args.gpus, file=sys.stderr)
         sys.exit(2)
+    studies = {"table3": bench_table3, "stats": bench_stats, "profiles": bench_profiles,
+               "lyapunov_spectrum": bench_lyapunov_spectrum, "taumin": bench_taumin, "lyapunov": bench_lyapunov}
+    if args.workload in studies:
+        studies[args.workload](args)
+        return
+    if args.workload == "all":
+        bench_all(args)
+        return
+    cpu = not args.no_cpu_baseline
     if args.workload == "ensemble":
-        bench_ensemble(args)
+        print(json.dumps(run_ensemble(args.precision, args.instances, args.lb_steps, args.steps, args.warmup,
+                                      args.chunk, args.segments, args.autotune, cpu=cpu)), flush=True)
         return
     if args.workload == "serve":
-        bench_serve(args)
+        print(json.dumps(run_serve(args.rate, args.requests, args.budget_gib, args.chunk, args.round_steps,
+                                   args.serve_fp32, cpu=cpu)), flush=True)
         return
-    if args.workload == "table3":
-        bench_table3(args)
+    if args.workload == "serve_sweep":
+        rates = [float(r) for r in args.rates.split(",") if r]
+        print(json.dumps(serve_sweep(rates, args.sweep_requests, args.budget_gib, args.serve_fp32)), flush=True)
         return
-    if args.workload == "stats":
-        bench_stats(args)
-        return
-    if args.workload == "profiles":
-        bench_profiles(args)
-        return
-    if args.workload == "lyapunov_spectrum":
-        bench_lyapunov_spectrum(args)
-        return
-    if args.workload == "taumin":
-        bench_taumin(args)
-        return
-    if args.workload == "lyapunov":
-        bench_lyapunov(args)
-        return
-    import numpy as np
     import torch
 
     from paper_1711_03540_amd import inputs
-    from paper_1711_03540_amd.lattice import Lattice
-
+    torch.cuda.set_device(0)
     wname, default_kernel = WORKLOADS[args.workload]
     w = getattr(inputs, wname)
     kernel = args.kernel or default_kernel
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    print("bench: workload %s q=%d n=%d steps/solve=%d precision=%s kernel=%s" %
-          (w.name, w.q, w.n, w.steps, args.precision, kernel), file=sys.stderr, flush=True)
-
-    rho0 = torch.tensor(w.rho0(), dtype=torch.float64, device=dev)
-    rho_out = torch.empty(w.n, dtype=torch.float64, device=dev)
-    lat = Lattice(w.n, w.q, args.precision, device=dev)
-    lat.set_physical(w.dX, w.dT, 0.0)
-    lat.set_kernel(kernel, args.tile_steps)
-    tuned = None
-    if args.autotune and args.kernel is None:
-        from paper_1711_03540_amd import tune
-        tuned = tune.tune_lattice(w.n, w.q, args.precision, steps=min(w.steps, 2000), dX=w.dX, dT=w.dT, cache=None)
-        tune.apply_lattice(lat, tuned)
-        kernel = tuned["best"]["kernel"]
-        print("bench: autotuned %s" % tuned["best"], file=sys.stderr, flush=True)
-    tau = lat.coefficients()["tau"]
-    stream = lat.stream
-
-    def solve(ev=None):
-        lat.init_rho(rho0)
-        if ev is not None:
-            ev[0].record(stream)
-        lat.advance(w.steps)
-        if ev is not None:
-            ev[1].record(stream)
-        lat.read_rho(rho_out)
-
-    for _ in range(args.warmup):
-        solve()
-    torch.cuda.synchronize()
-
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(stream)
-        solve(kev[k])
-        ends[k].record(stream)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-
-    lat_ms = np.array([starts[k].elapsed_time(ends[k]) for k in range(args.steps)])
-    adv_ms = np.array([kev[k][0].elapsed_time(kev[k][1]) for k in range(args.steps)])
-    site_updates = w.n * w.steps
-    value = site_updates * args.steps / total / 1e9
-    mass, bad = lat.diagnostics()
-    if bad:
-        raise SystemExit("bench: non-finite state")
-
-    # launches per advance and the dominant kernel's average duration, from
-    # the launch shape the library resolved for this lattice
-    shape = lat.kernel()
-    assert shape["kernel"] == kernel, shape
-    launches = math.ceil(w.steps / shape["steps_per_launch"])
-    units = w.n * w.steps / launches
-    kname = {"resident": "k_ring", "span": "k_span", "tiled": "k_tile", "plain": "k_plain"}[kernel]
-    kernel_ms = float(np.mean(adv_ms)) / launches
-    if kernel == "plain":
-        ach = bytes_per_site_update(w.q, args.precision) * units / (kernel_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None}
-    else:
-        ach = flops_per_site_update(w.q, args.precision) * units / (kernel_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": None}
-        if kernel in ("resident", "span"):
-            # execution resources the launch can use: one workgroup of 8 waves
-            # on one CU (4 SIMDs) for resident; one single-wave owner of
-            # 256 - 2 H s sites per workgroup, each on one SIMD, for span
-            if kernel == "resident":
-                simds = 4
-            else:
-                simds = shape["workgroups"]
-                roof["steps_between_exchanges"] = shape["exchange_steps"]
-                roof["workgroups"] = simds
-            roof["simds_used"] = simds
-            roof["frac_of_used_simds"] = ach / (PEAK_FP64_VECTOR_TFLOPS * simds / (4 * N_CU))
-    roof["traffic"] = measured_traffic(kname, w.name, args.precision)
-    roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
-    roof["traffic_algorithmic"] = bytes_per_site_update(w.q, args.precision) * w.n
-    roof["kernel"] = kname
-    roof["launch_shape"] = shape
-    roof["kernel_ms_avg"] = kernel_ms
-    roof["algorithmic_per_site_update"] = (flops_per_site_update(w.q, args.precision) if kernel != "plain"
-                                           else bytes_per_site_update(w.q, args.precision))
-    roof["units_per_launch"] = units
-
-    out = {
-        "metric": "GLUPS vs plain kernel at matched error; % HBM/LDS peak; p50/p99 solve latency",
-        "value": value,
-        "unit": "GLUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": total / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "split": "f64+f32", "rho": "f64"}[args.precision],
-        "data": "synthetic",
-        "config": {"workload": w.name, "scheme": "D1Q%d" % w.q, "n_sites": w.n, "lb_steps_per_solve": w.steps,
-                   "dX": w.dX, "dT": w.dT, "tau": tau, "precision": args.precision, "kernel": kernel,
-                   "instances": 1},
-        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
-                       "min": float(lat_ms.min())},
-        "roofline": roof,
-        "autotuned": tuned["best"] if tuned else None,
-    }
-
-    if not args.no_plain and kernel != "plain":
-        # plain one-step-per-launch kernel on the same lattice; bitwise identical results
-        chk = min(w.steps, 2000)
-        ref = Lattice(w.n, w.q, args.precision, device=dev).set_physical(w.dX, w.dT, 0.0).set_kernel("plain")
-        ref.init_rho(rho0).advance(chk)
-        opt = Lattice(w.n, w.q, args.precision, device=dev).set_physical(w.dX, w.dT, 0.0).set_kernel(kernel)
-        opt.init_rho(rho0).advance(chk)
-        same = bool(torch.equal(ref.save_state(), opt.save_state()))
-        psteps = min(w.steps, 5000)
-        ref.advance(psteps)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        ref.advance(psteps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        pg = w.n * psteps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        hbm = pg * bytes_per_site_update(w.q, args.precision)     # GB/s, algorithmic bytes
-        out["plain_kernel"] = {"glups": pg, "timed_lb_steps": psteps, "speedup": value / pg,
-                               "bitwise_identical_state_after_%d_steps" % chk: same,
-                               "hbm_gb_s": hbm, "hbm_frac": hbm / PEAK_HBM_GBS}
-    # the one-step HBM roofline (2 Q b bytes per site update at 8 TB/s) that
-    # temporal blocking lifts the solve above
-    s1 = PEAK_HBM_GBS / bytes_per_site_update(w.q, args.precision)
-    out["s1_hbm_roofline_glups"] = s1
-    out["vs_s1_hbm_roofline"] = value / s1
-
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, tau)
-        out["cpu_baseline"]["host"] = {"nproc": os.cpu_count()}
-
+    res = run_lattice(w, args.precision, kernel, args.steps, args.warmup, args.tile_steps,
+                      args.autotune and args.kernel is None, plain=not args.no_plain, cpu=cpu)
+    out = line(res, args.steps, args.warmup, args.precision)
+    out.update({k: v for k, v in res.items() if k not in out})
     print(json.dumps(out), flush=True)
 
 

@@ -347,6 +347,21 @@ kslb_status kslb_ensemble_get_tau(const kslb_ensemble* ens, int idx, double* tau
  * size given at create).  Its state is dropped; init it again.             */
 kslb_status kslb_ensemble_resize(kslb_ensemble* ens, int idx, int64_t n_sites);
 
+/* Device bytes of one instance's state outside an ensemble's buffer: two
+ * copies, each rounded up to 256 bytes (no diagnostics).  0 for a bad shape. */
+size_t kslb_instance_bytes(int64_t n_sites, int q, int precision);
+
+/* Rebind instance idx to a lattice of n_sites sites (its scheme and storage
+ * unchanged) whose state lives in caller-owned device memory dev_state
+ * (>= kslb_instance_bytes bytes, 256-byte aligned, on the ensemble's device;
+ * never freed by the library).  Its capacity becomes n_sites, its state is
+ * dropped (init it again) and its coefficients are kept.  Work already
+ * enqueued still uses the previous memory (stream order), so the caller may
+ * release that memory once such work has completed.  This lets a server size
+ * each admitted request's state to the request and admit requests by a
+ * device-memory budget.                                                    */
+kslb_status kslb_ensemble_bind(kslb_ensemble* ens, int idx, int64_t n_sites, void* dev_state, size_t bytes);
+
 /* As kslb_init_rho for instance idx: f := feq(rho) from its current number
  * of densities (device or host), step counter := 0.                        */
 kslb_status kslb_ensemble_init_rho(kslb_ensemble* ens, int idx, const double* rho, int on_device);

@@ -1,4 +1,4 @@
-"""Build libkslb.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libkslb.so and libkslb_probe.so (HIP, gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
 import os
@@ -9,6 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkslb.so")
 SOURCES = ["kslb_kernels.hip", "kslb_api.cpp", "kslb_params.cpp"]
+# device-peak measurement kernels, a library of their own (not the method)
+PROBE_LIB = os.path.join(HERE, "libkslb_probe.so")
+PROBE_SOURCES = ["kslb_probe.hip"]
 
 # -ffp-contract=off: only the explicit FMAs of the kernels are fused, so every
 # kernel class rounds identically.  Packed FP32 instructions are disabled.
@@ -27,17 +30,22 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False, extra=None) -> str:
-    """Compile every source into libkslb.so next to this file (always rebuilds)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + FLAGS + list(extra or []) + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+def _compile(lib: str, sources, verbose: bool, extra) -> None:
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + FLAGS + list(extra or []) + ["-o", tmp] + [os.path.join(CSRC, s) for s in sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libkslb.so")
-    os.replace(tmp, LIB)
+        raise RuntimeError("hipcc failed building %s" % os.path.basename(lib))
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False, extra=None) -> str:
+    """Compile libkslb.so and libkslb_probe.so next to this file (always rebuilds)."""
+    _compile(LIB, SOURCES, verbose, extra)
+    _compile(PROBE_LIB, PROBE_SOURCES, verbose, extra)
     return LIB
 
 

@@ -74,6 +74,8 @@ SIGNATURES = {
     "kslb_ensemble_set_tiling": (_st, [_vp, _i, _i, _i]),
     "kslb_ensemble_set_graphs": (_st, [_vp, _i]),
     "kslb_ensemble_resize": (_st, [_vp, _i, _i64]),
+    "kslb_instance_bytes": (_sz, [_i64, _i, _i]),
+    "kslb_ensemble_bind": (_st, [_vp, _i, _i64, _vp, _sz]),
     "kslb_ensemble_init_rho": (_st, [_vp, _i, _vp, _i]),
     "kslb_ensemble_init_rho_all": (_st, [_vp, _vp, _i]),
     "kslb_ensemble_read_rho_all": (_st, [_vp, _vp, _i]),

@@ -942,7 +942,11 @@ struct kslb_ensemble {
     hipStream_t stream = nullptr;
     std::vector<int> q, prec;          // scheme and storage of each instance
     std::vector<int64_t> cap, n;       // capacity and current size (sites) per instance
-    std::vector<size_t> off, copy;     // byte offset of copy 0, bytes per copy (at capacity)
+    // byte offset of copy 0 from buf (negative or beyond the buffer for an
+    // instance bound to caller memory elsewhere), bytes per copy (at capacity)
+    std::vector<int64_t> off;
+    std::vector<size_t> copy;
+    uint64_t layout_gen = 1;           // changes whenever an instance is bound to other memory
     std::vector<int> cur;
     std::vector<int64_t> step;
     std::vector<char> have_state;
@@ -998,13 +1002,13 @@ struct kslb_ensemble {
 
 namespace {
 
-size_t ens_layout(int count, const int64_t* n_sites, const int* q, const int* prec, std::vector<size_t>* off,
+size_t ens_layout(int count, const int64_t* n_sites, const int* q, const int* prec, std::vector<int64_t>* off,
                   std::vector<size_t>* copy)
 {
     size_t pos = 0;
     for (int i = 0; i < count; i++) {
         const size_t c = state_copy_bytes(n_sites[i], q[i], prec[i]);
-        if (off) off->push_back(pos);
+        if (off) off->push_back((int64_t)pos);
         if (copy) copy->push_back(c);
         pos += 2 * c;
     }
@@ -1033,7 +1037,10 @@ kslb_status ens_staging(kslb_ensemble* E, int64_t n)
     return KSLB_OK;
 }
 
-char* ens_state(kslb_ensemble* E, int i) { return E->buf + E->off[i] + (size_t)E->cur[i] * E->copy[i]; }
+// Byte offset, from the ensemble's base, of copy `which` (0 or 1) of instance i.
+int64_t ens_off(const kslb_ensemble* E, int i, int which) { return E->off[i] + (int64_t)which * (int64_t)E->copy[i]; }
+
+char* ens_state(kslb_ensemble* E, int i) { return E->buf + ens_off(E, i, E->cur[i]); }
 
 int ens_max_halo(const kslb_ensemble* E)
 {
@@ -1124,6 +1131,7 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, EnsPlan* pla
     key.push_back((uint64_t)E->B);
     key.push_back((uint64_t)E->max_seg);
     key.push_back(E->coef_gen);
+    key.push_back(E->layout_gen);
     for (int i = 0; i < E->count; i++) {
         if (adv[i] <= 0) continue;
         key.push_back((uint64_t)i);
@@ -1216,8 +1224,8 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, EnsPlan* pla
         for (const Tile& t : w.t) {
             const int i = t.inst;
             SegDesc d;
-            d.src_off = (int64_t)(E->off[i] + (size_t)E->cur[i] * E->copy[i]);
-            d.dst_off = (int64_t)(E->off[i] + (size_t)(1 - E->cur[i]) * E->copy[i]);
+            d.src_off = ens_off(E, i, E->cur[i]);
+            d.dst_off = ens_off(E, i, 1 - E->cur[i]);
             d.n = E->n[i];
             d.pitch = state_pitch(E->n[i]);
             d.start = t.start;
@@ -1424,7 +1432,7 @@ std::vector<InstDesc> ens_inst_table(const kslb_ensemble* E, CopyOf copy_of, int
     groups->clear();
     for (int k = 0; k < E->count; k++) {
         const int i = order[k];
-        dv[k] = InstDesc{(int64_t)(E->off[i] + (size_t)copy_of(i) * E->copy[i]), rho_off[i], E->n[i],
+        dv[k] = InstDesc{ens_off(E, i, copy_of(i)), rho_off[i], E->n[i],
                          state_pitch(E->n[i]), std::max(E->cls[i], 0), 0};
         if (groups->empty() || groups->back().q != E->q[i] || groups->back().prec != E->prec[i])
             groups->push_back(InstGroup{k, k, E->q[i], E->prec[i], 0});
@@ -1556,6 +1564,32 @@ kslb_status kslb_ensemble_resize(kslb_ensemble* E, int idx, int64_t n_sites)
     E->n[idx] = n_sites;
     E->have_state[idx] = 0;
     E->step[idx] = 0;
+    return KSLB_OK;
+}
+
+size_t kslb_instance_bytes(int64_t n_sites, int q, int precision)
+{
+    if (!valid_shape(n_sites, q, precision)) return 0;
+    return 2 * state_copy_bytes(n_sites, q, precision);
+}
+
+kslb_status kslb_ensemble_bind(kslb_ensemble* E, int idx, int64_t n_sites, void* dev_state, size_t bytes)
+{
+    if (auto s = check_ens(E, idx)) return s;
+    if (!valid_shape(n_sites, E->q[idx], E->prec[idx]))
+        return fail(KSLB_EINVAL, "bad size %lld for instance %d", (long long)n_sites, idx);
+    if (!dev_state || reinterpret_cast<uintptr_t>(dev_state) % 256)
+        return fail(KSLB_EINVAL, "state memory missing or not 256-byte aligned");
+    const size_t need = kslb_instance_bytes(n_sites, E->q[idx], E->prec[idx]);
+    if (bytes < need) return fail(KSLB_ENOMEM, "instance %d needs %zu bytes, got %zu", idx, need, bytes);
+    E->off[idx] = (int64_t)(reinterpret_cast<uintptr_t>(dev_state) - reinterpret_cast<uintptr_t>(E->buf));
+    E->copy[idx] = state_copy_bytes(n_sites, E->q[idx], E->prec[idx]);
+    E->cap[idx] = n_sites;
+    E->n[idx] = n_sites;
+    E->cur[idx] = 0;
+    E->have_state[idx] = 0;
+    E->step[idx] = 0;
+    E->layout_gen++;
     return KSLB_OK;
 }
 
@@ -1778,8 +1812,7 @@ kslb_status kslb_ensemble_renormalize(kslb_ensemble* E, int npairs, const int* r
     for (int p = 0; p < npairs; p++) {
         const int a = ref[p], b = pert[p];
         pd[E->q[a] == 5 ? at5++ : at7++] =
-            PairDesc{(int64_t)(E->off[a] + (size_t)E->cur[a] * E->copy[a]),
-                     (int64_t)(E->off[b] + (size_t)E->cur[b] * E->copy[b]), E->n[a], state_pitch(E->n[a]), p, 0};
+            PairDesc{ens_off(E, a, E->cur[a]), ens_off(E, b, E->cur[b]), E->n[a], state_pitch(E->n[a]), p, 0};
     }
     DeviceGuard g(E->device);
     const size_t bytes = sizeof(PairDesc) * (size_t)npairs;
@@ -1850,11 +1883,11 @@ kslb_status kslb_ensemble_orthonormalize(kslb_ensemble* E, int ngroups, int k, c
     for (int g = 0; g < ngroups; g++) {
         const int a = ref[g];
         const int row = E->q[a] == 5 ? at5++ : at7++;
-        gv[row] = GroupDesc{(int64_t)(E->off[a] + (size_t)E->cur[a] * E->copy[a]), E->n[a], state_pitch(E->n[a]),
+        gv[row] = GroupDesc{ens_off(E, a, E->cur[a]), E->n[a], state_pitch(E->n[a]),
                             row * k, k, g * k, 0};
         for (int m = 0; m < k; m++) {
             const int i = pert[(size_t)g * k + m];
-            offs[(size_t)row * k + m] = (int64_t)(E->off[i] + (size_t)E->cur[i] * E->copy[i]);
+            offs[(size_t)row * k + m] = ens_off(E, i, E->cur[i]);
         }
     }
     const size_t off_at = sizeof(GroupDesc) * gv.size();

@@ -80,6 +80,14 @@ class Ensemble:
         self.n[idx] = n
         return self
 
+    def bind(self, idx: int, n: int, dev_ptr: int, nbytes: int) -> "Ensemble":
+        """Rebind instance idx to n sites whose state lives at device address
+        dev_ptr (nbytes >= kslb_instance_bytes, 256-byte aligned, owned by the
+        caller); its state is dropped."""
+        call("kslb_ensemble_bind", self._h, int(idx), int(n), ctypes.c_void_p(int(dev_ptr)), int(nbytes))
+        self.n[idx] = n
+        return self
+
     def init_rho(self, idx: int, rho) -> "Ensemble":
         import torch
         if isinstance(rho, torch.Tensor) and rho.is_cuda:

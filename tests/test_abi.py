@@ -174,3 +174,16 @@ def test_host_functions_from_many_threads():
     for t in threads:
         t.join()
     assert not errors, errors
+
+
+def test_probe_library_exports_its_header():
+    # the measurement kernels (device peaks) sit in a library of their own
+    from paper_1711_03540_amd import probe
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "kslb_probe.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(kslb_probe_[a-z0-9_]+)\s*\(", text)))
+    assert names == sorted(probe.SIGNATURES)
+    lib = probe.load()
+    for name in names:
+        assert hasattr(lib, name)
+    assert lib.kslb_probe_copy(None, None, 16, None) != 0      # refused without device work
+    assert lib.kslb_probe_lds(None, 1, 1, None) != 0

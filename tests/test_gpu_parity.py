@@ -599,6 +599,45 @@ def test_rho_only_ensemble_16_sites_per_lane(q):
             assert np.array_equal(o[i], want), (i, n)
 
 
+def test_ensemble_instances_bound_to_caller_memory():
+    # instances rebound to device memory outside the ensemble's buffer (one
+    # block allocated before it, one after, so offsets from its base have
+    # either sign) compute bitwise what single lattices compute; rebinding to
+    # another size drops the state; bad memory is refused
+    import torch
+
+    from paper_1711_03540_amd import KslbError
+    from paper_1711_03540_amd.serve import instance_bytes
+    say("case ensemble bind")
+    dX, dT = math.pi / 16, 1e-4
+    shapes = [(5000, 7, "fp64"), (777, 5, "fp32"), (3000, 7, "split")]
+    before = [torch.empty(instance_bytes(n, q, p), dtype=torch.uint8, device="cuda") for n, q, p in shapes]
+    ens = Ensemble([1, 1, 1], [q for _, q, _ in shapes], [p for _, _, p in shapes]).set_physical(dX, dT, 0.0)
+    after = [torch.empty(instance_bytes(n, q, p), dtype=torch.uint8, device="cuda") for n, q, p in shapes]
+    mem = [before[0], after[1], before[2]]
+    for k, (n, q, p) in enumerate(shapes):
+        ens.bind(k, n, mem[k].data_ptr(), mem[k].numel())
+        ens.init_rho(k, ic(n, dX, 40 + k, 0.1))
+    ens.advance([300, 500, 200])
+    for k, (n, q, p) in enumerate(shapes):
+        lat = Lattice(n, q, p).set_physical(dX, dT, 0.0).set_kernel("plain").init_rho(ic(n, dX, 40 + k, 0.1))
+        lat.advance([300, 500, 200][k])
+        assert np.array_equal(ens.rho(k), lat.rho()), k
+    # rebind instance 0 to a smaller lattice in the other block
+    ens.bind(0, 1234, after[0].data_ptr(), after[0].numel())
+    with pytest.raises(KslbError):
+        ens.advance([10, 0, 0])                              # no state until init
+    ens.init_rho(0, ic(1234, dX, 9, 0.1)).advance([64, 0, 0])
+    lat = Lattice(1234, 7, "fp64").set_physical(dX, dT, 0.0).set_kernel("plain").init_rho(ic(1234, dX, 9, 0.1))
+    assert np.array_equal(ens.rho(0), lat.advance(64).rho())
+    with pytest.raises(KslbError) as e:
+        ens.bind(1, 777, after[1].data_ptr() + 8, after[1].numel() - 8)
+    assert e.value.status == -1                              # EINVAL: not 256-byte aligned
+    with pytest.raises(KslbError) as e:
+        ens.bind(1, 5000, after[1].data_ptr(), after[1].numel())
+    assert e.value.status == -2                              # ENOMEM: the block is too small
+
+
 def test_served_results_equal_solo_solves():
     # continuous batching: requests of both schemes and precisions arrive while
     # others run; each result equals the same solve run alone (bitwise)
@@ -615,12 +654,17 @@ def test_served_results_equal_solo_solves():
     bad = 7
     init[bad] = init[bad] * 1e300
     for fp32_storage in ("fp32", "split"):
-        srv = SolveServer(dX, dT, slots=6, capacity=6000, chunk=24, round_steps=100, fp32_storage=fp32_storage)
+        # a budget of 1 MiB holds only a few of these requests at once, so
+        # most wait for memory and are admitted while others run
+        srv = SolveServer(dX, dT, budget_bytes=1 << 20, slots=64, chunk=24, round_steps=100,
+                          fp32_storage=fp32_storage)
         stats = srv.serve(reqs, init, realtime=True)
         summ = stats.summary()
         say("serve summary (fp32 requests in %s storage)" % fp32_storage, summ)
         assert summ["completed"] == len(reqs)
         assert summ["p99_ms"] >= summ["p50_ms"] > 0
+        assert summ["arena_peak_bytes"] <= 1 << 20 and summ["queue_depth_max"] > 0 and summ["active_max"] >= 2
+        assert srv.arena.used == 0 and srv.arena.largest_free() == srv.arena.size   # every block returned
         assert stats.results[bad].finite is False
         for i, r in enumerate(reqs):
             if i == bad:

@@ -212,11 +212,11 @@ Limits device_limits(int q, int prec, bool fixed)
 
 // Multi-workgroup plan: nwg single-wave owners of about n / nwg sites each,
 // every window (own sites + 2 H s halo, a halo possibly spanning several
-// owners) within span_lanes() x span_sites_per_lane(q) slots.  Returns nwg,
-// or 0 when the shape cannot use it or needs more than max_owners owners.
-int span_plan(int64_t n, int q, int s, int64_t max_owners)
+// owners) within span_lanes() x span_sites_per_lane(q, prec) slots.  Returns
+// nwg, or 0 when the shape cannot use it or needs more than max_owners owners.
+int span_plan(int64_t n, int q, int prec, int s, int64_t max_owners)
 {
-    const int64_t W = (int64_t)span_lanes() * span_sites_per_lane(q);
+    const int64_t W = (int64_t)span_lanes() * span_sites_per_lane(q, prec);
     const int64_t hs = (int64_t)halo(q) * s;
     const int64_t own = W - 2 * hs;
     if (s < 1 || own < 1) return 0;
@@ -231,11 +231,11 @@ int span_plan(int64_t n, int q, int s, int64_t max_owners)
 // measured on D1Q7 N = 4096: s = 21, 24, 28, 31 (63, 86, 171, 683 owners) ran
 // 26.7, 25.1, 26.1, 57 ms per 10^5 steps; s = 22, 23, 25, 26, 27 ran 26.7,
 // 26.3, 26.2, 26.4, 26.6 ms.
-int span_default_steps(int64_t n, int q, int64_t max_owners)
+int span_default_steps(int64_t n, int q, int prec, int64_t max_owners)
 {
-    const int64_t W = (int64_t)span_lanes() * span_sites_per_lane(q);
+    const int64_t W = (int64_t)span_lanes() * span_sites_per_lane(q, prec);
     for (int s = (int)((3 * W) / (8 * halo(q))); s >= 1; s--)
-        if (span_plan(n, q, s, max_owners)) return s;
+        if (span_plan(n, q, prec, s, max_owners)) return s;
     return 0;
 }
 
@@ -293,14 +293,14 @@ KernelChoice plan_kernel(int64_t n, int q, int prec, bool fixed, int req, int re
 {
     int kernel = req;
     if (kernel == KSLB_KERNEL_AUTO) {
-        if (n <= kSpanAutoMaxSites && span_default_steps(n, q, lim.span_owners) >= kSpanAutoMinSteps)
+        if (n <= kSpanAutoMaxSites && span_default_steps(n, q, prec, lim.span_owners) >= kSpanAutoMinSteps)
             kernel = KSLB_KERNEL_SPAN;
         else if (fixed) kernel = KSLB_KERNEL_PLAIN;
         else kernel = ring_sites_per_lane(n, q, lim.lds_bytes) ? KSLB_KERNEL_RESIDENT : KSLB_KERNEL_TILED;
     }
     int steps = 0;
     if (kernel == KSLB_KERNEL_SPAN)
-        steps = (req == KSLB_KERNEL_SPAN && req_steps > 0) ? req_steps : span_default_steps(n, q, lim.span_owners);
+        steps = (req == KSLB_KERNEL_SPAN && req_steps > 0) ? req_steps : span_default_steps(n, q, prec, lim.span_owners);
     else if (kernel == KSLB_KERNEL_TILED)
         steps = req_steps > 0 ? req_steps : default_tile_steps(q, prec);
     return KernelChoice{kernel, steps};
@@ -513,8 +513,8 @@ kslb_status kslb_set_kernel(kslb_lattice* L, int kernel, int steps_per_launch)
             return fail(KSLB_EINVAL, "n=%lld cannot use the resident kernel (needs n = B*L, B in {4,8}, L <= 512)",
                         (long long)L->n);
         if (kernel == KSLB_KERNEL_SPAN) {
-            const int sp = steps_per_launch > 0 ? steps_per_launch : span_default_steps(L->n, L->q, lim.span_owners);
-            if (!sp || !span_plan(L->n, L->q, sp, lim.span_owners))
+            const int sp = steps_per_launch > 0 ? steps_per_launch : span_default_steps(L->n, L->q, L->prec, lim.span_owners);
+            if (!sp || !span_plan(L->n, L->q, L->prec, sp, lim.span_owners))
                 return fail(KSLB_EINVAL,
                             "n=%lld cannot be split over at most %lld resident workgroups with %d steps between "
                             "exchanges", (long long)L->n, (long long)lim.span_owners, sp);
@@ -551,7 +551,7 @@ void describe(const KernelChoice& kc, int64_t n, int q, int prec, const Limits& 
     }
     case KSLB_KERNEL_SPAN:
         exch = kc.steps;
-        wg = kc.steps ? span_plan(n, q, kc.steps, lim.span_owners) : 0;
+        wg = kc.steps ? span_plan(n, q, prec, kc.steps, lim.span_owners) : 0;
         per_launch = wg ? (int)span_steps_per_launch(wg * span_edge_copy_bytes(q, prec, n, (int)wg, kc.steps),
                                                      kc.steps, kSpanSlotBytes)
                         : 0;
@@ -605,7 +605,7 @@ kslb_status kslb_plan_kernel(int64_t n_sites, int q, int precision, int boundary
         if (lds_bytes == 0) lim.lds_bytes = dev.lds_bytes;
     }
     const KernelChoice kc = plan_kernel(n_sites, q, precision, fixed, kernel, steps_per_launch, lim);
-    if (kc.kernel == KSLB_KERNEL_SPAN && !span_plan(n_sites, q, kc.steps, lim.span_owners))
+    if (kc.kernel == KSLB_KERNEL_SPAN && !span_plan(n_sites, q, precision, kc.steps, lim.span_owners))
         return fail(KSLB_EINVAL, "n=%lld cannot be split over at most %lld resident workgroups", (long long)n_sites,
                     (long long)lim.span_owners);
     if (kc.kernel == KSLB_KERNEL_RESIDENT && !ring_sites_per_lane(n_sites, q, lim.lds_bytes))
@@ -694,7 +694,7 @@ kslb_status advance_impl(kslb_lattice* L, int64_t n_steps, bool noalloc)
         }
     } else if (kernel == KSLB_KERNEL_SPAN) {
         const int sp = kc.steps;
-        const int nwg = sp ? span_plan(L->n, L->q, sp, lim.span_owners) : 0;
+        const int nwg = sp ? span_plan(L->n, L->q, L->prec, sp, lim.span_owners) : 0;
         if (!nwg)
             return fail(KSLB_EINVAL, "shape cannot use the multi-workgroup kernel (at most %lld resident workgroups)",
                         (long long)lim.span_owners);

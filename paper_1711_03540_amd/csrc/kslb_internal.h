@@ -67,7 +67,7 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
 // aborted launches), set up by launch_span_ctl_init.  The state is read from
 // src and written to dst.
 int span_lanes();
-int span_sites_per_lane(int q);
+int span_sites_per_lane(int q, int prec);
 int span_ctl_ints();
 int span_ctl_error_index();   // sticky: a launch stopped early since the state was set
 int span_ctl_aborts_index();  // launches that stopped early since the control block was set up

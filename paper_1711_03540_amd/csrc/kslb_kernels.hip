@@ -624,9 +624,35 @@ struct Engine {
     // rho-only state: the neighbours need the densities of the H edge sites
     // on each side, not the 12 (6) populations
     static constexpr bool kR = (P == kRHO);
-    static constexpr int NX = kR ? 2 * H : nx_of(Q);
+
+    // Where site b of this lane streams population i from: site sb = b - c_i
+    // in this lane's numbering, i.e. site rem_site(i, b) of the lane
+    // rem_lane(i, b) lanes away (negative: to the left).  With at least max|c|
+    // sites per lane every remote source is a neighbouring lane; single-wave
+    // engines also take fewer, with sources up to ceil(max|c| / B) lanes away.
+    static constexpr int sdiv(int a) { return a >= 0 ? a / B : -((-a + B - 1) / B); }
+    static constexpr bool is_remote(int i, int b) { return b - vel(i) < 0 || b - vel(i) >= B; }
+    static constexpr int rem_lane(int i, int b) { return sdiv(b - vel(i)); }
+    static constexpr int rem_site(int i, int b) { return (b - vel(i)) - rem_lane(i, b) * B; }
+    // index of the remote value (i, b) among all remote values, population by
+    // population and site by site; with B >= max|c| this is koff(i) plus the
+    // value's place in its population, the layout the LDS exchange writes
+    static constexpr int rslot(int i, int b)
+    {
+        int k = 0;
+        for (int i2 = 0; i2 < Q; i2++)
+            for (int b2 = 0; b2 < B; b2++) {
+                if (i2 == i && b2 == b) return k;
+                if (is_remote(i2, b2)) k++;
+            }
+        return k;
+    }
+    static constexpr int NR = rslot(Q, 0);   // remote values per lane and step
+    static constexpr int NX = kR ? 2 * H : NR;
     static constexpr int SLOT = NX * LD;     // exchanged values per buffer
-    static_assert(B >= H, "a lane must hold at least max|c| sites");
+    static_assert(B >= H || (LD == 64 && !kR),
+                  "a lane holds at least max|c| sites, except in single-wave engines of populations");
+    static_assert(B < H || kR || NR == nx_of(Q), "neighbour exchange layout");
     // Exchanged value: FP32 populations travel as stored (widening them to
     // double is exact, so the receiver widens them instead); every other
     // state sends the double population (or density) its update reads.
@@ -679,8 +705,7 @@ struct Engine {
                 constexpr int sb = b - c;
                 if constexpr (sb >= 0 && sb < B) g[i] = PL::template pop<i>(x[sb], cf);
                 else if constexpr (kR) g[i] = PL::template pop<i>(Site{hv[sb < 0 ? H + sb : H + sb - B]}, cf);
-                else if constexpr (c > 0) g[i] = (double)hv[koff(i) + b];
-                else g[i] = (double)hv[koff(i) + sb - B];
+                else g[i] = (double)hv[rslot(i, b)];
             });
             PL::update(g, y[b], cf);
         });
@@ -751,14 +776,16 @@ struct Engine {
                 hv[H + T] = from_lane(x[T].rho, false);
             });
         } else {
-            unroll<Q - 1>([&](auto I1) {
-                constexpr int i = I1 + 1;
-                constexpr int c = vel(i);
-                constexpr int k0 = koff(i);
-                unroll<iabs(c)>([&](auto T) {
-                    constexpr int t = T;
-                    constexpr int src = (c > 0) ? (B - c + t) : t;
-                    hv[k0 + t] = from_lane(xval<i>(x[src], cf), c > 0);
+            // each remote value moves |rem_lane| lanes, one rotation per lane
+            unroll<Q>([&](auto I) {
+                unroll<B>([&](auto Bi) {
+                    constexpr int i = I, b = Bi;
+                    if constexpr (is_remote(i, b)) {
+                        constexpr int d = rem_lane(i, b);
+                        XV v = xval<i>(x[rem_site(i, b)], cf);
+                        unroll<iabs(d)>([&](auto) { v = from_lane(v, d < 0); });
+                        hv[rslot(i, b)] = v;
+                    }
                 });
             });
         }
@@ -793,32 +820,32 @@ struct Engine {
                 unroll<B>([&](auto Bi) { x[Bi] = y[Bi]; });
                 fix(x);
             }
-            return;
-        }
-        XV* xb = reinterpret_cast<XV*>(xch);   // the exchange area, in exchanged values
-        for (; st + 1 < steps; st += 2) {
-            if (active) publish(x, xb + lane, cf);
-            __syncthreads();
-            if (active) {
-                step(x, y, xb + left, xb + right, cf);
-                fix(y);
-                publish(y, xb + SLOT + lane, cf);
+        } else {
+            XV* xb = reinterpret_cast<XV*>(xch);   // the exchange area, in exchanged values
+            for (; st + 1 < steps; st += 2) {
+                if (active) publish(x, xb + lane, cf);
+                __syncthreads();
+                if (active) {
+                    step(x, y, xb + left, xb + right, cf);
+                    fix(y);
+                    publish(y, xb + SLOT + lane, cf);
+                }
+                __syncthreads();
+                if (active) {
+                    step(y, x, xb + SLOT + left, xb + SLOT + right, cf);
+                    fix(x);
+                }
             }
-            __syncthreads();
-            if (active) {
-                step(y, x, xb + SLOT + left, xb + SLOT + right, cf);
-                fix(x);
+            if (st < steps) {
+                if (active) publish(x, xb + lane, cf);
+                __syncthreads();
+                if (active) {
+                    step(x, y, xb + left, xb + right, cf);
+                    unroll<B>([&](auto Bi) { x[Bi] = y[Bi]; });
+                    fix(x);
+                }
+                __syncthreads();   // the next call writes slot 0 again
             }
-        }
-        if (st < steps) {
-            if (active) publish(x, xb + lane, cf);
-            __syncthreads();
-            if (active) {
-                step(x, y, xb + left, xb + right, cf);
-                unroll<B>([&](auto Bi) { x[Bi] = y[Bi]; });
-                fix(x);
-            }
-            __syncthreads();   // the next call writes slot 0 again
         }
     }
 };
@@ -938,16 +965,21 @@ __global__ __launch_bounds__(kTileLD) __attribute__((amdgpu_waves_per_eu(ens_wav
 // ---------------------------------------------------------------- one lattice over many workgroups
 
 constexpr int kSpanLD = 64;      // one wave per workgroup: lanes trade values by DPP, no barrier
-// Sites per lane of a SPAN window: the fewest a lane can hold (max|c|), so
-// that a step's dependency chain is short; a narrower window exchanges more
-// often, which measures as the better trade for the lattices SPAN serves.
-__host__ __device__ constexpr int span_b_of(int q) { return halo_of(q); }
+// Sites per lane of a SPAN window: few, so that a step's dependency chain is
+// short; a narrower window exchanges more often, which measures as the better
+// trade for the lattices SPAN serves.  Two for the population states of both
+// schemes (a D1Q7 population with |c| = 3 then moves up to two lanes per
+// step); max|c| for the rho-only state, whose exchange sends densities to the
+// neighbouring lanes only.
+__host__ __device__ constexpr int span_b_of(int q, int p) { return p == kRHO ? halo_of(q) : 2; }
 constexpr int kSpinLimit = 1 << 21;
 // Wait before the first poll of an exchange, in units of 64 clocks: about as
 // long as the neighbours' stores take to become visible, which grows with
-// the words an owner publishes (D1Q7: 21 per lane, D1Q5: 10).  Shorter waits
-// spend memory traffic on polls that find sentinels, longer ones idle.
-__host__ __device__ constexpr int first_poll_delay(int q) { return q == 7 ? 12 : 6; }
+// the words an owner publishes (two sites of 7 or 5 populations per lane).
+// Shorter waits spend memory traffic on polls that find sentinels, longer
+// ones idle (D1Q7 N = 4096, 16 steps between exchanges: 4 / 6 / 8 / 12 / 16
+// units ran 18.2 / 18.8 / 19.5 / 19.1 / 18.5 GLUPS).
+__host__ __device__ constexpr int first_poll_delay(int q) { return q == 7 ? 8 : 6; }
 
 // Control words of the multi-workgroup kernel (device memory, kept by the
 // lattice across launches): the abort word of the current launch, a sticky
@@ -1123,10 +1155,10 @@ __global__ __launch_bounds__(kSpanLD) void k_span(const char* __restrict__ src, 
                                                   int64_t ecopy, int64_t epitch, int64_t slots,
                                                   int* __restrict__ ctl, Coef cf, double rho_l, double rho_r)
 {
-    using E = Engine<Q, P, span_b_of(Q), kSpanLD>;
+    using E = Engine<Q, P, span_b_of(Q, P), kSpanLD>;
     using PL = typename E::PL;
     using Site = typename E::Site;
-    constexpr int B = span_b_of(Q);
+    constexpr int B = span_b_of(Q, P);
     double* xch = nullptr;   // single wave: the engine exchanges by DPP
     // consecutive owners share an XCD (workgroups are dealt round-robin to 8 XCDs)
     const int per = (nwg + 7) / 8;
@@ -1255,7 +1287,7 @@ template <int Q, int P>
 __global__ __launch_bounds__(256) void k_span_fill(char* ebase, int64_t ecopy, int64_t epitch, int64_t copies,
                                                    int hs, int sites)
 {
-    const SpanSlot sl = span_slot_shape(span_b_of(Q), hs, sites);
+    const SpanSlot sl = span_slot_shape(span_b_of(Q, P), hs, sites);
     const int64_t total = copies * sites;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
         const int64_t c = i / sites, k = hs + (i - c * sites);
@@ -1742,11 +1774,11 @@ int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegD
 }
 
 int span_lanes() { return kSpanLD; }
-int span_sites_per_lane(int q) { return span_b_of(q); }
+int span_sites_per_lane(int q, int prec) { return span_b_of(q, prec); }
 int span_ctl_ints() { return kCtlWords; }
 int64_t span_edge_copy_bytes(int q, int prec, int64_t n, int nwg, int s)
 {
-    const SpanSlot sl = span_slot_shape(span_b_of(q), (int64_t)halo_of(q) * s, (n + nwg - 1) / nwg);
+    const SpanSlot sl = span_slot_shape(span_b_of(q, prec), (int64_t)halo_of(q) * s, (n + nwg - 1) / nwg);
     return ((int64_t)state_copy_bytes(sl.pitch, q, prec) + 255) / 256 * 256;
 }
 
@@ -1800,14 +1832,14 @@ int launch_span(int q, int prec, const void* src, void* dst, int64_t n, int nwg,
     hipStream_t st = (hipStream_t)stream;
     const int h = halo_of(q);
     const int64_t hs = (int64_t)h * s;
-    const int64_t W = (int64_t)kSpanLD * span_b_of(q);
+    const int64_t W = (int64_t)kSpanLD * span_b_of(q, prec);
     if (nwg < 2 || s < 1 || steps < 1 || slots < 1) return (int)hipErrorInvalidValue;
     // every owner holds at least one site and its window fits
     const int64_t mmin = n / nwg, mmax = (n + nwg - 1) / nwg;
     if (mmin < 1 || mmax + 2 * hs > W) return (int)hipErrorInvalidValue;
     // the exchanges of this launch fit the slots
     if ((steps + s - 1) / s - 1 > slots) return (int)hipErrorInvalidValue;
-    const int64_t epitch = span_slot_shape(span_b_of(q), hs, mmax).pitch;
+    const int64_t epitch = span_slot_shape(span_b_of(q, prec), hs, mmax).pitch;
     if (ecopy < (int64_t)state_copy_bytes(epitch, q, prec)) return (int)hipErrorInvalidValue;
     const int64_t copies = std::min<int64_t>(slots, (steps + s - 1) / s - 1) * nwg;
     k_span_prep<<<1, 64, 0, st>>>(ctl);

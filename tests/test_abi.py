@@ -101,22 +101,25 @@ LDS = 160 * 1024   # one gfx950 workgroup may use the CU's 160 KiB
 
 
 def test_plan_takes_span_when_every_owner_fits():
-    # N = 4096 D1Q7: 86 single-wave owners of 48 sites (192-site windows, 24
-    # steps between exchanges) on a device that keeps 2048 owners resident
+    # N = 4096 D1Q7: 128 single-wave owners of 32 sites (128-site windows of
+    # 2 sites per lane, 16 steps between exchanges) on a device that keeps
+    # 2048 owners resident
     p = plan_kernel(4096, 7, "fp64", span_owners=2048, lds_bytes=LDS)
-    assert p == {"kernel": "span", "steps_per_launch": p["steps_per_launch"], "exchange_steps": 24,
-                 "workgroups": 86, "lanes": 64}
-    assert p["steps_per_launch"] % 24 == 0 and p["steps_per_launch"] > 10_000
+    assert p == {"kernel": "span", "steps_per_launch": p["steps_per_launch"], "exchange_steps": 16,
+                 "workgroups": 128, "lanes": 64}
+    assert p["steps_per_launch"] % 16 == 0 and p["steps_per_launch"] > 5_000
+    # the rho-only state keeps 3 sites per lane (densities move one lane per step)
+    assert plan_kernel(4096, 7, "rho", span_owners=2048, lds_bytes=LDS)["exchange_steps"] == 24
 
 
 def test_plan_refuses_span_beyond_half_the_resident_owners():
-    # a plan uses at most half the owners the device keeps resident: 86
-    # owners need 172
-    assert plan_kernel(4096, 7, "fp64", span_owners=172, lds_bytes=LDS)["workgroups"] == 86
+    # a plan uses at most half the owners the device keeps resident: 128
+    # owners need 256
+    assert plan_kernel(4096, 7, "fp64", span_owners=256, lds_bytes=LDS)["workgroups"] == 128
     # with fewer, AUTO shortens the exchange interval so that wider owners fit
-    # (100 resident: at most 50 owners of 192 - 6 s >= 82 sites, s = 18) ...
-    p = plan_kernel(4096, 7, "fp64", span_owners=100, lds_bytes=LDS)
-    assert p["kernel"] == "span" and p["exchange_steps"] == 18 and p["workgroups"] == 49
+    # (200 resident: at most 100 owners of 128 - 6 s >= 41 sites, s = 14) ...
+    p = plan_kernel(4096, 7, "fp64", span_owners=200, lds_bytes=LDS)
+    assert p["kernel"] == "span" and p["exchange_steps"] == 14 and p["workgroups"] == 94
     # ... but not below 12 steps between exchanges: then the one-workgroup
     # kernel takes the lattice (4096 = 8 sites x 512 lanes) ...
     p = plan_kernel(4096, 7, "fp64", span_owners=60, lds_bytes=LDS)
@@ -126,7 +129,7 @@ def test_plan_refuses_span_beyond_half_the_resident_owners():
     assert p["kernel"] == "tiled" and p["steps_per_launch"] == 64
     # an explicit SPAN request that cannot fit is refused
     with pytest.raises(_lib.KslbError) as e:
-        plan_kernel(4096, 7, "fp64", kernel="span", steps_per_launch=24, span_owners=171, lds_bytes=LDS)
+        plan_kernel(4096, 7, "fp64", kernel="span", steps_per_launch=16, span_owners=255, lds_bytes=LDS)
     assert e.value.status == _lib.KSLB_EINVAL and "resident" in str(e.value)
 
 

@@ -343,6 +343,20 @@ def run_lattice(w, precision, kernel, solves, warmup, tile_steps=0, autotune=Fal
             roof["frac_of_used_simds"] = ach / (PEAK_FP64_VECTOR_TFLOPS * simds / N_SIMD)
             roof["frac_of_used_simds_valu_ceiling"] = glups_kernel / valu_ceiling_glups(w.q, simds)
             roof["ns_per_step"] = kernel_ms * 1e6 / (w.steps / launches)
+    if kernel == "tiled" and peaks:
+        # the tile engine trades 12 (D1Q7) or 6 (D1Q5) values per lane and step
+        # through LDS, each written once and read once: 2 x 8 x 12 / 8 = 24 B
+        # per computed site update of 8 sites per lane (FP64), against the
+        # measured LDS read peak
+        per_lane = {7: 12, 5: 6}[w.q] * (4 if precision == "fp32" else 8) * 2
+        sites = 16 if precision == "rho" else 8
+        win = 256 * sites
+        valid = win - 2 * (3 if w.q == 7 else 2) * shape["steps_per_launch"]
+        lds_b = per_lane / sites * units * win / valid
+        lp = peaks["lds"]["bytes_per_clk_per_cu"] * N_CU * peaks["lds"]["shader_ghz"] * 1e9
+        roof["lds_bytes_per_launch"] = lds_b
+        roof["lds_achieved_gb_s"] = lds_b / (kernel_ms * 1e-3) / 1e9
+        roof["lds_frac_of_measured_peak"] = lds_b / (kernel_ms * 1e-3) / lp
     roof["traffic"] = measured_traffic(kname, w.name, precision)
     roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["traffic_algorithmic"] = bytes_per_site_update(w.q, precision) * w.n
@@ -505,7 +519,9 @@ def run_ensemble(precision, instances, lb_steps, solves=3, warmup=1, chunk=0, se
            "roofline": {"bound": "alu", "kernel": "k_ens", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
                         "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS,
                         "frac_of_valu_ceiling": su / (float(np.mean(sol_ms)) * 1e-3) / 1e9 / valu_ceiling_glups(7),
-                        "traffic": None}}
+                        "traffic": measured_traffic("k_ens", "ensemble_d1q7_%d" % len(sizes), precision),
+                        "traffic_unit": "bytes per chunk launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                        "traffic_algorithmic": bytes_per_site_update(7, precision) * float(np.sum(sizes))}}
     ens.close()
     if cpu:
         # a seeded 64-instance subset of the same ensemble, extrapolated

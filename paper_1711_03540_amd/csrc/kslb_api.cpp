@@ -942,9 +942,9 @@ struct kslb_ensemble {
     hipStream_t stream = nullptr;
     std::vector<int> q, prec;          // scheme and storage of each instance
     std::vector<int64_t> cap, n;       // capacity and current size (sites) per instance
-    // byte offset of copy 0 from buf (negative or beyond the buffer for an
-    // instance bound to caller memory elsewhere), bytes per copy (at capacity)
-    std::vector<int64_t> off;
+    // device address of copy 0 (in buf, or in caller memory for an instance
+    // bound elsewhere) and bytes per copy (at capacity)
+    std::vector<uintptr_t> addr;
     std::vector<size_t> copy;
     uint64_t layout_gen = 1;           // changes whenever an instance is bound to other memory
     std::vector<int> cur;
@@ -1002,13 +1002,15 @@ struct kslb_ensemble {
 
 namespace {
 
-size_t ens_layout(int count, const int64_t* n_sites, const int* q, const int* prec, std::vector<int64_t>* off,
+// Byte offsets of the instances' copy 0 in an ensemble buffer and bytes per
+// copy; returns the bytes of all instances' states.
+size_t ens_layout(int count, const int64_t* n_sites, const int* q, const int* prec, std::vector<size_t>* off,
                   std::vector<size_t>* copy)
 {
     size_t pos = 0;
     for (int i = 0; i < count; i++) {
         const size_t c = state_copy_bytes(n_sites[i], q[i], prec[i]);
-        if (off) off->push_back((int64_t)pos);
+        if (off) off->push_back(pos);
         if (copy) copy->push_back(c);
         pos += 2 * c;
     }
@@ -1037,10 +1039,13 @@ kslb_status ens_staging(kslb_ensemble* E, int64_t n)
     return KSLB_OK;
 }
 
-// Byte offset, from the ensemble's base, of copy `which` (0 or 1) of instance i.
-int64_t ens_off(const kslb_ensemble* E, int i, int which) { return E->off[i] + (int64_t)which * (int64_t)E->copy[i]; }
+// Device address of copy `which` (0 or 1) of instance i.
+uint64_t ens_addr(const kslb_ensemble* E, int i, int which)
+{
+    return (uint64_t)(E->addr[i] + (uintptr_t)which * E->copy[i]);
+}
 
-char* ens_state(kslb_ensemble* E, int i) { return E->buf + ens_off(E, i, E->cur[i]); }
+char* ens_state(kslb_ensemble* E, int i) { return reinterpret_cast<char*>(ens_addr(E, i, E->cur[i])); }
 
 int ens_max_halo(const kslb_ensemble* E)
 {
@@ -1224,8 +1229,8 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, EnsPlan* pla
         for (const Tile& t : w.t) {
             const int i = t.inst;
             SegDesc d;
-            d.src_off = ens_off(E, i, E->cur[i]);
-            d.dst_off = ens_off(E, i, 1 - E->cur[i]);
+            d.src = ens_addr(E, i, E->cur[i]);
+            d.dst = ens_addr(E, i, 1 - E->cur[i]);
             d.n = E->n[i];
             d.pitch = state_pitch(E->n[i]);
             d.start = t.start;
@@ -1293,7 +1298,7 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, EnsPlan* pla
 int ens_launch(const kslb_ensemble* E, const EnsPlan& plan, hipStream_t stream)
 {
     for (const auto& l : *plan.launches) {
-        int e = launch_ens(l.q, l.prec, E->B, E->buf, plan.hdr + l.w0, plan.seg, l.nwin, plan.coefs, stream);
+        int e = launch_ens(l.q, l.prec, E->B, plan.hdr + l.w0, plan.seg, l.nwin, plan.coefs, stream);
         if (e) return e;
     }
     return 0;
@@ -1432,7 +1437,7 @@ std::vector<InstDesc> ens_inst_table(const kslb_ensemble* E, CopyOf copy_of, int
     groups->clear();
     for (int k = 0; k < E->count; k++) {
         const int i = order[k];
-        dv[k] = InstDesc{ens_off(E, i, copy_of(i)), rho_off[i], E->n[i],
+        dv[k] = InstDesc{ens_addr(E, i, copy_of(i)), rho_off[i], E->n[i],
                          state_pitch(E->n[i]), std::max(E->cls[i], 0), 0};
         if (groups->empty() || groups->back().q != E->q[i] || groups->back().prec != E->prec[i])
             groups->push_back(InstGroup{k, k, E->q[i], E->prec[i], 0});
@@ -1481,7 +1486,10 @@ kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* 
     E->stream = (hipStream_t)hip_stream;
     E->cap.assign(n_sites, n_sites + count);
     E->n = E->cap;
-    E->diag_off = ens_layout(count, n_sites, q, precision, &E->off, &E->copy);
+    std::vector<size_t> off;
+    E->diag_off = ens_layout(count, n_sites, q, precision, &off, &E->copy);
+    E->addr.resize(count);
+    for (int i = 0; i < count; i++) E->addr[i] = reinterpret_cast<uintptr_t>(E->buf) + off[i];
     E->cur.assign(count, 0);
     E->step.assign(count, 0);
     E->have_state.assign(count, 0);
@@ -1582,7 +1590,7 @@ kslb_status kslb_ensemble_bind(kslb_ensemble* E, int idx, int64_t n_sites, void*
         return fail(KSLB_EINVAL, "state memory missing or not 256-byte aligned");
     const size_t need = kslb_instance_bytes(n_sites, E->q[idx], E->prec[idx]);
     if (bytes < need) return fail(KSLB_ENOMEM, "instance %d needs %zu bytes, got %zu", idx, need, bytes);
-    E->off[idx] = (int64_t)(reinterpret_cast<uintptr_t>(dev_state) - reinterpret_cast<uintptr_t>(E->buf));
+    E->addr[idx] = reinterpret_cast<uintptr_t>(dev_state);
     E->copy[idx] = state_copy_bytes(n_sites, E->q[idx], E->prec[idx]);
     E->cap[idx] = n_sites;
     E->n[idx] = n_sites;
@@ -1646,8 +1654,7 @@ kslb_status kslb_ensemble_init_rho_all(kslb_ensemble* E, const double* rho, int 
     const InstDesc* dd = reinterpret_cast<const InstDesc*>(dev);
     const Coef* dc = reinterpret_cast<const Coef*>(dev + coef_at);
     for (const InstGroup& gr : groups) {
-        int e = launch_init_many(gr.q, gr.prec, E->buf, dd + gr.begin, gr.end - gr.begin, gr.max_n, dc, src,
-                                 E->stream);
+        int e = launch_init_many(gr.q, gr.prec, dd + gr.begin, gr.end - gr.begin, gr.max_n, dc, src, E->stream);
         if (e) return hip_fail(e, "init kernel");
     }
     if (!on_device) {
@@ -1751,7 +1758,7 @@ kslb_status kslb_ensemble_read_rho_all(kslb_ensemble* E, double* out, int on_dev
     if (auto st = ens_upload(E, E->read_tab, dv.data(), sizeof(InstDesc) * dv.size(), &dev)) return st;
     const InstDesc* dd = reinterpret_cast<const InstDesc*>(dev);
     for (const InstGroup& gr : groups) {
-        int e = launch_read_many(gr.q, gr.prec, E->buf, dd + gr.begin, gr.end - gr.begin, gr.max_n, dst, E->stream);
+        int e = launch_read_many(gr.q, gr.prec, dd + gr.begin, gr.end - gr.begin, gr.max_n, dst, E->stream);
         if (e) return hip_fail(e, "readout kernel");
     }
     if (!on_device) {
@@ -1812,7 +1819,7 @@ kslb_status kslb_ensemble_renormalize(kslb_ensemble* E, int npairs, const int* r
     for (int p = 0; p < npairs; p++) {
         const int a = ref[p], b = pert[p];
         pd[E->q[a] == 5 ? at5++ : at7++] =
-            PairDesc{ens_off(E, a, E->cur[a]), ens_off(E, b, E->cur[b]), E->n[a], state_pitch(E->n[a]), p, 0};
+            PairDesc{ens_addr(E, a, E->cur[a]), ens_addr(E, b, E->cur[b]), E->n[a], state_pitch(E->n[a]), p, 0};
     }
     DeviceGuard g(E->device);
     const size_t bytes = sizeof(PairDesc) * (size_t)npairs;
@@ -1846,8 +1853,8 @@ kslb_status kslb_ensemble_renormalize(kslb_ensemble* E, int npairs, const int* r
     if (e) return hip_fail(e, "pair table upload");
     E->pairs_pending = true;
     const PairDesc* dt = reinterpret_cast<const PairDesc*>(E->d_pairs);
-    if (nq5) e = launch_pair_renorm(5, E->buf, dt, nq5, delta, log_accum, E->stream);
-    if (!e && npairs > nq5) e = launch_pair_renorm(7, E->buf, dt + nq5, npairs - nq5, delta, log_accum, E->stream);
+    if (nq5) e = launch_pair_renorm(5, dt, nq5, delta, log_accum, E->stream);
+    if (!e && npairs > nq5) e = launch_pair_renorm(7, dt + nq5, npairs - nq5, delta, log_accum, E->stream);
     if (e) return hip_fail(e, "pair renormalisation kernel");
     return KSLB_OK;
 }
@@ -1876,32 +1883,32 @@ kslb_status kslb_ensemble_orthonormalize(kslb_ensemble* E, int ngroups, int k, c
         }
         nq5 += E->q[a] == 5;
     }
-    // table: group descriptors (D1Q5 groups first), then the perturbed-state offsets
+    // table: group descriptors (D1Q5 groups first), then the perturbed-state addresses
     std::vector<GroupDesc> gv((size_t)ngroups);
-    std::vector<int64_t> offs((size_t)ngroups * k);
+    std::vector<uint64_t> offs((size_t)ngroups * k);
     int at5 = 0, at7 = nq5;
     for (int g = 0; g < ngroups; g++) {
         const int a = ref[g];
         const int row = E->q[a] == 5 ? at5++ : at7++;
-        gv[row] = GroupDesc{ens_off(E, a, E->cur[a]), E->n[a], state_pitch(E->n[a]),
+        gv[row] = GroupDesc{ens_addr(E, a, E->cur[a]), E->n[a], state_pitch(E->n[a]),
                             row * k, k, g * k, 0};
         for (int m = 0; m < k; m++) {
             const int i = pert[(size_t)g * k + m];
-            offs[(size_t)row * k + m] = ens_off(E, i, E->cur[i]);
+            offs[(size_t)row * k + m] = ens_addr(E, i, E->cur[i]);
         }
     }
     const size_t off_at = sizeof(GroupDesc) * gv.size();
-    std::vector<char> blob(off_at + sizeof(int64_t) * offs.size());
+    std::vector<char> blob(off_at + sizeof(uint64_t) * offs.size());
     std::memcpy(blob.data(), gv.data(), off_at);
-    std::memcpy(blob.data() + off_at, offs.data(), sizeof(int64_t) * offs.size());
+    std::memcpy(blob.data() + off_at, offs.data(), sizeof(uint64_t) * offs.size());
     DeviceGuard dg(E->device);
     char* dev = nullptr;
     if (auto st = ens_upload(E, E->group_tab, blob.data(), blob.size(), &dev)) return st;
     const GroupDesc* dd = reinterpret_cast<const GroupDesc*>(dev);
-    const int64_t* doff = reinterpret_cast<const int64_t*>(dev + off_at);
+    const uint64_t* doff = reinterpret_cast<const uint64_t*>(dev + off_at);
     int e = 0;
-    if (nq5) e = launch_group_orth(5, k, E->buf, dd, doff, nq5, delta, log_accum, E->stream);
-    if (!e && ngroups > nq5) e = launch_group_orth(7, k, E->buf, dd + nq5, doff, ngroups - nq5, delta, log_accum, E->stream);
+    if (nq5) e = launch_group_orth(5, k, dd, doff, nq5, delta, log_accum, E->stream);
+    if (!e && ngroups > nq5) e = launch_group_orth(7, k, dd + nq5, doff, ngroups - nq5, delta, log_accum, E->stream);
     if (e) return hip_fail(e, "group orthonormalisation kernel");
     return KSLB_OK;
 }

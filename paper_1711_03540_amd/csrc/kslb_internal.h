@@ -80,25 +80,26 @@ int noalloc_scratch(char** ptr);
 int64_t span_edge_copy_bytes(int q, int prec, int64_t n, int nwg, int s);   // one slot copy
 int launch_span_ctl_init(int* ctl, int count, void* stream);
 int launch_span_set_ctl(int* ctl, int index, int value, void* stream);
-// Trajectory pair of an FP64 ensemble: byte offsets of the two current state
-// copies from the ensemble base, sites, row pitch and the accumulator slot.
+// Trajectory pair of an FP64 ensemble: device addresses of the two current
+// state copies, sites, row pitch and the accumulator slot.
 struct PairDesc {
-    int64_t ref_off, pert_off, n, pitch;
+    uint64_t ref, pert;
+    int64_t n, pitch;
     int32_t slot, pad;
 };
-int launch_pair_renorm(int q, char* base, const PairDesc* desc, int npairs, double delta, double* log_accum,
-                       void* stream);
-// A reference and k perturbed copies of an FP64 ensemble: byte offset of the
-// reference's current state copy, sites, row pitch, the index of the group's
-// first perturbed-state offset in a separate int64 array, k, and the first of
-// its k accumulator slots.
+int launch_pair_renorm(int q, const PairDesc* desc, int npairs, double delta, double* log_accum, void* stream);
+// A reference and k perturbed copies of an FP64 ensemble: device address of
+// the reference's current state copy, sites, row pitch, the index of the
+// group's first perturbed-state address in a separate array, k, and the first
+// of its k accumulator slots.
 constexpr int kGroupMaxK = 8;
 struct GroupDesc {
-    int64_t ref_off, n, pitch;
+    uint64_t ref;
+    int64_t n, pitch;
     int32_t first, k, slot, pad;
 };
-int launch_group_orth(int q, int k, char* base, const GroupDesc* desc, const int64_t* pert_off, int ngroups,
-                      double delta, double* log_accum, void* stream);
+int launch_group_orth(int q, int k, const GroupDesc* desc, const uint64_t* pert, int ngroups, double delta,
+                      double* log_accum, void* stream);
 // fixed-end boundary values (NULL / absent = periodic)
 struct Ends {
     double rho_l, rho_r;
@@ -133,29 +134,29 @@ struct WinHdr {
     int32_t coef;       // index of the window's coefficient set in the launch's table
 };
 struct SegDesc {
-    int64_t src_off;    // byte offset of the instance's source state copy
-    int64_t dst_off;    // byte offset of the destination state copy
+    uint64_t src;       // device address of the instance's source state copy
+    uint64_t dst;       // device address of the destination state copy
     int64_t n;          // sites of the instance
     int64_t pitch;      // row pitch of the instance (state_pitch(n))
     int64_t start;      // site of the segment's first slot (may be negative: periodic)
     int32_t lane_lo;    // first lane of the segment
     int32_t valid;      // sites written back, from slot H * steps on
 };
-// One ensemble instance in a batched init or readout: byte offset of its
-// state copy from the ensemble base, offset of its densities in the packed
-// density array, sites, row pitch and coefficient set (init only).
+// One ensemble instance in a batched init or readout: device address of its
+// state copy, offset of its densities in the packed density array, sites,
+// row pitch and coefficient set (init only).
 struct InstDesc {
-    int64_t state_off, rho_off, n, pitch;
+    uint64_t state;
+    int64_t rho_off, n, pitch;
     int32_t coef, pad;
 };
 // Instances desc[0 .. count) of one scheme and storage; max_n bounds their sizes.
-int launch_init_many(int q, int prec, char* base, const InstDesc* desc, int count, int64_t max_n,
-                     const Coef* coefs, const double* rho, void* stream);
-int launch_read_many(int q, int prec, const char* base, const InstDesc* desc, int count, int64_t max_n,
-                     double* rho, void* stream);
+int launch_init_many(int q, int prec, const InstDesc* desc, int count, int64_t max_n, const Coef* coefs,
+                     const double* rho, void* stream);
+int launch_read_many(int q, int prec, const InstDesc* desc, int count, int64_t max_n, double* rho, void* stream);
 
 // coefs: device table of coefficient sets, indexed by WinHdr::coef
-int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegDesc* seg, int nwin,
+int launch_ens(int q, int prec, int B, const WinHdr* hdr, const SegDesc* seg, int nwin,
                const Coef* coefs, void* stream);
 
 }  // namespace kslb

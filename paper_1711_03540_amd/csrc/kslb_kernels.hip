@@ -530,13 +530,14 @@ __global__ __launch_bounds__(256) void k_init(char* st, int64_t n, int64_t p, co
 // instance d[y] (its descriptor and coefficient set are uniform over the
 // block), block column x its sites [256 x, 256 x + 256).
 template <int Q, int P>
-__global__ __launch_bounds__(256) void k_init_many(char* base, const InstDesc* __restrict__ d,
+__global__ __launch_bounds__(256) void k_init_many(const InstDesc* __restrict__ d,
                                                    const Coef* __restrict__ coefs, const double* __restrict__ rho)
 {
     using PL = Pol<Q, P>;
     const InstDesc e = d[blockIdx.y];
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j < e.n) PL::store(base + e.state_off, e.pitch, j, PL::equilibrium(rho[e.rho_off + j], coefs[e.coef]));
+    if (j < e.n)
+        PL::store(reinterpret_cast<char*>(e.state), e.pitch, j, PL::equilibrium(rho[e.rho_off + j], coefs[e.coef]));
 }
 
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
@@ -945,7 +946,7 @@ constexpr int ens_waves_per_simd(int p) { return p == kSPLIT ? 1 : 3; }
 // Lanes past the last segment's tile carry junk that is never stored.  The
 // window's coefficient set is uniform over the workgroup (scalar loads).
 template <int Q, int P, int B>
-__global__ __launch_bounds__(kTileLD) __attribute__((amdgpu_waves_per_eu(ens_waves_per_simd(P)))) void k_ens(char* base, const WinHdr* __restrict__ hdr,
+__global__ __launch_bounds__(kTileLD) __attribute__((amdgpu_waves_per_eu(ens_waves_per_simd(P)))) void k_ens(const WinHdr* __restrict__ hdr,
                                                  const SegDesc* __restrict__ seg, const Coef* __restrict__ coefs)
 {
     extern __shared__ double xch[];
@@ -958,7 +959,8 @@ __global__ __launch_bounds__(kTileLD) __attribute__((amdgpu_waves_per_eu(ens_wav
         if (seg[h.first_seg + k].lane_lo <= lane) my = k;
     const SegDesc d = seg[h.first_seg + my];
     const int64_t kl0 = (int64_t)(lane - d.lane_lo) * B;
-    window_lane<Q, P, B>(base + d.src_off, base + d.dst_off, d.n, d.pitch, d.start + kl0, kl0,
+    window_lane<Q, P, B>(reinterpret_cast<const char*>(d.src), reinterpret_cast<char*>(d.dst), d.n, d.pitch,
+                         d.start + kl0, kl0,
                          (int64_t)H * h.steps, d.valid, h.steps, xch, cf);
 }
 
@@ -1315,14 +1317,14 @@ __global__ void k_span_init_ctl(int* ctl, int count)
 constexpr int kPairLD = 1024;
 
 template <int Q>
-__global__ __launch_bounds__(kPairLD) void k_pair_renorm(char* __restrict__ base, const PairDesc* __restrict__ pd,
+__global__ __launch_bounds__(kPairLD) void k_pair_renorm(const PairDesc* __restrict__ pd,
                                                         double delta, double* __restrict__ log_accum)
 {
     __shared__ double red[kPairLD];
     __shared__ double scale_sh;
     const PairDesc d = pd[blockIdx.x];
-    const double* r = reinterpret_cast<const double*>(base + d.ref_off);
-    double* x = reinterpret_cast<double*>(base + d.pert_off);
+    const double* r = reinterpret_cast<const double*>(d.ref);
+    double* x = reinterpret_cast<double*>(d.pert);
     const int t = threadIdx.x;
     const int64_t total = (int64_t)Q * d.n;
     double ss = 0.0;
@@ -1353,12 +1355,11 @@ __global__ __launch_bounds__(kPairLD) void k_pair_renorm(char* __restrict__ base
     }
 }
 
-int launch_pair_renorm(int q, char* base, const PairDesc* desc, int npairs, double delta, double* log_accum,
-                       void* stream)
+int launch_pair_renorm(int q, const PairDesc* desc, int npairs, double delta, double* log_accum, void* stream)
 {
     if (npairs <= 0) return 0;
-    if (q == 5) k_pair_renorm<5><<<npairs, kPairLD, 0, (hipStream_t)stream>>>(base, desc, delta, log_accum);
-    else k_pair_renorm<7><<<npairs, kPairLD, 0, (hipStream_t)stream>>>(base, desc, delta, log_accum);
+    if (q == 5) k_pair_renorm<5><<<npairs, kPairLD, 0, (hipStream_t)stream>>>(desc, delta, log_accum);
+    else k_pair_renorm<7><<<npairs, kPairLD, 0, (hipStream_t)stream>>>(desc, delta, log_accum);
     return (int)hipGetLastError();
 }
 
@@ -1371,8 +1372,8 @@ int launch_pair_renorm(int q, char* base, const PairDesc* desc, int npairs, doub
 // log_accum[slot + m] += ln(R_mm / delta).  If R is not positive definite and
 // finite the group is left unchanged and NaN is stored.
 template <int Q, int K>
-__global__ __launch_bounds__(kPairLD) void k_group_orth(char* __restrict__ base, const GroupDesc* __restrict__ gd,
-                                                       const int64_t* __restrict__ pert_off, double delta,
+__global__ __launch_bounds__(kPairLD) void k_group_orth(const GroupDesc* __restrict__ gd,
+                                                       const uint64_t* __restrict__ pert, double delta,
                                                        double* __restrict__ log_accum)
 {
     constexpr int NP = K * (K + 1) / 2;
@@ -1381,9 +1382,9 @@ __global__ __launch_bounds__(kPairLD) void k_group_orth(char* __restrict__ base,
     __shared__ double rm[K][K];
     __shared__ int ok_sh;
     const GroupDesc g = gd[blockIdx.x];
-    const double* r = reinterpret_cast<const double*>(base + g.ref_off);
+    const double* r = reinterpret_cast<const double*>(g.ref);
     double* x[K];
-    unroll<K>([&](auto M) { x[M] = reinterpret_cast<double*>(base + pert_off[g.first + M]); });
+    unroll<K>([&](auto M) { x[M] = reinterpret_cast<double*>(pert[g.first + M]); });
     const int t = threadIdx.x;
     const int64_t total = (int64_t)Q * g.n;
     double acc[NP];
@@ -1451,29 +1452,29 @@ __global__ __launch_bounds__(kPairLD) void k_group_orth(char* __restrict__ base,
 }
 
 template <int Q>
-static int group_orth_q(int k, char* base, const GroupDesc* desc, const int64_t* pert_off, int ngroups,
-                        double delta, double* log_accum, hipStream_t st)
+static int group_orth_q(int k, const GroupDesc* desc, const uint64_t* pert, int ngroups, double delta,
+                        double* log_accum, hipStream_t st)
 {
     switch (k) {
-    case 1: k_group_orth<Q, 1><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
-    case 2: k_group_orth<Q, 2><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
-    case 3: k_group_orth<Q, 3><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
-    case 4: k_group_orth<Q, 4><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
-    case 5: k_group_orth<Q, 5><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
-    case 6: k_group_orth<Q, 6><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
-    case 7: k_group_orth<Q, 7><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
-    case 8: k_group_orth<Q, 8><<<ngroups, kPairLD, 0, st>>>(base, desc, pert_off, delta, log_accum); break;
+    case 1: k_group_orth<Q, 1><<<ngroups, kPairLD, 0, st>>>(desc, pert, delta, log_accum); break;
+    case 2: k_group_orth<Q, 2><<<ngroups, kPairLD, 0, st>>>(desc, pert, delta, log_accum); break;
+    case 3: k_group_orth<Q, 3><<<ngroups, kPairLD, 0, st>>>(desc, pert, delta, log_accum); break;
+    case 4: k_group_orth<Q, 4><<<ngroups, kPairLD, 0, st>>>(desc, pert, delta, log_accum); break;
+    case 5: k_group_orth<Q, 5><<<ngroups, kPairLD, 0, st>>>(desc, pert, delta, log_accum); break;
+    case 6: k_group_orth<Q, 6><<<ngroups, kPairLD, 0, st>>>(desc, pert, delta, log_accum); break;
+    case 7: k_group_orth<Q, 7><<<ngroups, kPairLD, 0, st>>>(desc, pert, delta, log_accum); break;
+    case 8: k_group_orth<Q, 8><<<ngroups, kPairLD, 0, st>>>(desc, pert, delta, log_accum); break;
     default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
 }
 
-int launch_group_orth(int q, int k, char* base, const GroupDesc* desc, const int64_t* pert_off, int ngroups,
-                      double delta, double* log_accum, void* stream)
+int launch_group_orth(int q, int k, const GroupDesc* desc, const uint64_t* pert, int ngroups, double delta,
+                      double* log_accum, void* stream)
 {
     if (ngroups <= 0) return 0;
-    if (q == 5) return group_orth_q<5>(k, base, desc, pert_off, ngroups, delta, log_accum, (hipStream_t)stream);
-    return group_orth_q<7>(k, base, desc, pert_off, ngroups, delta, log_accum, (hipStream_t)stream);
+    if (q == 5) return group_orth_q<5>(k, desc, pert, ngroups, delta, log_accum, (hipStream_t)stream);
+    return group_orth_q<7>(k, desc, pert, ngroups, delta, log_accum, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------- readout and diagnostics
@@ -1492,13 +1493,13 @@ __global__ __launch_bounds__(256) void k_read_rho(const char* __restrict__ st, i
 
 // Density readout of many lattices in one launch (block row y: instance d[y]).
 template <int Q, int P>
-__global__ __launch_bounds__(256) void k_read_many(const char* __restrict__ base, const InstDesc* __restrict__ d,
+__global__ __launch_bounds__(256) void k_read_many(const InstDesc* __restrict__ d,
                                                    double* __restrict__ rho)
 {
     using PL = Pol<Q, P>;
     const InstDesc e = d[blockIdx.y];
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j < e.n) rho[e.rho_off + j] = PL::density(PL::load(base + e.state_off, e.pitch, j));
+    if (j < e.n) rho[e.rho_off + j] = PL::density(PL::load(reinterpret_cast<const char*>(e.state), e.pitch, j));
 }
 
 // out is dense Q x n
@@ -1666,28 +1667,25 @@ int launch_init(int q, int prec, void* state, int64_t n, const double* rho0, con
     return (int)hipGetLastError();
 }
 
-int launch_read_many(int q, int prec, const char* base, const InstDesc* desc, int count, int64_t max_n,
-                     double* rho, void* stream)
+int launch_read_many(int q, int prec, const InstDesc* desc, int count, int64_t max_n, double* rho, void* stream)
 {
     constexpr int kMaxRows = 65535;   // grid y limit
     for (int y0 = 0; y0 < count; y0 += kMaxRows) {
         const dim3 grid(blocks_for(max_n), (unsigned)std::min(kMaxRows, count - y0));
-        KSLB_DISPATCH_QP(q, prec, (k_read_many<Q_, P_><<<grid, 256, 0, (hipStream_t)stream>>>(
-                                      base, desc + y0, rho)));
+        KSLB_DISPATCH_QP(q, prec, (k_read_many<Q_, P_><<<grid, 256, 0, (hipStream_t)stream>>>(desc + y0, rho)));
         int e = (int)hipGetLastError();
         if (e) return e;
     }
     return 0;
 }
 
-int launch_init_many(int q, int prec, char* base, const InstDesc* desc, int count, int64_t max_n,
-                     const Coef* coefs, const double* rho, void* stream)
+int launch_init_many(int q, int prec, const InstDesc* desc, int count, int64_t max_n, const Coef* coefs,
+                     const double* rho, void* stream)
 {
     constexpr int kMaxRows = 65535;   // grid y limit
     for (int y0 = 0; y0 < count; y0 += kMaxRows) {
         const dim3 grid(blocks_for(max_n), (unsigned)std::min(kMaxRows, count - y0));
-        KSLB_DISPATCH_QP(q, prec, (k_init_many<Q_, P_><<<grid, 256, 0, (hipStream_t)stream>>>(
-                                      base, desc + y0, coefs, rho)));
+        KSLB_DISPATCH_QP(q, prec, (k_init_many<Q_, P_><<<grid, 256, 0, (hipStream_t)stream>>>(desc + y0, coefs, rho)));
         int e = (int)hipGetLastError();
         if (e) return e;
     }
@@ -1751,24 +1749,24 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
 }
 
 template <int Q, int P, int B>
-static int ens_one(char* base, const WinHdr* hdr, const SegDesc* seg, int nwin, const Coef* cf, void* stream)
+static int ens_one(const WinHdr* hdr, const SegDesc* seg, int nwin, const Coef* cf, void* stream)
 {
     const int lds = tile_lds_bytes(Q);
     int e = prep_lds(k_ens<Q, P, B>, lds);
     if (e) return e;
-    k_ens<Q, P, B><<<(unsigned)nwin, kTileLD, lds, (hipStream_t)stream>>>(base, hdr, seg, cf);
+    k_ens<Q, P, B><<<(unsigned)nwin, kTileLD, lds, (hipStream_t)stream>>>(hdr, seg, cf);
     return (int)hipGetLastError();
 }
 
-int launch_ens(int q, int prec, int B, char* base, const WinHdr* hdr, const SegDesc* seg, int nwin,
+int launch_ens(int q, int prec, int B, const WinHdr* hdr, const SegDesc* seg, int nwin,
                const Coef* cf, void* stream)
 {
     if (nwin <= 0) return 0;
-    if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 4>(base, hdr, seg, nwin, cf, stream))); }
-    if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 8>(base, hdr, seg, nwin, cf, stream))); }
+    if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 4>(hdr, seg, nwin, cf, stream))); }
+    if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 8>(hdr, seg, nwin, cf, stream))); }
     if (B == 16 && prec == kRHO) {
-        if (q == 5) return ens_one<5, kRHO, 16>(base, hdr, seg, nwin, cf, stream);
-        return ens_one<7, kRHO, 16>(base, hdr, seg, nwin, cf, stream);
+        if (q == 5) return ens_one<5, kRHO, 16>(hdr, seg, nwin, cf, stream);
+        return ens_one<7, kRHO, 16>(hdr, seg, nwin, cf, stream);
     }
     return (int)hipErrorInvalidValue;
 }

@@ -44,30 +44,47 @@ CLOCK_GHZ = 2.4
 TARGET_HBM_FRAC = 0.70      # the one-step kernel on the large lattice
 
 
-# Algorithmic flops of one site update (an FMA counts 2).  Population
-# storage: density Q-1 adds; rho^2 1 mul; A_i rho 1 mul for c = 0 and one per
-# +-c pair (A is even in c); one FMA per population with G != 0 (c = +-1, +-2)
-# for G_i rho^2 + A_i rho; one FMA per population for (1 - omega) g_i + feq_i.
-# D1Q7: 6 + 5 + 2 * 11 = 33, D1Q5: 4 + 4 + 2 * 9 = 26.  Rho-only storage
-# (tau = 1, post-collision populations feq(rho)): rho^2 1 mul, then the new
-# density sum_i A_i rho(j - c_i) + B_i rho^2(j - c_i) as 1 mul + (Q + 4 - 1) FMA.
+# Algorithmic flops and FP64 instructions of one site update (an FMA counts 2
+# flops and one instruction).  Population storage: density Q-1 adds; rho^2
+# 1 mul; A_i rho 1 mul for c = 0 and one per +-c pair (A is even in c); one
+# FMA per population with G != 0 (c = +-1, +-2) for G_i rho^2 + A_i rho; one
+# FMA per population for (1 - omega) g_i + feq_i.  D1Q7: 6 adds + 5 muls +
+# 11 FMAs = 22 instructions, 33 flops; D1Q5: 4 + 4 + 9 = 17, 26.  Rho-only
+# storage (tau = 1, post-collision populations feq(rho)): each site's outgoing
+# populations A_i rho + B_i rho^2 from its density (rho^2, A_0 rho and one
+# A rho per pair, 4 FMAs), then the density sum over the Q incoming ones:
+# D1Q7 1 + 4 + 4 + 6 = 15 instructions, 19 flops; D1Q5 1 + 3 + 4 + 4 = 12, 16.
+# The conversions the FP32 and split storages add are not counted: they are
+# overhead of the storage, not of the method.
 def flops_per_site_update(q: int, precision: str = "fp64") -> int:
-    with_g = 4
     if precision == "rho":
-        return 1 + 1 + 2 * (q + with_g - 1)
-    return (q - 1) + (2 + (q - 1) // 2) + 2 * (with_g + q)
+        return {7: 19, 5: 16}[q]
+    return {7: 33, 5: 26}[q]
 
 
-# FP64 VALU instructions of one site update (each add, mul or FMA one issue):
-# D1Q7 6 + 5 + 11 = 22, D1Q5 4 + 4 + 9 = 17.  A wave64 FP64 instruction issues
-# in 4 clocks on a 16-lane SIMD, so one SIMD retires 16 / 22 D1Q7 updates per
-# clock: 1024 SIMDs x 2.4 GHz x 16 / 22 = 1.79e12 updates/s is the VALU ceiling.
-def valu_per_site_update(q: int) -> int:
+def valu_per_site_update(q: int, precision: str = "fp64") -> int:
+    if precision == "rho":
+        return {7: 15, 5: 12}[q]
     return {7: 22, 5: 17}[q]
 
 
-def valu_ceiling_glups(q: int, simds: int = N_SIMD) -> float:
-    return simds * CLOCK_GHZ * 16.0 / valu_per_site_update(q)
+# The ALU roofline of the path.  A wave64 FP64 instruction issues in 4 clocks
+# on a 16-lane SIMD (64 FP64 lanes per CU per clock; the published 78.6 TFLOP/s
+# counts every instruction as an FMA), so 1024 SIMDs x 16 lanes x 2.4 GHz /
+# 22 = 1.79e12 D1Q7 updates/s is the issue ceiling, or 1024 x 16 x 2.4e9 x 33 /
+# 22 = 59.0 TFLOP/s of the update's own flops.
+def valu_ceiling_glups(q: int, simds: int = N_SIMD, precision: str = "fp64") -> float:
+    return simds * CLOCK_GHZ * 16.0 / valu_per_site_update(q, precision)
+
+
+def alu_peak_tflops(q: int, precision: str = "fp64", simds: int = N_SIMD) -> float:
+    return valu_ceiling_glups(q, simds, precision) * flops_per_site_update(q, precision) / 1e3
+
+
+ALU_PEAK_BASIS = ("FP64 VALU issue ceiling from unit counts and clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, "
+                  "at the update's own flops per FP64 instruction (D1Q7 33 / 22, D1Q5 26 / 17, rho-only 19 / 15 "
+                  "and 16 / 12); frac_of_published_fp64_peak is against 78.6 TFLOP/s, which counts every "
+                  "instruction as an FMA")
 
 
 # Algorithmic HBM bytes of one s = 1 step per site: read Q populations and
@@ -326,11 +343,12 @@ def run_lattice(w, precision, kernel, solves, warmup, tile_steps=0, autotune=Fal
                 "frac": ach / PEAK_HBM_GBS, "traffic": None}
     else:
         ach = flops_per_site_update(w.q, precision) * units / (kernel_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": None}
+        peak = alu_peak_tflops(w.q, precision)
+        roof = {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "traffic": None, "peak_basis": ALU_PEAK_BASIS,
+                "frac_of_published_fp64_peak": ach / PEAK_FP64_VECTOR_TFLOPS}
         glups_kernel = units / (kernel_ms * 1e-3) / 1e9
-        roof["valu_ceiling_glups"] = valu_ceiling_glups(w.q)
-        roof["frac_of_valu_ceiling"] = glups_kernel / valu_ceiling_glups(w.q)
+        roof["valu_ceiling_glups"] = valu_ceiling_glups(w.q, precision=precision)
         if kernel in ("resident", "span"):
             # execution resources the launch can use: one workgroup of 8 waves
             # on one CU (4 SIMDs) for resident; one single-wave owner per SIMD
@@ -340,8 +358,7 @@ def run_lattice(w, precision, kernel, solves, warmup, tile_steps=0, autotune=Fal
                 roof["steps_between_exchanges"] = shape["exchange_steps"]
                 roof["workgroups"] = simds
             roof["simds_used"] = simds
-            roof["frac_of_used_simds"] = ach / (PEAK_FP64_VECTOR_TFLOPS * simds / N_SIMD)
-            roof["frac_of_used_simds_valu_ceiling"] = glups_kernel / valu_ceiling_glups(w.q, simds)
+            roof["frac_of_used_simds"] = ach / alu_peak_tflops(w.q, precision, simds)
             roof["ns_per_step"] = kernel_ms * 1e6 / (w.steps / launches)
     if kernel == "tiled" and peaks:
         # the tile engine trades 12 (D1Q7) or 6 (D1Q5) values per lane and step
@@ -506,6 +523,7 @@ def run_ensemble(precision, instances, lb_steps, solves=3, warmup=1, chunk=0, se
     lat.close()
     fl = flops_per_site_update(7, precision)
     ach = fl * su / (float(np.mean(sol_ms)) * 1e-3) / 1e12
+    peak = alu_peak_tflops(7, precision)
     out = {"workload": "ensemble_d1q7_%d" % len(sizes), "precision": precision, "value": value,
            "unit": "GLUPS", "ms_per_solve": 1e3 * total / solves, "solves": solves, "warmup": warmup,
            "site_updates_per_solve": su, "instances": len(sizes), "mean_n": float(np.mean(sizes)),
@@ -516,9 +534,9 @@ def run_ensemble(precision, instances, lb_steps, solves=3, warmup=1, chunk=0, se
            # algorithmic flops of the site updates (halo re-computation not
            # counted) over the solve time from HIP events on the ensemble's
            # stream (init and readout included), against the FP64 vector peak
-           "roofline": {"bound": "alu", "kernel": "k_ens", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
-                        "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS,
-                        "frac_of_valu_ceiling": su / (float(np.mean(sol_ms)) * 1e-3) / 1e9 / valu_ceiling_glups(7),
+           "roofline": {"bound": "alu", "kernel": "k_ens", "achieved": ach, "peak": peak,
+                        "unit": "TFLOP/s", "frac": ach / peak, "peak_basis": ALU_PEAK_BASIS,
+                        "frac_of_published_fp64_peak": ach / PEAK_FP64_VECTOR_TFLOPS,
                         "traffic": measured_traffic("k_ens", "ensemble_d1q7_%d" % len(sizes), precision),
                         "traffic_unit": "bytes per chunk launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                         "traffic_algorithmic": bytes_per_site_update(7, precision) * float(np.sum(sizes))}}
@@ -576,6 +594,9 @@ def run_serve(rate, requests, budget_gib=4.0, chunk=0, round_steps=0, serve_fp32
     for r in reqs:
         su[r.q] += r.n * r.steps
     flops = sum(flops_per_site_update(q) * v for q, v in su.items())
+    # the issue ceiling for this mix of schemes: the wall time the mix's FP64
+    # instructions would take at full issue on every SIMD
+    t_issue = sum(valu_per_site_update(q) * v for q, v in su.items()) / (N_SIMD * 16 * CLOCK_GHZ * 1e9)
     out = {"workload": "serve_%d_requests" % len(reqs), "rate_per_s": rate,
            "fp32_requests_storage": serve_fp32, "budget_bytes": srv.arena.size,
            "offered_glups": float(sum(r.n * r.steps for r in reqs) / reqs[-1].arrival / 1e9)}
@@ -586,8 +607,10 @@ def run_serve(rate, requests, budget_gib=4.0, chunk=0, round_steps=0, serve_fp32
     # the ensemble kernel's work (algorithmic flops of the site updates) over
     # the wall time of the whole served stream
     ach = flops / st.wall / 1e12
-    out["roofline"] = {"bound": "alu", "kernel": "k_ens", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS,
-                       "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": None}
+    peak = flops / t_issue / 1e12
+    out["roofline"] = {"bound": "alu", "kernel": "k_ens", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                       "frac": ach / peak, "peak_basis": ALU_PEAK_BASIS,
+                       "frac_of_published_fp64_peak": ach / PEAK_FP64_VECTOR_TFLOPS, "traffic": None}
     if cpu:
         # the oracle on a seeded sample of 16 of the requests (FP64 arithmetic for all)
         from paper_1711_03540_amd.inputs import SplitMix64
@@ -1063,11 +1086,22 @@ def bench_all(args):
         out["gpu_over_cpu"] = head["gpu_over_cpu"]
     out["peaks"] = peaks
     configs = {}
+    # the large lattice in FP32 storage (the configuration names FP32 and
+    # FP64), and in the rho-only state: at tau = 1 (this lattice's tau) the
+    # collision leaves f = feq(rho), the densities are bitwise those of the
+    # FP64 populations, and the state is one double per site
+    w4 = inputs.CFG_LARGE_Q7
+    for prec in ("fp32", "rho"):
+        r = run_lattice(w4, prec, "tiled", max(5, args.steps // 2), 1, plain=not args.no_plain, cpu=False,
+                        peaks=peaks)
+        configs["%s_%s" % (w4.name, prec)] = r
     w0, w1 = inputs.CFG_SMALL_Q5, inputs.CFG_RESIDENT_Q7
     configs[w0.name] = run_lattice(w0, "fp64", "span", 100, 5, plain=not args.no_plain, cpu=cpu)
     configs[w1.name] = run_lattice(w1, "fp64", "span", 30, 2, plain=not args.no_plain, cpu=cpu)
-    ens64 = run_ensemble("fp64", args.instances, args.lb_steps, cpu=cpu)
-    ens32 = run_ensemble("fp32", args.instances, args.lb_steps, cpu=False)
+    # the ensemble's tiling (sites per lane, steps per chunk, instance tiles
+    # per workgroup window) picked by the autotuner for each storage
+    ens64 = run_ensemble("fp64", args.instances, args.lb_steps, autotune=True, cpu=cpu)
+    ens32 = run_ensemble("fp32", args.instances, args.lb_steps, autotune=True, cpu=False)
     configs[ens64["workload"]] = ens64
     configs[ens64["workload"] + "_fp32"] = ens32
     srv = run_serve(2000.0, args.requests, args.budget_gib, serve_fp32=args.serve_fp32, cpu=cpu)

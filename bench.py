@@ -361,14 +361,21 @@ def run_lattice(w, precision, kernel, solves, warmup, tile_steps=0, autotune=Fal
             roof["frac_of_used_simds"] = ach / alu_peak_tflops(w.q, precision, simds)
             roof["ns_per_step"] = kernel_ms * 1e6 / (w.steps / launches)
     if kernel == "tiled" and peaks:
-        # the tile engine trades 12 (D1Q7) or 6 (D1Q5) values per lane and step
-        # through LDS, each written once and read once: 2 x 8 x 12 / 8 = 24 B
-        # per computed site update of 8 sites per lane (FP64), against the
-        # measured LDS read peak
-        per_lane = {7: 12, 5: 6}[w.q] * (4 if precision == "fp32" else 8) * 2
-        sites = 16 if precision == "rho" else 8
+        # the tile engine trades 12 (D1Q7) or 6 (D1Q5) populations per lane and
+        # step through LDS (the rho-only state 2 H densities), each written once
+        # and read once: 2 x 8 x 12 / 12 = 16 B per computed site update of 12
+        # sites per lane (FP64), against the measured LDS read peak.  Sites per
+        # lane from the launch: workgroups = ceil(N / (256 B - 2 H s)).
+        hh = 3 if w.q == 7 else 2
+        vals = 2 * hh if precision == "rho" else {7: 12, 5: 6}[w.q]
+        per_lane = vals * (4 if precision == "fp32" else 8) * 2
+        s_l = shape["steps_per_launch"]
+        b_est = (w.n / shape["workgroups"] + 2 * hh * s_l) / 256.0
+        sites = int(round(b_est))
+        assert abs(b_est - sites) < 0.05 and -(-w.n // (256 * sites - 2 * hh * s_l)) == shape["workgroups"], shape
         win = 256 * sites
-        valid = win - 2 * (3 if w.q == 7 else 2) * shape["steps_per_launch"]
+        valid = win - 2 * hh * s_l
+        roof["sites_per_lane"] = sites
         lds_b = per_lane / sites * units * win / valid
         lp = peaks["lds"]["bytes_per_clk_per_cu"] * N_CU * peaks["lds"]["shader_ghz"] * 1e9
         roof["lds_bytes_per_launch"] = lds_b

@@ -189,8 +189,16 @@ int ring_sites_per_lane(int64_t n, int q, int lds_bytes)
     return 0;
 }
 
-constexpr int kTileB = 8;
-int tile_sites_per_lane(int prec) { return prec == kRHO ? 16 : kTileB; }
+// Sites per lane of the tiled kernel: 12 FP64 (228 registers for D1Q7, two
+// waves per SIMD: a 3072-site window recomputes less halo per stored site
+// than 2048 sites at three waves; on N = 2^24 D1Q7 1060 against 1026 GLUPS,
+// D1Q5 1447 against 1411), 16 for the rho-only state, 8 for FP32 and split
+// (at 12 the FP32 record needs 200 registers: 788 against 840 GLUPS).
+int tile_sites_per_lane(int prec)
+{
+    if (prec == kFP64) return 12;
+    return prec == kRHO ? 16 : 8;
+}
 
 // Device limits a plan assumes: SPAN owners that may run at once, and the
 // dynamic LDS one workgroup may use.
@@ -251,17 +259,18 @@ constexpr size_t kSpanSlotBytes = size_t(256) << 20;
 constexpr int64_t kSpanAutoMaxSites = 65536;
 constexpr int kSpanAutoMinSteps = 12;
 
-// Steps per tiled launch, a multiple of 8 so that every window starts on an
-// 8-site boundary.  Longer launches re-read the state less often but
+// Steps per tiled launch, even so that every lane's first site is even (its
+// 16-byte accesses).  Longer launches re-read the state less often but
 // recompute a wider halo (2 H s of the window's W sites).  Sweeps of s on
-// N = 2^24 put the optimum at 64 for D1Q7 FP64 (1001 GLUPS against 958 at
-// 40), 80 for D1Q5 FP64 and for the rho-only state of both schemes, 64 for
-// D1Q7 FP32 (810 GLUPS against 784 at 40) and 40 for D1Q7 split; other
-// combinations keep 2 H s <= W / 8.
+// N = 2^24 put the optimum at 80 for D1Q7 FP64 (1063 GLUPS; 1060 at 64,
+// 1063 at 96), 112 for D1Q5 FP64 (1447; 1396 at 64), 64 for the rho-only
+// D1Q7 state (1834 against 1782 at 80), 80 for rho-only D1Q5 (flat from 48
+// to 96), 64 for D1Q7 FP32 (840 against 816 at 80) and 40 for D1Q7 split;
+// other combinations keep 2 H s <= W / 8.
 int default_tile_steps(int q, int prec)
 {
-    if (prec == kFP64) return q == 7 ? 64 : 80;
-    if (prec == kRHO) return 80;
+    if (prec == kFP64) return q == 7 ? 80 : 112;
+    if (prec == kRHO) return q == 7 ? 64 : 80;
     if (q == 7) return prec == kFP32 ? 64 : 40;
     const int W = tile_lanes() * tile_sites_per_lane(prec);
     int s = W / (16 * halo(q));
@@ -1480,6 +1489,9 @@ kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* 
     E->count = count;
     E->q.assign(q, q + count);
     E->prec.assign(precision, precision + count);
+    // FP64 throughout: 12 sites per lane by default (3072-site windows: 862
+    // against 796 GLUPS for 4096 D1Q7 instances of 512 to 8192 sites)
+    if (std::all_of(precision, precision + count, [](int p) { return p == kFP64; })) E->B = 12;
     E->device = dev;
     E->buf = (char*)dev_buf;
     E->bytes = buf_bytes;
@@ -1542,10 +1554,14 @@ kslb_status kslb_ensemble_set_tiling(kslb_ensemble* E, int sites_per_lane, int m
     int B = sites_per_lane ? sites_per_lane : E->B;
     int m = max_segments ? max_segments : E->max_seg;
     int c = steps_per_chunk ? steps_per_chunk : E->chunk;
-    bool all_rho = true;
-    for (int i = 0; i < E->count; i++) all_rho = all_rho && E->prec[i] == kRHO;
-    if (B != 4 && B != 8 && !(B == 16 && all_rho))
-        return fail(KSLB_EINVAL, "sites_per_lane must be 4 or 8 (or 16 with the rho-only storage throughout)");
+    bool all_rho = true, all_fp64 = true;
+    for (int i = 0; i < E->count; i++) {
+        all_rho = all_rho && E->prec[i] == kRHO;
+        all_fp64 = all_fp64 && E->prec[i] == kFP64;
+    }
+    if (B != 4 && B != 8 && !(B == 12 && all_fp64) && !(B == 16 && all_rho))
+        return fail(KSLB_EINVAL, "sites_per_lane must be 4 or 8 (12 with FP64 storage throughout, 16 with the "
+                                 "rho-only storage throughout)");
     if (m < 1 || m > tile_lanes()) return fail(KSLB_EINVAL, "max_segments must lie in [1, %d]", tile_lanes());
     const int64_t W = (int64_t)tile_lanes() * B;
     if (c < 1 || W - 2 * ens_max_halo(E) * (int64_t)c < B)

@@ -80,11 +80,14 @@ __device__ __forceinline__ double dsum(const double (&g)[Q])
 // which take equal values at +c and -c, and from the first-moment weight w(1),
 // which changes sign; so e_{+c} = e_{-c} and g_{+c} = -g_{-c} exactly, and a
 // +-c pair shares its product e rho.  eq_one and eq_all round identically.
+// eq_one takes e of the pair's +c member, so that the two members evaluated
+// from one density share the product e rho
 template <int I>
 __device__ __forceinline__ double eq_one(double rho, const double* e, const double* g)
 {
-    if constexpr (has_g(I)) return __builtin_fma(g[I], rho * rho, e[I] * rho);
-    else return e[I] * rho;
+    constexpr int ie = (I > 0 && I % 2 == 0) ? I - 1 : I;
+    if constexpr (has_g(I)) return __builtin_fma(g[I], rho * rho, e[ie] * rho);
+    else return e[ie] * rho;
 }
 
 template <int Q>
@@ -900,8 +903,11 @@ __device__ __forceinline__ void window_lane(const char* __restrict__ src, char* 
     constexpr int L = kTileLD;
     const int lane = threadIdx.x;
     typename E::Site x[B];
+    // the 16-byte accesses need an even first site (rows are 256-byte aligned
+    // and their pitch is a multiple of 64 sites)
     const bool inside = j0 >= 0 && j0 + B <= n;
-    if (kVecIO<P> && inside && j0 % B == 0) {
+    const bool even = (j0 & 1) == 0;
+    if (kVecIO<P> && inside && even) {
         E::PL::template load_vec<B>(src, p, j0, x);
     } else if (inside) {
         unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, p, j0 + Bi); });
@@ -911,7 +917,7 @@ __device__ __forceinline__ void window_lane(const char* __restrict__ src, char* 
     const int left = lane == 0 ? L - 1 : lane - 1;
     const int right = lane + 1 == L ? 0 : lane + 1;
     E::run(x, s, xch, lane, left, right, true, cf);
-    if (kVecIO<P> && kl0 >= k_lo && kl0 + B <= k_lo + valid && inside && j0 % B == 0) {
+    if (kVecIO<P> && kl0 >= k_lo && kl0 + B <= k_lo + valid && inside && even) {
         E::PL::template store_vec<B>(dst, p, j0, x);
     } else {
         unroll<B>([&](auto Bi) {
@@ -937,8 +943,9 @@ __global__ __launch_bounds__(kTileLD) void k_tile(const char* __restrict__ src, 
 
 // Waves per SIMD the ensemble kernel is compiled for: three (the LDS
 // exchange areas of three workgroups fit a CU) where that costs at most a few
-// spills outside the step loop; split storage needs too many registers.
-constexpr int ens_waves_per_simd(int p) { return p == kSPLIT ? 1 : 3; }
+// spills outside the step loop; two for 12 FP64 sites per lane (228
+// registers); split storage needs too many registers.
+constexpr int ens_waves_per_simd(int p, int b) { return p == kSPLIT ? 1 : (b == 12 ? 2 : 3); }
 
 // Ensemble: workgroup w runs window hdr[w], whose segments seg[first ..
 // first + nseg) occupy consecutive lane ranges; each segment is one tile of
@@ -946,7 +953,7 @@ constexpr int ens_waves_per_simd(int p) { return p == kSPLIT ? 1 : 3; }
 // Lanes past the last segment's tile carry junk that is never stored.  The
 // window's coefficient set is uniform over the workgroup (scalar loads).
 template <int Q, int P, int B>
-__global__ __launch_bounds__(kTileLD) __attribute__((amdgpu_waves_per_eu(ens_waves_per_simd(P)))) void k_ens(const WinHdr* __restrict__ hdr,
+__global__ __launch_bounds__(kTileLD) __attribute__((amdgpu_waves_per_eu(ens_waves_per_simd(P, B)))) void k_ens(const WinHdr* __restrict__ hdr,
                                                  const SegDesc* __restrict__ seg, const Coef* __restrict__ coefs)
 {
     extern __shared__ double xch[];
@@ -1741,6 +1748,10 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
 {
     if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (tile_one<Q_, P_, 4>(src, dst, n, s, cf, stream))); }
     if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (tile_one<Q_, P_, 8>(src, dst, n, s, cf, stream))); }
+    if (B == 12 && prec == kFP64) {  // 12 sites per lane: FP64 populations only
+        if (q == 5) return tile_one<5, kFP64, 12>(src, dst, n, s, cf, stream);
+        return tile_one<7, kFP64, 12>(src, dst, n, s, cf, stream);
+    }
     if (B == 16 && prec == kRHO) {   // 16 sites per lane: rho-only state only
         if (q == 5) return tile_one<5, kRHO, 16>(src, dst, n, s, cf, stream);
         return tile_one<7, kRHO, 16>(src, dst, n, s, cf, stream);
@@ -1764,6 +1775,10 @@ int launch_ens(int q, int prec, int B, const WinHdr* hdr, const SegDesc* seg, in
     if (nwin <= 0) return 0;
     if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 4>(hdr, seg, nwin, cf, stream))); }
     if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (ens_one<Q_, P_, 8>(hdr, seg, nwin, cf, stream))); }
+    if (B == 12 && prec == kFP64) {
+        if (q == 5) return ens_one<5, kFP64, 12>(hdr, seg, nwin, cf, stream);
+        return ens_one<7, kFP64, 12>(hdr, seg, nwin, cf, stream);
+    }
     if (B == 16 && prec == kRHO) {
         if (q == 5) return ens_one<5, kRHO, 16>(hdr, seg, nwin, cf, stream);
         return ens_one<7, kRHO, 16>(hdr, seg, nwin, cf, stream);

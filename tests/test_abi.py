@@ -126,7 +126,7 @@ def test_plan_refuses_span_beyond_half_the_resident_owners():
     assert p["kernel"] == "resident" and p["workgroups"] == 1 and p["lanes"] == 512
     # ... or tiles, where it does not fit one workgroup
     p = plan_kernel(12345, 7, "fp64", span_owners=64, lds_bytes=LDS)
-    assert p["kernel"] == "tiled" and p["steps_per_launch"] == 64
+    assert p["kernel"] == "tiled" and p["steps_per_launch"] == 80
     # an explicit SPAN request that cannot fit is refused
     with pytest.raises(_lib.KslbError) as e:
         plan_kernel(4096, 7, "fp64", kernel="span", steps_per_launch=16, span_owners=255, lds_bytes=LDS)

@@ -408,14 +408,18 @@ def test_ensemble_graph_replays_match_eager_launches():
 @pytest.mark.parametrize("q,prec", [(7, "fp64"), (5, "fp64"), (7, "split"), (5, "fp32")])
 def test_ensemble_packing_and_chunking_bitwise(q, prec):
     # packed windows (several instance tiles per workgroup), one tile per
-    # workgroup, 4 or 8 sites per lane and any chunk length give the same bits
+    # workgroup, 4, 8 (or, FP64, 12) sites per lane and any chunk length give
+    # the same bits
     say("case ensemble packing q=%d %s" % (q, prec))
     sizes = [5, 100, 333, 640, 1500, 2048, 3001, 7777]
     steps = [40, 77, 64, 5, 100, 31, 64, 90]
     dX, dT = 0.2, 1e-4
     rho0s = [ic(n, dX, 50 + i) for i, n in enumerate(sizes)]
     outs = []
-    for B, segs, chunk in ((8, 16, 32), (8, 1, 32), (4, 16, 16), (8, 256, 7), (8, 3, 40)):
+    tilings = [(8, 16, 32), (8, 1, 32), (4, 16, 16), (8, 256, 7), (8, 3, 40)]
+    if prec == "fp64":
+        tilings += [(12, 16, 32), (12, 1, 41), (12, 5, 96)]
+    for B, segs, chunk in tilings:
         ens = Ensemble(sizes, q, prec).set_physical(dX, dT, 1.1).set_tiling(B, segs, chunk)
         for i, r in enumerate(rho0s):
             ens.init_rho(i, r)
@@ -503,6 +507,8 @@ def test_ensemble_per_instance_errors():
         ens.init_rho(0, np.ones(64))                       # coefficients first
     with pytest.raises(KslbError):
         ens.set_tiling(16, 0, 0)                           # 16 sites per lane: rho-only throughout
+    with pytest.raises(KslbError):
+        ens.set_tiling(12, 0, 0)                           # 12 sites per lane: FP64 throughout
     ens.set_physical(0.3, 2e-4, 1.0)                       # every instance, one set per scheme
     assert ens.tau_of(0) == ens.tau_of(1) == ens.tau_of(2) == 1.0
     ens.set_physical(0.3, 2e-4, 1.1, idx=2)
@@ -844,7 +850,7 @@ def test_resolved_kernel_and_launch_shape():
     assert k["kernel"] == "span" and k["steps_per_launch"] % k["exchange_steps"] == 0
     assert k["exchange_steps"] >= 1 and k["workgroups"] >= 2 and k["lanes"] == 64
     n = 100_000
-    for prec, sites, s_default in (("fp64", 8, 64), ("rho", 16, 80)):
+    for prec, sites, s_default in (("fp64", 12, 80), ("rho", 16, 64), ("fp32", 8, 64)):
         lat = Lattice(n, 7, prec).set_physical(0.3, 2e-4, 1.0)
         k = lat.kernel()
         s = k["steps_per_launch"]
@@ -860,7 +866,7 @@ def test_resolved_kernel_and_launch_shape():
     k = make(7, 4096, kernel="resident").kernel()
     assert k["kernel"] == "resident" and k["workgroups"] == 1
     k = make(7, 4096, kernel="tiled", steps_per_launch=24).kernel()
-    assert k["steps_per_launch"] == 24 and k["workgroups"] == -(-4096 // (2048 - 144))
+    assert k["steps_per_launch"] == 24 and k["workgroups"] == -(-4096 // (3072 - 144))
     # fixed ends beyond the SPAN size run on PLAIN
     lat = make(7, 70001)
     lat.set_fixed_ends(1.0, 2.0)

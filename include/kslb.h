@@ -338,8 +338,11 @@ kslb_status kslb_ensemble_set_tiling(kslb_ensemble* ens, int sites_per_lane, int
 
 /* Steady-state graphs (default on): when every instance still to advance
  * has at least four more full chunks, the two alternating chunk launches are
- * captured once as a HIP graph (kernel nodes only) and replayed.  Results
- * are bitwise those of the launch-per-chunk path.                          */
+ * captured as a HIP graph (kernel nodes only) and replayed, provided one call
+ * replays them at least four times or the same pair recurs from the
+ * previous call; otherwise they are launched directly.  A replaced graph is
+ * destroyed once its replays have completed, without blocking the caller.
+ * Results are bitwise those of the launch-per-chunk path.                  */
 kslb_status kslb_ensemble_set_graphs(kslb_ensemble* ens, int enable);
 
 /* The tau instance idx uses (after the fit and the guard). */

@@ -989,6 +989,8 @@ struct kslb_ensemble {
     hipStream_t cap_stream = nullptr;       // private stream the graph is recorded on
     hipGraphExec_t gexec = nullptr;
     uint64_t gkey[5] = {0, 0, 0, 0, 0};
+    uint64_t gseen[5] = {0, 0, 0, 0, 0};    // last pair of plans that ran eagerly
+    std::vector<std::pair<hipGraphExec_t, hipEvent_t>> retired;   // graphs that may still run
     double* staging = nullptr;
     int64_t staging_n = 0;
     // batched init and readout: descriptor (and coefficient) tables, each
@@ -1257,7 +1259,11 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, EnsPlan* pla
     E->next_slot = k ^ 1;
     E->slot_gen[k]++;
     E->sig[k].clear();   // the slot holds no valid plan until the upload below is enqueued
+    // the tables grow geometrically: an ensemble whose active set grows call
+    // by call (continuous admission) reallocates, and waits for its stream,
+    // a logarithmic number of times
     if (E->d_cap[k] < bytes) {
+        const size_t want = std::max(bytes, 2 * E->d_cap[k]);
         if (E->d_tab[k]) {
             (void)hipStreamSynchronize(E->stream);
             (void)hipFree(E->d_tab[k]);
@@ -1265,9 +1271,9 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, EnsPlan* pla
             E->d_cap[k] = 0;
         }
         void* p = nullptr;
-        if (hipMalloc(&p, bytes)) return fail(KSLB_ENOMEM, "descriptor allocation of %zu bytes failed", bytes);
+        if (hipMalloc(&p, want)) return fail(KSLB_ENOMEM, "descriptor allocation of %zu bytes failed", want);
         E->d_tab[k] = (char*)p;
-        E->d_cap[k] = bytes;
+        E->d_cap[k] = want;
     }
     // pinned staging: wait for this slot's previous upload before rewriting it
     if (E->up_pending[k]) {
@@ -1276,13 +1282,14 @@ kslb_status ens_plan(kslb_ensemble* E, const std::vector<int>& adv, EnsPlan* pla
         E->up_pending[k] = false;
     }
     if (E->h_cap[k] < bytes) {
+        const size_t want = std::max(bytes, 2 * E->h_cap[k]);
         if (E->h_pin[k]) (void)hipHostFree(E->h_pin[k]);
         E->h_pin[k] = nullptr;
         E->h_cap[k] = 0;
         void* hp = nullptr;
-        if (hipHostMalloc(&hp, bytes, hipHostMallocDefault)) return fail(KSLB_ENOMEM, "pinned staging allocation failed");
+        if (hipHostMalloc(&hp, want, hipHostMallocDefault)) return fail(KSLB_ENOMEM, "pinned staging allocation failed");
         E->h_pin[k] = (char*)hp;
-        E->h_cap[k] = bytes;
+        E->h_cap[k] = want;
     }
     if (!E->up_ev[k] && hipEventCreateWithFlags(&E->up_ev[k], hipEventDisableTiming))
         return fail(KSLB_EDEVICE, "hipEventCreate failed");
@@ -1319,6 +1326,42 @@ int ens_launch(const kslb_ensemble* E, const EnsPlan& plan, hipStream_t stream)
 // once as a graph of their kernel launches, replayed `pairs` times.  The
 // graph holds kernels only (no memset or copy nodes); it is rebuilt whenever
 // either slot is rewritten.
+constexpr int64_t kGraphMinPairs = 4;
+
+// Retire the current graph: record an event behind its replays on the
+// ensemble's stream and keep both until the event has completed.
+kslb_status ens_retire_graph(kslb_ensemble* E)
+{
+    hipEvent_t ev = nullptr;
+    int e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (!e) e = hipEventRecord(ev, E->stream);
+    if (e) {
+        if (ev) (void)hipEventDestroy(ev);
+        return hip_fail(e, "graph retirement event");
+    }
+    E->retired.push_back({E->gexec, ev});
+    E->gexec = nullptr;
+    return KSLB_OK;
+}
+
+// Destroy the retired graphs whose replays have completed (all of them,
+// waiting, when wait is set).
+void ens_reap_graphs(kslb_ensemble* E, bool wait)
+{
+    size_t keep = 0;
+    for (size_t k = 0; k < E->retired.size(); k++) {
+        auto& r = E->retired[k];
+        const bool done = wait ? hipEventSynchronize(r.second) == hipSuccess : hipEventQuery(r.second) == hipSuccess;
+        if (done || wait) {
+            (void)hipGraphExecDestroy(r.first);
+            (void)hipEventDestroy(r.second);
+        } else {
+            E->retired[keep++] = r;
+        }
+    }
+    E->retired.resize(keep);
+}
+
 kslb_status ens_replay_pairs(kslb_ensemble* E, const std::vector<int>& adv, int64_t pairs)
 {
     EnsPlan pa, pb;
@@ -1332,11 +1375,25 @@ kslb_status ens_replay_pairs(kslb_ensemble* E, const std::vector<int>& adv, int6
     const uint64_t key[5] = {(uint64_t)pa.slot, E->slot_gen[pa.slot], (uint64_t)pb.slot, E->slot_gen[pb.slot],
                              ((uint64_t)E->B << 32) | (uint64_t)(pa.nwin + pb.nwin)};
     if (!E->gexec || std::memcmp(key, E->gkey, sizeof key) != 0) {
-        if (E->gexec) {
-            (void)hipStreamSynchronize(E->stream);
-            (void)hipGraphExecDestroy(E->gexec);
-            E->gexec = nullptr;
+        // Recording and instantiating a graph pays for a pair of plans that
+        // one call replays at least kGraphMinPairs times or that recurs; a
+        // layout that changes every call (continuous admission) launches
+        // directly.
+        if (pairs < kGraphMinPairs && std::memcmp(key, E->gseen, sizeof key) != 0) {
+            std::memcpy(E->gseen, key, sizeof key);
+            for (int64_t r = 0; r < pairs; r++) {
+                int e = ens_launch(E, pa, E->stream);
+                if (!e) e = ens_launch(E, pb, E->stream);
+                if (e) return hip_fail(e, "ensemble kernel");
+            }
+            return KSLB_OK;
         }
+        // the previous graph may still run: it is destroyed once an event
+        // recorded after its last replay has completed, without waiting here
+        if (E->gexec) {
+            if (auto st = ens_retire_graph(E)) return st;
+        }
+        ens_reap_graphs(E, false);
         // record on a private stream (the caller's may be the null stream,
         // which cannot be captured); replay on the caller's stream
         if (!E->cap_stream) {
@@ -1935,6 +1992,7 @@ kslb_status kslb_ensemble_destroy(kslb_ensemble* E)
     DeviceGuard g(E->device);
     (void)hipStreamSynchronize(E->stream);
     if (E->gexec) (void)hipGraphExecDestroy(E->gexec);
+    ens_reap_graphs(E, true);
     if (E->cap_stream) (void)hipStreamDestroy(E->cap_stream);
     for (int k = 0; k < 2; k++) {
         if (E->d_tab[k]) (void)hipFree(E->d_tab[k]);

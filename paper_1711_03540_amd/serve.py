@@ -22,7 +22,9 @@ initialise on the device, without synchronising), advances every class by one
 round of up to ``round_steps`` steps (the ensemble launches one kernel per chunk
 for all of the class's active requests, so requests admitted while others run
 share their launches), and retires finished requests: their density is read out
-on the class's stream and their completion is observed through an event.
+on the class's stream and their completion is observed through an event.  Each
+round takes the widest tiling (sites per lane) whose windows over the class's
+active requests still fill the device, narrower ones while few requests run.
 Classes run on separate streams, so their kernels overlap on the device.  The
 per-site arithmetic is the library's, identical for a request alone and in any
 mix.
@@ -123,6 +125,34 @@ class Result:
         return self.completed - self.arrival
 
 
+# Workgroup windows one class's launch should reach before it takes wider
+# tiles: wide windows recompute less halo per site (the better throughput
+# once the device is full), narrow ones split a few large requests over more
+# workgroups (the shorter solve while it is not).
+WINDOWS_TARGET = 128
+LANES = 256
+
+
+def tile_width(n, q: int, widths: Sequence[int], chunk: int, target: int = WINDOWS_TARGET) -> int:
+    """Sites per lane for a round over requests of n sites: the first (widest)
+    of ``widths`` at which the requests' tiles fill at least ``target``
+    windows of LANES lanes, else the last.  A request of n sites takes
+    ceil(n / valid) tiles of at most valid = LANES * width - 2 max|c| chunk
+    sites, each with 2 max|c| chunk halo sites, at width sites per lane;
+    small tiles share windows."""
+    n = np.asarray(n, dtype=np.int64)
+    h = 3 if q == 7 else 2
+    for b in widths:
+        valid = LANES * b - 2 * h * chunk
+        if valid < b:
+            continue
+        tiles = -(-n // valid)
+        lanes = -(-(n + tiles * 2 * h * chunk) // b)
+        if int(lanes.sum()) >= target * LANES:
+            return b
+    return widths[-1]
+
+
 class _Pool:
     """One (scheme, storage) class: an ensemble of request descriptors on its own stream."""
 
@@ -130,6 +160,9 @@ class _Pool:
                  tau: float = 0.0):
         import torch
         self.q, self.precision = q, precision
+        self.chunk = chunk
+        self.widths = (12, 8, 4) if precision == "fp64" else (8, 4)
+        self.width = None
         self.stream = torch.cuda.Stream(device=device)          # default priority
         # descriptors start bound to one-site placeholders in the ensemble's own buffer
         self.ens = Ensemble([1] * slots, q, precision, device=device, stream=self.stream)
@@ -149,10 +182,20 @@ class _Pool:
         self.remaining[slot] = steps
         self.owner[slot] = res
 
+    def pick_width(self) -> None:
+        """Sites per lane for the next round: the widest tiling whose windows
+        over the active requests reach WINDOWS_TARGET, else the narrowest.
+        Every width computes the same bits."""
+        width = tile_width(self.ens.n[list(self.owner)], self.q, self.widths, self.chunk)
+        if width != self.width:
+            self.ens.set_tiling(width, 0, 0)
+            self.width = width
+
     def launch(self, round_steps: int) -> bool:
         import torch
         if not self.owner:
             return False
+        self.pick_width()
         adv = np.minimum(self.remaining, round_steps)
         self.ens.advance(adv)
         self.remaining -= adv

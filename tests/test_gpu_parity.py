@@ -395,7 +395,9 @@ def test_ensemble_graph_replays_match_eager_launches():
     for e in (a, b):
         for i, r in enumerate(rho0s):
             e.init_rho(i, r)
-    for rnd, steps in enumerate(([200] * 5, [160, 96, 300, 0, 64], [128] * 5)):
+    # chunk pairs: 6 replays (recorded), 2 (launched directly), 4 (recorded),
+    # then 2 twice (the same pair recurs: recorded on the second call)
+    for rnd, steps in enumerate(([200] * 5, [160, 96, 300, 0, 64], [128] * 5, [64] * 5, [64] * 5)):
         a.advance(steps)
         torch.cuda.synchronize()
         _ = torch.ones(1000, device="cuda").sum().item()      # eager work between replays

@@ -71,3 +71,25 @@ def test_arena_holds_requests_up_to_its_budget():
     while a.alloc(instance_bytes(65536, 7, "fp64")) is not None:
         n_fit += 1
     assert n_fit == ((4 << 30) - 2 * big) // instance_bytes(65536, 7, "fp64")
+
+
+def test_tile_width_follows_load():
+    from paper_1711_03540_amd.serve import tile_width
+    # D1Q7, 64-step chunks: windows keep 3072 - 384 = 2688 (12 sites per
+    # lane), 1664 (8) or 640 (4) sites
+    assert tile_width([2688] * 128, 7, (12, 8, 4), 64) == 12
+    assert tile_width([2688] * 127, 7, (12, 8, 4), 64) == 8      # 127 x 2 windows at 8 sites
+    assert tile_width([1664] * 127, 7, (12, 8, 4), 64) == 4      # 127 x 3 windows at 4 sites
+    assert tile_width([65536], 7, (12, 8, 4), 64) == 4           # one large request: the most windows
+    assert tile_width([65536] * 6, 7, (12, 8, 4), 64) == 12      # 6 x 25 windows
+    # D1Q5 keeps 2 x 2 x 64 = 256 halo sites: 2816 per 12-site window
+    assert tile_width([2816] * 128, 5, (12, 8, 4), 64) == 12
+    assert tile_width([2817] * 128, 5, (12, 8, 4), 64) == 12     # two tiles each, 278 lanes
+    assert tile_width([2817] * 64, 5, (12, 8, 4), 64) == 4       # 69 windows at 12, 104 at 8
+    # small requests share windows: 256 sites fill 54 lanes at 12 sites per
+    # lane (106 windows for 500 requests) and 80 at 8 (156 windows)
+    assert tile_width([256] * 500, 7, (12, 8, 4), 64) == 8
+    assert tile_width([256] * 700, 7, (12, 8, 4), 64) == 12
+    # FP32 and split classes choose between 8 and 4
+    assert tile_width([1664] * 200, 7, (8, 4), 64) == 8
+    assert tile_width([100] * 10, 7, (8, 4), 64) == 4

@@ -165,10 +165,12 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1711_03540_amd", "csrc", "kslb_kernels
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
-def measured_traffic(kname: str, workload: str, precision: str):
+def measured_traffic(kname: str, workload: str, precision: str, launch: dict = None):
     """HBM bytes per dispatch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs
-    (scaled by the copy calibration); None when absent or when the kernel source
-    changed since the counters were taken."""
+    (scaled by the copy calibration); None when absent, when the kernel source
+    changed since the counters were taken, or when this run's launch shape
+    (steps per launch, workgroups; an ensemble's tiling) differs from the
+    counted one."""
     import hashlib
     try:
         data = json.load(open(TRAFFIC_FILE))
@@ -177,6 +179,8 @@ def measured_traffic(kname: str, workload: str, precision: str):
         return None
     e = data.get("entries", {}).get("%s/%s/%s" % (kname, workload, precision))
     if not e or e.get("kernel_source_sha256") != sha:
+        return None
+    if launch is not None and any(launch.get(k) != v for k, v in e.get("launch", {}).items()):
         return None
     return e["fetch_bytes"] + e["write_bytes"]
 
@@ -381,7 +385,8 @@ def run_lattice(w, precision, kernel, solves, warmup, tile_steps=0, autotune=Fal
         roof["lds_bytes_per_launch"] = lds_b
         roof["lds_achieved_gb_s"] = lds_b / (kernel_ms * 1e-3) / 1e9
         roof["lds_frac_of_measured_peak"] = lds_b / (kernel_ms * 1e-3) / lp
-    roof["traffic"] = measured_traffic(kname, w.name, precision)
+    roof["traffic"] = measured_traffic(kname, w.name, precision,
+                                       {k: shape[k] for k in ("steps_per_launch", "exchange_steps", "workgroups")})
     roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["traffic_algorithmic"] = bytes_per_site_update(w.q, precision) * w.n
     roof["kernel"] = kname
@@ -421,6 +426,10 @@ def run_lattice(w, precision, kernel, solves, warmup, tile_steps=0, autotune=Fal
         pk = {"kernel": "k_plain", "glups": pg, "timed_lb_steps": psteps, "speedup": value / pg,
               "bitwise_identical_state_after_%d_steps" % chk: same,
               "hbm_gb_s": hbm, "hbm_frac": hbm / PEAK_HBM_GBS}
+        rs = ref.kernel()
+        pk["traffic"] = measured_traffic("k_plain", w.name, precision,
+                                         {k: rs[k] for k in ("steps_per_launch", "exchange_steps", "workgroups")})
+        pk["traffic_algorithmic"] = bytes_per_site_update(w.q, precision) * w.n
         if w.n >= (1 << 20):
             pk["hbm_frac_target"] = TARGET_HBM_FRAC
             pk["meets_target"] = hbm / PEAK_HBM_GBS >= TARGET_HBM_FRAC
@@ -470,6 +479,7 @@ def run_ensemble(precision, instances, lb_steps, solves=3, warmup=1, chunk=0, se
         tuned = tune.tune_ensemble(sizes, 7, precision, cache=None)
         tune.apply_ensemble(ens, tuned)
         log("autotuned ensemble tiling %s" % tuned["best"])
+    tiling = ens.tiling()
     ics = [inputs.random_modes_ic(int(n), n * dX, seed=1000 + i) for i, n in enumerate(sizes)]
     rho_all = torch.tensor(np.concatenate(ics), device=dev)       # every instance's density, in HBM
     rho_out = torch.empty_like(rho_all)
@@ -540,11 +550,12 @@ def run_ensemble(precision, instances, lb_steps, solves=3, warmup=1, chunk=0, se
            "errors": errors, "autotuned": tuned["best"] if tuned else None,
            # algorithmic flops of the site updates (halo re-computation not
            # counted) over the solve time from HIP events on the ensemble's
-           # stream (init and readout included), against the FP64 vector peak
+           # stream (init and readout included), against the FP64 issue ceiling
            "roofline": {"bound": "alu", "kernel": "k_ens", "achieved": ach, "peak": peak,
                         "unit": "TFLOP/s", "frac": ach / peak, "peak_basis": ALU_PEAK_BASIS,
                         "frac_of_published_fp64_peak": ach / PEAK_FP64_VECTOR_TFLOPS,
-                        "traffic": measured_traffic("k_ens", "ensemble_d1q7_%d" % len(sizes), precision),
+                        "traffic": measured_traffic("k_ens", "ensemble_d1q7_%d" % len(sizes), precision, tiling),
+                        "tiling": tiling,
                         "traffic_unit": "bytes per chunk launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                         "traffic_algorithmic": bytes_per_site_update(7, precision) * float(np.sum(sizes))}}
     ens.close()

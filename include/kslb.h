@@ -336,6 +336,10 @@ kslb_status kslb_ensemble_set_physical(kslb_ensemble* ens, int idx, double dX, d
 kslb_status kslb_ensemble_set_tiling(kslb_ensemble* ens, int sites_per_lane, int max_segments,
                                      int steps_per_chunk);
 
+/* The tiling in effect (any output pointer may be NULL).  Host only.      */
+kslb_status kslb_ensemble_get_tiling(const kslb_ensemble* ens, int* sites_per_lane, int* max_segments,
+                                     int* steps_per_chunk);
+
 /* Steady-state graphs (default on): when every instance still to advance
  * has at least four more full chunks, the two alternating chunk launches are
  * captured as a HIP graph (kernel nodes only) and replayed, provided one call

@@ -72,6 +72,7 @@ SIGNATURES = {
     "kslb_ensemble_set_physical": (_st, [_vp, _i, _d, _d, _d, _i, _i, _d]),
     "kslb_ensemble_get_tau": (_st, [_vp, _i, _vp]),
     "kslb_ensemble_set_tiling": (_st, [_vp, _i, _i, _i]),
+    "kslb_ensemble_get_tiling": (_st, [_vp, _vp, _vp, _vp]),
     "kslb_ensemble_set_graphs": (_st, [_vp, _i]),
     "kslb_ensemble_resize": (_st, [_vp, _i, _i64]),
     "kslb_instance_bytes": (_sz, [_i64, _i, _i]),

@@ -1629,6 +1629,16 @@ kslb_status kslb_ensemble_set_tiling(kslb_ensemble* E, int sites_per_lane, int m
     return KSLB_OK;
 }
 
+kslb_status kslb_ensemble_get_tiling(const kslb_ensemble* E, int* sites_per_lane, int* max_segments,
+                                     int* steps_per_chunk)
+{
+    if (!E) return fail(KSLB_EINVAL, "null ensemble");
+    if (sites_per_lane) *sites_per_lane = E->B;
+    if (max_segments) *max_segments = E->max_seg;
+    if (steps_per_chunk) *steps_per_chunk = E->chunk;
+    return KSLB_OK;
+}
+
 kslb_status kslb_ensemble_set_graphs(kslb_ensemble* E, int enable)
 {
     if (!E) return fail(KSLB_EINVAL, "null ensemble");

@@ -64,8 +64,15 @@ class Ensemble:
         instances of one scheme)."""
         return self.tau_of(0)
 
+    def tiling(self) -> dict:
+        """The tiling in effect: sites per lane, instance tiles per window, steps per launch."""
+        b, m, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        call("kslb_ensemble_get_tiling", self._h, ctypes.byref(b), ctypes.byref(m), ctypes.byref(c))
+        return {"sites_per_lane": b.value, "max_segments": m.value, "steps_per_chunk": c.value}
+
     def set_tiling(self, sites_per_lane: int = 0, max_segments: int = 0, steps_per_chunk: int = 0) -> "Ensemble":
-        """Sites per lane (4/8), instance tiles per workgroup window, steps per launch (0 = keep)."""
+        """Sites per lane (4/8; 12 with FP64 and 16 with the rho-only storage throughout),
+        instance tiles per workgroup window, steps per launch (0 = keep)."""
         call("kslb_ensemble_set_tiling", self._h, sites_per_lane, max_segments, steps_per_chunk)
         self.chunk = steps_per_chunk or getattr(self, "chunk", 64)
         return self

@@ -1320,12 +1320,7 @@ int ens_launch(const kslb_ensemble* E, const EnsPlan& plan, hipStream_t stream)
     return 0;
 }
 
-// Steady state: every active instance has at least `pairs` * 2 more full
-// chunks.  The chunk with the current parities and the one after it (all
-// parities flipped) are planned into the two descriptor slots and captured
-// once as a graph of their kernel launches, replayed `pairs` times.  The
-// graph holds kernels only (no memset or copy nodes); it is rebuilt whenever
-// either slot is rewritten.
+// Replays of one pair of plans within a call from which recording a graph pays.
 constexpr int64_t kGraphMinPairs = 4;
 
 // Retire the current graph: record an event behind its replays on the
@@ -1362,6 +1357,12 @@ void ens_reap_graphs(kslb_ensemble* E, bool wait)
     E->retired.resize(keep);
 }
 
+// Steady state: every active instance has at least `pairs` * 2 more full
+// chunks.  The chunk with the current parities and the one after it (all
+// parities flipped) are planned into the two descriptor slots and captured
+// as a graph of their kernel launches, replayed `pairs` times (or launched
+// directly, see below).  The graph holds kernels only (no memset or copy
+// nodes); it is rebuilt whenever either slot is rewritten.
 kslb_status ens_replay_pairs(kslb_ensemble* E, const std::vector<int>& adv, int64_t pairs)
 {
     EnsPlan pa, pb;

@@ -407,6 +407,29 @@ def test_ensemble_graph_replays_match_eager_launches():
             assert a.status(i)[0] == b.status(i)[0]
 
 
+def test_ensemble_graphs_replaced_without_waiting():
+    # every call advances a different subset of instances by five chunk pairs,
+    # so each call records a new graph and retires the previous one while its
+    # replays may still run; no host synchronisation between the calls
+    say("case ensemble graphs replaced")
+    sizes = [700, 2500, 5000, 9000, 64, 3001]
+    dX, dT = 0.2, 1e-4
+    rho0s = [ic(n, dX, 80 + i) for i, n in enumerate(sizes)]
+    a = Ensemble(sizes, 7, "fp64").set_physical(dX, dT, 1.1).set_tiling(8, 16, 16).set_graphs(True)
+    b = Ensemble(sizes, 7, "fp64").set_physical(dX, dT, 1.1).set_tiling(8, 16, 16).set_graphs(False)
+    for e in (a, b):
+        for i, r in enumerate(rho0s):
+            e.init_rho(i, r)
+    for k in range(9):
+        steps = [160] * len(sizes)
+        steps[k % len(sizes)] = 0
+        a.advance(steps)
+        b.advance(steps)
+    for i in range(len(sizes)):
+        assert np.array_equal(a.rho(i), b.rho(i)), i
+        assert a.status(i) == b.status(i)
+
+
 @pytest.mark.parametrize("q,prec", [(7, "fp64"), (5, "fp64"), (7, "split"), (5, "fp32")])
 def test_ensemble_packing_and_chunking_bitwise(q, prec):
     # packed windows (several instance tiles per workgroup), one tile per

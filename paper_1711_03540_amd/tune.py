@@ -51,7 +51,7 @@ def _time(fn, reps: int = 3) -> float:
 
 def tune_lattice(n: int, q: int = 7, precision: str = "fp64", steps: int = 2000, dX: float = math.pi / 16,
                  dT: float = 1e-4, cache: Optional[str] = DEFAULT_CACHE,
-                 tile_steps: Iterable[int] = (0, 16, 32, 40, 48, 64, 80),
+                 tile_steps: Iterable[int] = (0, 16, 32, 48, 64, 80, 96, 112),
                  span_steps: Iterable[int] = (0, 12, 18, 24)) -> Dict:
     """Best (kernel, steps_per_launch) for one periodic lattice of n sites
     (steps_per_launch is the exchange interval for SPAN; 0 = the library's

@@ -104,15 +104,21 @@ enum { KSLB_GUARD_REFUSE = 0, KSLB_GUARD_RAISE_TAU = 1, KSLB_GUARD_OFF = 2 };
  *   PLAIN    : one fused stream+collide step per launch (HBM ping-pong).
  *   RESIDENT : one workgroup holds the whole lattice in registers for all
  *              steps; needs n_sites = B * L with B in {4, 8}, L <= 512.
- *   TILED    : halo-widened tiles, several steps per launch in registers.
+ *   TILED    : halo-widened tiles, several steps per launch in registers:
+ *              windows of 256 lanes x B sites (B = 12 for FP64, 8 for FP32
+ *              and split, 16 for the rho-only state) each keep W - 2 max|c| s
+ *              sites after s steps (by default 80 for D1Q7 FP64, 112 for
+ *              D1Q5 FP64, 64 for FP32 and the rho-only D1Q7 state).
  *   SPAN     : thousands of steps per launch; single-wave workgroups each
- *              hold W = 64 max|c| sites in registers (max|c| per lane):
- *              their own W - 2 max|c| s sites and a halo of max|c| s sites
- *              per side, refreshed every s steps from the own sites the
- *              other workgroups publish in a library-owned exchange area (a
- *              halo may reach past the nearest neighbour).  s is the
+ *              hold W = 64 B sites in registers (B = 2 sites per lane for
+ *              the population states, max|c| for the rho-only state): their
+ *              own W - 2 max|c| s sites and a halo of max|c| s sites per
+ *              side, refreshed every s steps from the own sites the other
+ *              workgroups publish in a library-owned exchange area (a halo
+ *              may reach past the nearest neighbour).  s is the
  *              steps_per_launch of kslb_set_kernel; by default the largest
- *              with 3 W >= 8 max|c| s (24 for both schemes).  Every owner
+ *              with 3 W >= 8 max|c| s whose owners fit (16 for D1Q7 and 24
+ *              for D1Q5 population states, 24 for the rho-only state).  Every owner
  *              waits on its neighbours, so all must be resident at once: a
  *              plan uses at least 2 and at most half of the owners the
  *              device keeps resident (its occupancy for the kernel times

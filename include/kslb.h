@@ -243,6 +243,16 @@ kslb_status kslb_init_rho(kslb_lattice* lat, const double* rho, int rho_on_devic
 /* Enqueue n_steps >= 0 steps of Eq. (2) on the stream (asynchronous).      */
 kslb_status kslb_advance(kslb_lattice* lat, int64_t n_steps);
 
+/* One whole solve, enqueued on the stream: the result of kslb_init_rho(rho0,
+ * on device), kslb_advance(n_steps) and kslb_read_rho(rho_out, on device),
+ * bitwise, state and step count included.  rho0 and rho_out: n_sites
+ * doubles of device memory owned by the caller.  On the TILED kernel with
+ * both pointers 16-byte aligned the initialisation is fused into the first
+ * launch (the equilibrium of Eq. (feq) formed from rho0 on load) and the
+ * readout into the last (the density of section 2, sum_i f_i); otherwise
+ * the three calls run as they are.                                         */
+kslb_status kslb_solve(kslb_lattice* lat, const double* rho0, int64_t n_steps, double* rho_out);
+
 /* As kslb_advance, for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
  * it allocates nothing, host or device.  The one kernel class that needs

@@ -56,6 +56,7 @@ SIGNATURES = {
     "kslb_set_boundary": (_st, [_vp, _i, _d, _d]),
     "kslb_init_rho": (_st, [_vp, _vp, _i]),
     "kslb_advance": (_st, [_vp, _i64]),
+    "kslb_solve": (_st, [_vp, _vp, _i64, _vp]),
     "kslb_advance_noalloc": (_st, [_vp, _i64]),
     "kslb_read_rho": (_st, [_vp, _vp, _i]),
     "kslb_read_f": (_st, [_vp, _vp, _i, _i]),

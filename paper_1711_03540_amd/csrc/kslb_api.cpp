@@ -770,6 +770,41 @@ extern "C" {
 
 kslb_status kslb_advance(kslb_lattice* L, int64_t n_steps) { return advance_impl(L, n_steps, false); }
 
+kslb_status kslb_solve(kslb_lattice* L, const double* rho0, int64_t n_steps, double* rho_out)
+{
+    if (auto s = check_lat(L)) return s;
+    if (!rho0 || !rho_out) return fail(KSLB_EINVAL, "rho0 and rho_out must not be NULL");
+    if (n_steps < 0) return fail(KSLB_EINVAL, "n_steps must be >= 0");
+    if (!L->ph.set) return fail(KSLB_ESTATE, "set the coefficients before solve");
+    DeviceGuard g(L->device);
+    const Limits lim = device_limits(L->q, L->prec, L->fixed);
+    const KernelChoice kc = plan_kernel(L->n, L->q, L->prec, L->fixed, L->kernel, L->tile_steps, lim);
+    const bool aligned = reinterpret_cast<uintptr_t>(rho0) % 16 == 0 && reinterpret_cast<uintptr_t>(rho_out) % 16 == 0;
+    if (kc.kernel != KSLB_KERNEL_TILED || L->fixed || n_steps == 0 || !aligned) {
+        if (auto st = kslb_init_rho(L, rho0, 1)) return st;
+        if (auto st = advance_impl(L, n_steps, false)) return st;
+        return kslb_read_rho(L, rho_out, 1);
+    }
+    // tiled: the first launch forms the initial state from rho0 on load, the
+    // last also writes the density; the state copies end as after the three
+    // separate calls
+    L->cur = 0;
+    L->have_state = true;
+    L->step = 0;
+    if (auto st = span_clear_error(L)) return st;
+    for (int64_t done = 0; done < n_steps;) {
+        const int s = (int)std::min<int64_t>(kc.steps, n_steps - done);
+        const bool first = done == 0, last = done + s == n_steps;
+        int e = launch_tile(L->q, L->prec, tile_sites_per_lane(L->prec), L->state(), L->other(), L->n, s, L->ph.cf,
+                            L->stream, first ? rho0 : nullptr, last ? rho_out : nullptr);
+        if (e) return hip_fail(e, "tiled kernel");
+        L->cur ^= 1;
+        done += s;
+    }
+    L->step = n_steps;
+    return KSLB_OK;
+}
+
 kslb_status kslb_advance_noalloc(kslb_lattice* L, int64_t n_steps) { return advance_impl(L, n_steps, true); }
 
 kslb_status kslb_read_rho(kslb_lattice* L, double* out, int out_on_device)

@@ -57,8 +57,10 @@ int launch_plain(int q, int prec, const void* src, void* dst, int64_t n, const C
                  void* stream);
 int launch_ring(int q, int prec, int B, const void* src, void* dst, int64_t n, int64_t steps,
                 const Coef& cf, void* stream);
+// rho0 / rho_out (16-byte aligned, may be null): start from feq(rho0)
+// instead of src, and write the density of every site as well as dst.
 int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, int s,
-                const Coef& cf, void* stream);
+                const Coef& cf, void* stream, const double* rho0 = nullptr, double* rho_out = nullptr);
 // One small lattice over nwg single-wave workgroups exchanging edges every s
 // steps through `slots` edge slots per launch (slots * nwg copies of ecopy
 // bytes from ebase, each holding one owner's own sites in state format; see

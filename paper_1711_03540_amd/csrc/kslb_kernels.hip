@@ -894,12 +894,19 @@ __global__ __launch_bounds__(kRingLD) void k_ring(const char* __restrict__ src, 
 // of the segment are exact and are written back (slots near a segment's
 // ends go stale by H per step and are never stored).  Every lane of the
 // workgroup calls this (it holds the barriers).
+// rho0 (optional): the window starts from feq(rho0), formed on load exactly
+// as the init kernel stores it, instead of from src.  rho_out (optional): the
+// density of every stored site is written too, as the readout computes it.
+// Both 16-byte aligned.
 template <int Q, int P, int B>
 __device__ __forceinline__ void window_lane(const char* __restrict__ src, char* __restrict__ dst, int64_t n,
                                             int64_t p, int64_t j0, int64_t kl0, int64_t k_lo, int64_t valid,
-                                            int s, double* xch, const Coef& cf)
+                                            int s, double* xch, const Coef& cf,
+                                            const double* __restrict__ rho0 = nullptr,
+                                            double* __restrict__ rho_out = nullptr)
 {
     using E = Engine<Q, P, B, kTileLD>;
+    using PL = typename E::PL;
     constexpr int L = kTileLD;
     const int lane = threadIdx.x;
     typename E::Site x[B];
@@ -907,7 +914,18 @@ __device__ __forceinline__ void window_lane(const char* __restrict__ src, char* 
     // and their pitch is a multiple of 64 sites)
     const bool inside = j0 >= 0 && j0 + B <= n;
     const bool even = (j0 & 1) == 0;
-    if (kVecIO<P> && inside && even) {
+    if (rho0) {
+        if (inside && even) {
+            const d2v* r = reinterpret_cast<const d2v*>(rho0 + j0);
+            unroll<B / 2>([&](auto K) {
+                const d2v v = r[K];
+                x[2 * K] = PL::equilibrium(v.x, cf);
+                x[2 * K + 1] = PL::equilibrium(v.y, cf);
+            });
+        } else {
+            unroll<B>([&](auto Bi) { x[Bi] = PL::equilibrium(rho0[wrap_site(j0 + Bi, n)], cf); });
+        }
+    } else if (kVecIO<P> && inside && even) {
         E::PL::template load_vec<B>(src, p, j0, x);
     } else if (inside) {
         unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, p, j0 + Bi); });
@@ -926,19 +944,39 @@ __device__ __forceinline__ void window_lane(const char* __restrict__ src, char* 
             if (k >= k_lo && k < k_lo + valid && j < n) E::PL::store(dst, p, j, x[Bi]);
         });
     }
+    if (rho_out) {
+        if (kl0 >= k_lo && kl0 + B <= k_lo + valid && inside && even) {
+            d2v* r = reinterpret_cast<d2v*>(rho_out + j0);
+            unroll<B / 2>([&](auto K) {
+                d2v v;
+                v.x = PL::density(x[2 * K]);
+                v.y = PL::density(x[2 * K + 1]);
+                r[K] = v;
+            });
+        } else {
+            unroll<B>([&](auto Bi) {
+                const int64_t k = kl0 + Bi;
+                const int64_t j = j0 + Bi;
+                if (k >= k_lo && k < k_lo + valid && j < n) rho_out[j] = PL::density(x[Bi]);
+            });
+        }
+    }
 }
 
 // Large periodic lattice: tile t writes sites [t T, t T + T) from a window of
 // B * 256 sites starting H s sites earlier.
+// rho0 / rho_out (may be null): the first and the last launch of a solve
+// start from feq(rho0) and also write the density (see window_lane).
 template <int Q, int P, int B>
 __global__ __launch_bounds__(kTileLD) void k_tile(const char* __restrict__ src, char* __restrict__ dst,
-                                                  int64_t n, int64_t p, int s, int64_t T, Coef cf)
+                                                  int64_t n, int64_t p, int s, int64_t T, Coef cf,
+                                                  const double* __restrict__ rho0, double* __restrict__ rho_out)
 {
     extern __shared__ double xch[];
     constexpr int H = halo_of(Q);
     const int64_t ws = xcd_block(blockIdx.x, gridDim.x) * T - (int64_t)H * s;
     const int64_t kl0 = (int64_t)threadIdx.x * B;
-    window_lane<Q, P, B>(src, dst, n, p, ws + kl0, kl0, (int64_t)H * s, T, s, xch, cf);
+    window_lane<Q, P, B>(src, dst, n, p, ws + kl0, kl0, (int64_t)H * s, T, s, xch, cf, rho0, rho_out);
 }
 
 // Waves per SIMD the ensemble kernel is compiled for: three (the LDS
@@ -1729,7 +1767,8 @@ int launch_ring(int q, int prec, int B, const void* src, void* dst, int64_t n, i
 }
 
 template <int Q, int P, int B>
-static int tile_one(const void* src, void* dst, int64_t n, int s, const Coef& cf, void* stream)
+static int tile_one(const void* src, void* dst, int64_t n, int s, const Coef& cf, void* stream,
+                    const double* rho0, double* rho_out)
 {
     const int64_t W = (int64_t)kTileLD * B;
     const int64_t T = W - 2 * (int64_t)halo_of(Q) * s;
@@ -1739,22 +1778,24 @@ static int tile_one(const void* src, void* dst, int64_t n, int s, const Coef& cf
     int e = prep_lds(k_tile<Q, P, B>, lds);
     if (e) return e;
     k_tile<Q, P, B><<<(unsigned)tiles, kTileLD, lds, (hipStream_t)stream>>>((const char*)src, (char*)dst, n,
-                                                                           state_pitch(n), s, T, cf);
+                                                                           state_pitch(n), s, T, cf, rho0, rho_out);
     return (int)hipGetLastError();
 }
 
 int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, int s, const Coef& cf,
-                void* stream)
+                void* stream, const double* rho0, double* rho_out)
 {
-    if (B == 4) { KSLB_DISPATCH_QP(q, prec, return (tile_one<Q_, P_, 4>(src, dst, n, s, cf, stream))); }
-    if (B == 8) { KSLB_DISPATCH_QP(q, prec, return (tile_one<Q_, P_, 8>(src, dst, n, s, cf, stream))); }
+#define KSLB_TILE(B_) (tile_one<Q_, P_, B_>(src, dst, n, s, cf, stream, rho0, rho_out))
+    if (B == 4) { KSLB_DISPATCH_QP(q, prec, return KSLB_TILE(4)); }
+    if (B == 8) { KSLB_DISPATCH_QP(q, prec, return KSLB_TILE(8)); }
+#undef KSLB_TILE
     if (B == 12 && prec == kFP64) {  // 12 sites per lane: FP64 populations only
-        if (q == 5) return tile_one<5, kFP64, 12>(src, dst, n, s, cf, stream);
-        return tile_one<7, kFP64, 12>(src, dst, n, s, cf, stream);
+        if (q == 5) return tile_one<5, kFP64, 12>(src, dst, n, s, cf, stream, rho0, rho_out);
+        return tile_one<7, kFP64, 12>(src, dst, n, s, cf, stream, rho0, rho_out);
     }
     if (B == 16 && prec == kRHO) {   // 16 sites per lane: rho-only state only
-        if (q == 5) return tile_one<5, kRHO, 16>(src, dst, n, s, cf, stream);
-        return tile_one<7, kRHO, 16>(src, dst, n, s, cf, stream);
+        if (q == 5) return tile_one<5, kRHO, 16>(src, dst, n, s, cf, stream, rho0, rho_out);
+        return tile_one<7, kRHO, 16>(src, dst, n, s, cf, stream, rho0, rho_out);
     }
     return (int)hipErrorInvalidValue;
 }

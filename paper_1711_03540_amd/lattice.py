@@ -146,6 +146,22 @@ class Lattice:
         call("kslb_advance", self._h, int(steps))
         return self
 
+    def solve(self, rho0, steps: int, out=None):
+        """init_rho(rho0) + advance(steps) + read_rho(out) as one enqueued call
+        (kslb_solve: fused into the first and last launches of the tiled
+        kernel); rho0 a float64 device tensor of n sites.  Returns out."""
+        import torch
+        if not (isinstance(rho0, torch.Tensor) and rho0.is_cuda):
+            raise TypeError("solve takes the initial density as a device tensor")
+        r = rho0.to(torch.float64).contiguous()
+        assert r.numel() == self.n
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        assert out.numel() == self.n and out.dtype == torch.float64 and out.is_contiguous()
+        call("kslb_solve", self._h, ctypes.c_void_p(r.data_ptr()), int(steps), ctypes.c_void_p(out.data_ptr()))
+        self._keep = r
+        return out
+
     def advance_guarded(self, steps: int, chunk: int = 1000, tau_step: float = 0.02, max_raises: int = 50,
                         bound: float = None) -> "Lattice":
         """Advance `steps` steps in chunks, saving the state before each chunk.  A

@@ -407,6 +407,46 @@ def test_ensemble_graph_replays_match_eager_launches():
             assert a.status(i)[0] == b.status(i)[0]
 
 
+@pytest.mark.parametrize("q,n,prec,kernel,steps_per_launch,steps", [
+    (7, 12345, "fp64", "tiled", 0, 1), (7, 12345, "fp64", "tiled", 0, 80), (7, 12345, "fp64", "tiled", 0, 81),
+    (7, 12345, "fp64", "tiled", 0, 250), (7, 70001, "fp64", "tiled", 7, 30), (5, 7001, "fp64", "tiled", 0, 150),
+    (7, 9000, "fp32", "tiled", 0, 100), (5, 9000, "split", "tiled", 0, 100), (7, 9000, "rho", "tiled", 0, 100),
+    (7, 4096, "fp64", "auto", 0, 100), (7, 5000, "fp64", "plain", 0, 20), (7, 12345, "fp64", "tiled", 0, 0)])
+def test_solve_matches_separate_calls(q, n, prec, kernel, steps_per_launch, steps):
+    # kslb_solve (initialisation and readout fused into the first and last
+    # tiled launches) against init_rho + advance + read_rho: density, stored
+    # populations and step count bitwise (the state rows' padding sites past
+    # n hold whatever the buffer held, so states are compared site by site)
+    import torch
+    say("case solve q=%d n=%d %s %s s=%d steps=%d" % (q, n, prec, kernel, steps_per_launch, steps))
+    tau = 1.0 if prec == "rho" else 1.1
+    rho0 = torch.tensor(ic(n, 0.2, 11), device="cuda")
+    a = make(q, n, prec, kernel, tau=tau, steps_per_launch=steps_per_launch)
+    b = make(q, n, prec, kernel, tau=tau, steps_per_launch=steps_per_launch)
+    got = a.solve(rho0, steps)
+    want = b.init_rho(rho0).advance(steps).read_rho()
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    state = b.f()
+    assert np.array_equal(a.f(), state)
+    assert a.step == b.step == steps
+    # the lattice continues from the solved state like any other
+    a.advance(7)
+    b.advance(7)
+    assert np.array_equal(a.rho(), b.rho())
+    # unaligned device pointers take the unfused path, with the same result
+    big = torch.empty(n + 1, dtype=torch.float64, device="cuda")
+    big[1:] = rho0
+    out = torch.empty(n + 1, dtype=torch.float64, device="cuda")
+    c = make(q, n, prec, kernel, tau=tau, steps_per_launch=steps_per_launch)
+    from paper_1711_03540_amd._lib import call
+    import ctypes
+    call("kslb_solve", c._h, ctypes.c_void_p(big[1:].data_ptr()), steps, ctypes.c_void_p(out[1:].data_ptr()))
+    torch.cuda.synchronize()
+    assert torch.equal(out[1:], want)
+    assert np.array_equal(c.f(), state)
+
+
 def test_ensemble_graphs_replaced_without_waiting():
     # every call advances a different subset of instances by five chunk pairs,
     # so each call records a new graph and retires the previous one while its

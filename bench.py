@@ -93,6 +93,15 @@ def bytes_per_site_update(q: int, precision: str) -> int:
     return {"fp64": 2 * q * 8, "fp32": 2 * q * 4, "split": 2 * (8 + q * 4), "rho": 2 * 8}[precision]
 
 
+# Algorithmic HBM bytes per site of one launch of a tiled solve, averaged over
+# its `launches` launches: each reads and writes the state once, except that
+# the first reads the initial density (8 B) instead of the state and the last
+# also writes the density (8 B).
+def solve_bytes_per_site_launch(q: int, precision: str, launches: int) -> float:
+    full = bytes_per_site_update(q, precision)
+    return (launches * full - (full // 2 - 8) + 8) / launches
+
+
 WORKLOADS = {
     "all": (None, None),
     "d1q7_n16m": ("CFG_LARGE_Q7", "tiled"),
@@ -389,7 +398,8 @@ def run_lattice(w, precision, kernel, solves, warmup, tile_steps=0, autotune=Fal
     roof["traffic"] = measured_traffic(kname, w.name, precision,
                                        {k: shape[k] for k in ("steps_per_launch", "exchange_steps", "workgroups")})
     roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
-    roof["traffic_algorithmic"] = bytes_per_site_update(w.q, precision) * w.n
+    roof["traffic_algorithmic"] = (solve_bytes_per_site_launch(w.q, precision, launches) if kernel == "tiled"
+                                   else bytes_per_site_update(w.q, precision)) * w.n
     roof["kernel"] = kname
     roof["launch_shape"] = shape
     roof["kernel_ms_avg"] = kernel_ms

@@ -1793,9 +1793,9 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
         if (q == 5) return tile_one<5, kFP64, 12>(src, dst, n, s, cf, stream, rho0, rho_out);
         return tile_one<7, kFP64, 12>(src, dst, n, s, cf, stream, rho0, rho_out);
     }
-    if (B == 16 && prec == kRHO) {   // 16 sites per lane: rho-only state only
-        if (q == 5) return tile_one<5, kRHO, 16>(src, dst, n, s, cf, stream, rho0, rho_out);
-        return tile_one<7, kRHO, 16>(src, dst, n, s, cf, stream, rho0, rho_out);
+    if (B == 32 && prec == kRHO) {   // 32 sites per lane: rho-only state only
+        if (q == 5) return tile_one<5, kRHO, 32>(src, dst, n, s, cf, stream, rho0, rho_out);
+        return tile_one<7, kRHO, 32>(src, dst, n, s, cf, stream, rho0, rho_out);
     }
     return (int)hipErrorInvalidValue;
 }

@@ -746,6 +746,40 @@ struct Engine {
         step_hv(x, y, hv, cf);
     }
 
+    // One step x -> y that computes and publishes the edge sites first (out:
+    // this lane's column of the other exchange buffer), at raised wave
+    // priority, then the interior: the values the neighbours wait for at the
+    // next barrier leave as early as possible.  (Without the priority change,
+    // which also bounds the compiler's reordering, the same order measured
+    // slower for D1Q7 FP64; with it D1Q7 FP64 is unchanged, D1Q5 FP64 and
+    // FP32 run 3-4 % faster.)
+    __device__ static __forceinline__ void step_ep(const Site (&x)[B], Site (&y)[B], const XV* left,
+                                                   const XV* right, XV* out, const Coef& cf)
+    {
+        XV hv[NX];
+        if constexpr (kR) {
+            unroll<H>([&](auto T) {
+                hv[T] = left[T * LD];
+                hv[H + T] = right[(H + T) * LD];
+            });
+        } else {
+            unroll<Q - 1>([&](auto I1) {
+                constexpr int i = I1 + 1;
+                constexpr int c = vel(i);
+                constexpr int k0 = koff(i);
+                unroll<iabs(c)>([&](auto T) {
+                    constexpr int t = T;
+                    hv[k0 + t] = (c > 0 ? left : right)[(k0 + t) * LD];
+                });
+            });
+        }
+        __builtin_amdgcn_s_setprio(1);
+        step_sites<false>(x, y, hv, cf);
+        publish(y, out, cf);
+        __builtin_amdgcn_s_setprio(0);
+        step_sites<true>(x, y, hv, cf);
+    }
+
     // Single-wave windows: the neighbour values move between lanes with DPP
     // wave rotations (lane l reads lane l-1 for c > 0, lane l+1 for c < 0),
     // with no LDS round trip and no barrier.
@@ -826,6 +860,26 @@ struct Engine {
             }
         } else {
             XV* xb = reinterpret_cast<XV*>(xch);   // the exchange area, in exchanged values
+            if constexpr (std::is_same<Fix, NoFix>::value) {
+                // each step publishes its own edges into the buffer the next
+                // step reads: one barrier per step, buffers alternating
+                if (active) publish(x, xb + lane, cf);
+                __syncthreads();
+                for (; st + 1 < steps; st += 2) {
+                    if (active) step_ep(x, y, xb + left, xb + right, xb + SLOT + lane, cf);
+                    __syncthreads();
+                    if (active) step_ep(y, x, xb + SLOT + left, xb + SLOT + right, xb + lane, cf);
+                    __syncthreads();
+                }
+                if (st < steps) {
+                    if (active) {
+                        step(x, y, xb + left, xb + right, cf);
+                        unroll<B>([&](auto Bi) { x[Bi] = y[Bi]; });
+                    }
+                    __syncthreads();   // the next call writes slot 0 again
+                }
+                return;
+            }
             for (; st + 1 < steps; st += 2) {
                 if (active) publish(x, xb + lane, cf);
                 __syncthreads();

@@ -251,6 +251,11 @@ def test_large_config_sampled_sites():
     rho = lat.rho()
     assert not bad
     assert abs(m1 - m0) < 1e-12 * np.abs(rho0).sum()
+    # the benchmark's launch: one kslb_solve (init and readout fused into the
+    # first and last tiled launches) gives the same densities bit for bit
+    import torch
+    fused = lat.solve(torch.tensor(rho0, device="cuda"), w.steps).cpu().numpy()
+    assert np.array_equal(fused, rho)
     half = 3 * w.steps + 8
     rng = np.random.default_rng(0)
     sites = [0, 1, w.n - 1, w.n // 2] + list(rng.integers(0, w.n, 4))

@@ -105,11 +105,11 @@ enum { KSLB_GUARD_REFUSE = 0, KSLB_GUARD_RAISE_TAU = 1, KSLB_GUARD_OFF = 2 };
  *   RESIDENT : one workgroup holds the whole lattice in registers for all
  *              steps; needs n_sites = B * L with B in {4, 8}, L <= 512.
  *   TILED    : halo-widened tiles, several steps per launch in registers:
- *              windows of 256 lanes x B sites (B = 12 for FP64, 8 for FP32
- *              and split, 32 for the rho-only state) each keep W - 2 max|c| s
- *              sites after s steps (by default 80 for D1Q7 FP64, 112 for
- *              D1Q5 FP64, 64 for FP32 and the rho-only D1Q7 state, 128 for
- *              the rho-only D1Q5 state).
+ *              windows of 256 lanes x B sites (B = 12 for FP64, 10 for FP32,
+ *              8 for split, 32 for the rho-only state) each keep
+ *              W - 2 max|c| s sites after s steps (by default 80 for D1Q7
+ *              FP64, 112 for D1Q5 FP64, 64 for FP32 and the rho-only D1Q7
+ *              state, 128 for the rho-only D1Q5 state).
  *   SPAN     : thousands of steps per launch; single-wave workgroups each
  *              hold W = 64 B sites in registers (B = 2 sites per lane for
  *              the population states, max|c| for the rho-only state): their

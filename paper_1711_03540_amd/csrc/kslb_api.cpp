@@ -193,11 +193,13 @@ int ring_sites_per_lane(int64_t n, int q, int lds_bytes)
 // waves per SIMD: a 3072-site window recomputes less halo per stored site
 // than 2048 sites at three waves; on N = 2^24 D1Q7 1060 against 1026 GLUPS,
 // D1Q5 1447 against 1411), 32 for the rho-only state (154 registers, three
-// waves: 1931 against 1844 GLUPS at 16, D1Q5 2371 against 2309), 8 for FP32
-// and split (at 12 the FP32 record needs 200 registers: 788 against 840).
+// waves: 1931 against 1844 GLUPS at 16, D1Q5 2371 against 2309), 10 for FP32
+// (134 registers, three waves: on two devices 888 and 913 GLUPS against 866
+// and 875 at 8 sites, s = 64) and 8 for split.
 int tile_sites_per_lane(int prec)
 {
     if (prec == kFP64) return 12;
+    if (prec == kFP32) return 10;
     return prec == kRHO ? 32 : 8;
 }
 
@@ -266,13 +268,15 @@ constexpr int kSpanAutoMinSteps = 12;
 // N = 2^24 put the optimum at 80 for D1Q7 FP64 (1063 GLUPS; 1060 at 64,
 // 1063 at 96), 112 for D1Q5 FP64 (1447; 1396 at 64), 64 for the rho-only
 // D1Q7 state (1931; 1925 at 96, 1913 at 128), 128 for rho-only D1Q5 (2371;
-// 2325 at 64), 64 for D1Q7 FP32 (840 against 816 at 80) and 40 for D1Q7
-// split; other combinations keep 2 H s <= W / 8.
+// 2325 at 64), 64 for FP32 (D1Q7 888-913, within 3 % of 48 and 80, whose
+// order changes from device to device; D1Q5 1275, 1214 at 96) and 40 for
+// D1Q7 split; other combinations keep 2 H s <= W / 8.
 int default_tile_steps(int q, int prec)
 {
     if (prec == kFP64) return q == 7 ? 80 : 112;
     if (prec == kRHO) return q == 7 ? 64 : 128;
-    if (q == 7) return prec == kFP32 ? 64 : 40;
+    if (prec == kFP32) return 64;
+    if (q == 7) return 40;
     const int W = tile_lanes() * tile_sites_per_lane(prec);
     int s = W / (16 * halo(q));
     s -= s % 8;

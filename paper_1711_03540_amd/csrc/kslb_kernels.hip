@@ -1650,7 +1650,7 @@ __global__ __launch_bounds__(256) void k_diag1(const char* __restrict__ st, int6
     }
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (unsigned w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
         __syncthreads();
     }
@@ -1843,6 +1843,10 @@ int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, i
     if (B == 4) { KSLB_DISPATCH_QP(q, prec, return KSLB_TILE(4)); }
     if (B == 8) { KSLB_DISPATCH_QP(q, prec, return KSLB_TILE(8)); }
 #undef KSLB_TILE
+    if (B == 10 && prec == kFP32) {  // 10 sites per lane: FP32 populations only
+        if (q == 5) return tile_one<5, kFP32, 10>(src, dst, n, s, cf, stream, rho0, rho_out);
+        return tile_one<7, kFP32, 10>(src, dst, n, s, cf, stream, rho0, rho_out);
+    }
     if (B == 12 && prec == kFP64) {  // 12 sites per lane: FP64 populations only
         if (q == 5) return tile_one<5, kFP64, 12>(src, dst, n, s, cf, stream, rho0, rho_out);
         return tile_one<7, kFP64, 12>(src, dst, n, s, cf, stream, rho0, rho_out);

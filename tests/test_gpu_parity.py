@@ -923,7 +923,7 @@ def test_resolved_kernel_and_launch_shape():
     assert k["kernel"] == "span" and k["steps_per_launch"] % k["exchange_steps"] == 0
     assert k["exchange_steps"] >= 1 and k["workgroups"] >= 2 and k["lanes"] == 64
     n = 100_000
-    for prec, sites, s_default in (("fp64", 12, 80), ("rho", 32, 64), ("fp32", 8, 64)):
+    for prec, sites, s_default in (("fp64", 12, 80), ("rho", 32, 64), ("fp32", 10, 64)):
         lat = Lattice(n, 7, prec).set_physical(0.3, 2e-4, 1.0)
         k = lat.kernel()
         s = k["steps_per_launch"]

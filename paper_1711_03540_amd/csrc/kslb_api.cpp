@@ -189,19 +189,6 @@ int ring_sites_per_lane(int64_t n, int q, int lds_bytes)
     return 0;
 }
 
-// Sites per lane of the tiled kernel: 12 FP64 (228 registers for D1Q7, two
-// waves per SIMD: a 3072-site window recomputes less halo per stored site
-// than 2048 sites at three waves; on N = 2^24 D1Q7 1060 against 1026 GLUPS,
-// D1Q5 1447 against 1411), 32 for the rho-only state (154 registers, three
-// waves: 1931 against 1844 GLUPS at 16, D1Q5 2371 against 2309), 10 for FP32
-// (134 registers, three waves: on two devices 888 and 913 GLUPS against 866
-// and 875 at 8 sites, s = 64) and 8 for split.
-int tile_sites_per_lane(int prec)
-{
-    if (prec == kFP64) return 12;
-    if (prec == kFP32) return 10;
-    return prec == kRHO ? 32 : 8;
-}
 
 // Device limits a plan assumes: SPAN owners that may run at once, and the
 // dynamic LDS one workgroup may use.
@@ -758,7 +745,7 @@ kslb_status advance_impl(kslb_lattice* L, int64_t n_steps, bool noalloc)
         const int s_max = kc.steps;
         for (int64_t done = 0; done < n_steps;) {
             const int s = (int)std::min<int64_t>(s_max, n_steps - done);
-            e = launch_tile(L->q, L->prec, tile_sites_per_lane(L->prec), L->state(), L->other(), L->n, s, L->ph.cf,
+            e = launch_tile(L->q, L->prec, L->state(), L->other(), L->n, s, L->ph.cf,
                             L->stream);
             if (e) return hip_fail(e, "tiled kernel");
             L->cur ^= 1;
@@ -800,7 +787,7 @@ kslb_status kslb_solve(kslb_lattice* L, const double* rho0, int64_t n_steps, dou
     for (int64_t done = 0; done < n_steps;) {
         const int s = (int)std::min<int64_t>(kc.steps, n_steps - done);
         const bool first = done == 0, last = done + s == n_steps;
-        int e = launch_tile(L->q, L->prec, tile_sites_per_lane(L->prec), L->state(), L->other(), L->n, s, L->ph.cf,
+        int e = launch_tile(L->q, L->prec, L->state(), L->other(), L->n, s, L->ph.cf,
                             L->stream, first ? rho0 : nullptr, last ? rho_out : nullptr);
         if (e) return hip_fail(e, "tiled kernel");
         L->cur ^= 1;

@@ -59,8 +59,11 @@ int launch_ring(int q, int prec, int B, const void* src, void* dst, int64_t n, i
                 const Coef& cf, void* stream);
 // rho0 / rho_out (16-byte aligned, may be null): start from feq(rho0)
 // instead of src, and write the density of every site as well as dst.
-int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, int s,
+int launch_tile(int q, int prec, const void* src, void* dst, int64_t n, int s,
                 const Coef& cf, void* stream, const double* rho0 = nullptr, double* rho_out = nullptr);
+// Sites per lane of the tiled kernel for a storage mode (its window holds
+// tile_lanes() * that many sites).
+int tile_sites_per_lane(int prec);
 // One small lattice over nwg single-wave workgroups exchanging edges every s
 // steps through `slots` edge slots per launch (slots * nwg copies of ecopy
 // bytes from ebase, each holding one owner's own sites in state format; see

@@ -1836,25 +1836,24 @@ static int tile_one(const void* src, void* dst, int64_t n, int s, const Coef& cf
     return (int)hipGetLastError();
 }
 
-int launch_tile(int q, int prec, int B, const void* src, void* dst, int64_t n, int s, const Coef& cf,
-                void* stream, const double* rho0, double* rho_out)
+// Sites per lane of the tiled kernel, one width per storage, from sweeps on
+// N = 2^24: 12 for FP64 (228 registers for D1Q7, two waves per SIMD: a
+// 3072-site window recomputes less halo per stored site than 2048 sites at
+// three waves; D1Q7 1060 against 1026 GLUPS, D1Q5 1447 against 1411), 10 for
+// FP32 (134 registers, three waves: on two devices 888 and 913 GLUPS against
+// 866 and 875 at 8 sites), 32 for the rho-only state (154 registers, three
+// waves: 1931 against 1844 GLUPS at 16, D1Q5 2371 against 2309), 8 for split.
+__host__ __device__ constexpr int tile_b_of(int p)
 {
-#define KSLB_TILE(B_) (tile_one<Q_, P_, B_>(src, dst, n, s, cf, stream, rho0, rho_out))
-    if (B == 4) { KSLB_DISPATCH_QP(q, prec, return KSLB_TILE(4)); }
-    if (B == 8) { KSLB_DISPATCH_QP(q, prec, return KSLB_TILE(8)); }
-#undef KSLB_TILE
-    if (B == 10 && prec == kFP32) {  // 10 sites per lane: FP32 populations only
-        if (q == 5) return tile_one<5, kFP32, 10>(src, dst, n, s, cf, stream, rho0, rho_out);
-        return tile_one<7, kFP32, 10>(src, dst, n, s, cf, stream, rho0, rho_out);
-    }
-    if (B == 12 && prec == kFP64) {  // 12 sites per lane: FP64 populations only
-        if (q == 5) return tile_one<5, kFP64, 12>(src, dst, n, s, cf, stream, rho0, rho_out);
-        return tile_one<7, kFP64, 12>(src, dst, n, s, cf, stream, rho0, rho_out);
-    }
-    if (B == 32 && prec == kRHO) {   // 32 sites per lane: rho-only state only
-        if (q == 5) return tile_one<5, kRHO, 32>(src, dst, n, s, cf, stream, rho0, rho_out);
-        return tile_one<7, kRHO, 32>(src, dst, n, s, cf, stream, rho0, rho_out);
-    }
+    return p == kFP64 ? 12 : (p == kFP32 ? 10 : (p == kRHO ? 32 : 8));
+}
+
+int tile_sites_per_lane(int prec) { return tile_b_of(prec); }
+
+int launch_tile(int q, int prec, const void* src, void* dst, int64_t n, int s, const Coef& cf, void* stream,
+                const double* rho0, double* rho_out)
+{
+    KSLB_DISPATCH_QP(q, prec, return (tile_one<Q_, P_, tile_b_of(P_)>(src, dst, n, s, cf, stream, rho0, rho_out)));
     return (int)hipErrorInvalidValue;
 }
 

@@ -1126,13 +1126,17 @@ def bench_all(args):
         configs["%s_%s" % (w4.name, prec)] = r
     w0, w1 = inputs.CFG_SMALL_Q5, inputs.CFG_RESIDENT_Q7
     configs[w0.name] = run_lattice(w0, "fp64", "span", 100, 5, plain=not args.no_plain, cpu=cpu)
-    configs[w1.name] = run_lattice(w1, "fp64", "span", 30, 2, plain=not args.no_plain, cpu=cpu)
+    configs[w1.name] = run_lattice(w1, "fp64", "span", 100, 2, plain=not args.no_plain, cpu=cpu)
     # the ensemble's tiling (sites per lane, steps per chunk, instance tiles
     # per workgroup window) picked by the autotuner for each storage
     ens64 = run_ensemble("fp64", args.instances, args.lb_steps, autotune=True, cpu=cpu)
     ens32 = run_ensemble("fp32", args.instances, args.lb_steps, autotune=True, cpu=False)
+    # the split storage (rho in double, the non-equilibrium part in single) at
+    # the library's default tiling
+    enssp = run_ensemble("split", args.instances, args.lb_steps, cpu=False)
     configs[ens64["workload"]] = ens64
     configs[ens64["workload"] + "_fp32"] = ens32
+    configs[ens64["workload"] + "_split"] = enssp
     srv = run_serve(2000.0, args.requests, args.budget_gib, serve_fp32=args.serve_fp32, cpu=cpu)
     configs[srv["workload"]] = srv
     rates = [float(r) for r in args.rates.split(",") if r]

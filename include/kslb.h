@@ -342,14 +342,15 @@ kslb_status kslb_ensemble_set_physical(kslb_ensemble* ens, int idx, double dX, d
                                        int dm_variant, int guard_policy, double rho_max);
 
 /* Tiling knobs (0 keeps the current value):
- *   sites_per_lane  4 or 8 (window of 256 lanes x that many sites; 12 when
- *                   every instance has FP64 storage, 16 when every instance
- *                   has the rho-only storage); EINVAL otherwise;
+ *   sites_per_lane  4 or 8 (window of 256 lanes x that many sites; 10 when
+ *                   every instance has FP32 storage, 12 when every instance
+ *                   has FP64 storage, 16 when every instance has the rho-only
+ *                   storage); EINVAL otherwise;
  *   max_segments    instance tiles one workgroup window may hold, 1..256
  *                   (1 = one tile per workgroup);
  *   steps_per_chunk steps per launch, with 2 max|c| steps < the window.
- * Defaults: 8 sites (12 when every instance has FP64 storage), 16
- * segments, 64 steps.                                                      */
+ * Defaults: 8 sites (12 when every instance has FP64 storage, 10 when every
+ * instance has FP32 storage), 16 segments, 64 steps.                       */
 kslb_status kslb_ensemble_set_tiling(kslb_ensemble* ens, int sites_per_lane, int max_segments,
                                      int steps_per_chunk);
 

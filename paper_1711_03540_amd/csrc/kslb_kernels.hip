@@ -1877,6 +1877,10 @@ int launch_ens(int q, int prec, int B, const WinHdr* hdr, const SegDesc* seg, in
         if (q == 5) return ens_one<5, kFP64, 12>(hdr, seg, nwin, cf, stream);
         return ens_one<7, kFP64, 12>(hdr, seg, nwin, cf, stream);
     }
+    if (B == 10 && prec == kFP32) {
+        if (q == 5) return ens_one<5, kFP32, 10>(hdr, seg, nwin, cf, stream);
+        return ens_one<7, kFP32, 10>(hdr, seg, nwin, cf, stream);
+    }
     if (B == 16 && prec == kRHO) {
         if (q == 5) return ens_one<5, kRHO, 16>(hdr, seg, nwin, cf, stream);
         return ens_one<7, kRHO, 16>(hdr, seg, nwin, cf, stream);

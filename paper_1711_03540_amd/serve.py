@@ -161,7 +161,7 @@ class _Pool:
         import torch
         self.q, self.precision = q, precision
         self.chunk = chunk
-        self.widths = (12, 8, 4) if precision == "fp64" else (8, 4)
+        self.widths = {"fp64": (12, 8, 4), "fp32": (10, 8, 4)}.get(precision, (8, 4))
         self.width = None
         self.stream = torch.cuda.Stream(device=device)          # default priority
         # descriptors start bound to one-site placeholders in the ensemble's own buffer

@@ -92,9 +92,10 @@ def tune_ensemble(sizes: Sequence[int], q: int = 7, precision: str = "fp64", ste
                   chunks: Iterable[int] = (16, 24, 32, 40, 48, 64),
                   segments: Iterable[int] = (1, 4, 16, 64)) -> Dict:
     """Best (sites per lane, steps per chunk, tiles per window) for a ragged ensemble.
-    sites_per_lane defaults to 12, 8 and 4 for FP64 storage, 8 and 4 otherwise."""
+    sites_per_lane defaults to 12, 8 and 4 for FP64 storage, 10, 8 and 4 for FP32, 8
+    and 4 otherwise."""
     if sites_per_lane is None:
-        sites_per_lane = (12, 8, 4) if precision == "fp64" else (8, 4)
+        sites_per_lane = {"fp64": (12, 8, 4), "fp32": (10, 8, 4)}.get(precision, (8, 4))
     sizes = np.asarray(sizes, dtype=np.int64)
     hist = np.histogram(np.log2(sizes), bins=8, range=(0, 24))[0]
     key = "ensemble/q%d/%s/count%d/%s" % (q, precision, sizes.size, ",".join(map(str, hist)))

@@ -489,8 +489,11 @@ def test_ensemble_packing_and_chunking_bitwise(q, prec):
     tilings = [(8, 16, 32), (8, 1, 32), (4, 16, 16), (8, 256, 7), (8, 3, 40)]
     if prec == "fp64":
         tilings += [(12, 16, 32), (12, 1, 41), (12, 5, 96)]
+    if prec == "fp32":
+        tilings += [(10, 16, 32), (10, 1, 41), (10, 5, 80)]
     default = Ensemble(sizes, q, prec).tiling()
-    assert default == {"sites_per_lane": 12 if prec == "fp64" else 8, "max_segments": 16, "steps_per_chunk": 64}
+    assert default == {"sites_per_lane": {"fp64": 12, "fp32": 10}.get(prec, 8), "max_segments": 16,
+                       "steps_per_chunk": 64}
     for B, segs, chunk in tilings:
         ens = Ensemble(sizes, q, prec).set_physical(dX, dT, 1.1).set_tiling(B, segs, chunk)
         assert ens.tiling() == {"sites_per_lane": B, "max_segments": segs, "steps_per_chunk": chunk}

@@ -247,11 +247,14 @@ kslb_status kslb_advance(kslb_lattice* lat, int64_t n_steps);
 /* One whole solve, enqueued on the stream: the result of kslb_init_rho(rho0,
  * on device), kslb_advance(n_steps) and kslb_read_rho(rho_out, on device),
  * bitwise, state and step count included.  rho0 and rho_out: n_sites
- * doubles of device memory owned by the caller.  On the TILED kernel with
- * both pointers 16-byte aligned the initialisation is fused into the first
- * launch (the equilibrium of Eq. (feq) formed from rho0 on load) and the
- * readout into the last (the density of section 2, sum_i f_i); otherwise
- * the three calls run as they are.                                         */
+ * doubles of device memory owned by the caller; they may be the same
+ * buffer.  On the TILED kernel with both pointers 16-byte aligned the
+ * initialisation is fused into the first launch (the equilibrium of Eq.
+ * (feq) formed from rho0 on load) and the readout into the last (the
+ * density of section 2, sum_i f_i), except where a single launch would read
+ * rho0 and write an overlapping rho_out: then the readout follows it.
+ * Otherwise the three calls run as they are.  On an error from the first
+ * launch the lattice holds no state (kslb_init_rho or kslb_write_f again). */
 kslb_status kslb_solve(kslb_lattice* lat, const double* rho0, int64_t n_steps, double* rho_out);
 
 /* As kslb_advance, for callers that cannot allocate device memory (code under

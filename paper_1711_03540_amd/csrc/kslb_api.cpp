@@ -779,22 +779,32 @@ kslb_status kslb_solve(kslb_lattice* L, const double* rho0, int64_t n_steps, dou
     }
     // tiled: the first launch forms the initial state from rho0 on load, the
     // last also writes the density; the state copies end as after the three
-    // separate calls
+    // separate calls.  One launch that both reads rho0 and writes an
+    // overlapping rho_out would race (a window stores its sites' densities
+    // while a neighbouring window may still load them as halo), so then the
+    // readout runs after it.
+    const uintptr_t in0 = reinterpret_cast<uintptr_t>(rho0), out0 = reinterpret_cast<uintptr_t>(rho_out);
+    const uintptr_t bytes = sizeof(double) * (uintptr_t)L->n;
+    const bool overlap = out0 < in0 + bytes && in0 < out0 + bytes;
+    const bool fuse_out = !(overlap && n_steps <= kc.steps);
     L->cur = 0;
-    L->have_state = true;
     L->step = 0;
     if (auto st = span_clear_error(L)) return st;
     for (int64_t done = 0; done < n_steps;) {
         const int s = (int)std::min<int64_t>(kc.steps, n_steps - done);
         const bool first = done == 0, last = done + s == n_steps;
         int e = launch_tile(L->q, L->prec, L->state(), L->other(), L->n, s, L->ph.cf,
-                            L->stream, first ? rho0 : nullptr, last ? rho_out : nullptr);
-        if (e) return hip_fail(e, "tiled kernel");
+                            L->stream, first ? rho0 : nullptr, last && fuse_out ? rho_out : nullptr);
+        if (e) {
+            if (first) L->have_state = false;     // neither copy holds a state now
+            return hip_fail(e, "tiled kernel");
+        }
+        L->have_state = true;
         L->cur ^= 1;
         done += s;
     }
     L->step = n_steps;
-    return KSLB_OK;
+    return fuse_out ? KSLB_OK : kslb_read_rho(L, rho_out, 1);
 }
 
 kslb_status kslb_advance_noalloc(kslb_lattice* L, int64_t n_steps) { return advance_impl(L, n_steps, true); }

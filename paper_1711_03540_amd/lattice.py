@@ -149,7 +149,8 @@ class Lattice:
     def solve(self, rho0, steps: int, out=None):
         """init_rho(rho0) + advance(steps) + read_rho(out) as one enqueued call
         (kslb_solve: fused into the first and last launches of the tiled
-        kernel); rho0 a float64 device tensor of n sites.  Returns out."""
+        kernel); rho0 a float64 device tensor of n sites; out may be rho0
+        itself.  Returns out."""
         import torch
         if not (isinstance(rho0, torch.Tensor) and rho0.is_cuda):
             raise TypeError("solve takes the initial density as a device tensor")

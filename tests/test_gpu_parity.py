@@ -416,7 +416,8 @@ def test_ensemble_graph_replays_match_eager_launches():
     (7, 12345, "fp64", "tiled", 0, 1), (7, 12345, "fp64", "tiled", 0, 80), (7, 12345, "fp64", "tiled", 0, 81),
     (7, 12345, "fp64", "tiled", 0, 250), (7, 70001, "fp64", "tiled", 7, 30), (5, 7001, "fp64", "tiled", 0, 150),
     (7, 9000, "fp32", "tiled", 0, 100), (5, 9000, "split", "tiled", 0, 100), (7, 9000, "rho", "tiled", 0, 100),
-    (7, 4096, "fp64", "auto", 0, 100), (7, 5000, "fp64", "plain", 0, 20), (7, 12345, "fp64", "tiled", 0, 0)])
+    (7, 4096, "fp64", "auto", 0, 100), (7, 5000, "fp64", "plain", 0, 20), (7, 12345, "fp64", "tiled", 0, 0),
+    (7, 1, "fp64", "tiled", 0, 5), (7, 100, "fp64", "tiled", 0, 90), (5, 301, "rho", "tiled", 0, 200)])
 def test_solve_matches_separate_calls(q, n, prec, kernel, steps_per_launch, steps):
     # kslb_solve (initialisation and readout fused into the first and last
     # tiled launches) against init_rho + advance + read_rho: density, stored
@@ -450,6 +451,14 @@ def test_solve_matches_separate_calls(q, n, prec, kernel, steps_per_launch, step
     torch.cuda.synchronize()
     assert torch.equal(out[1:], want)
     assert np.array_equal(c.f(), state)
+    # in place (the density written over rho0), in one launch or several
+    d = make(q, n, prec, kernel, tau=tau, steps_per_launch=steps_per_launch)
+    r = rho0.clone()
+    assert d.solve(r, steps, out=r) is r
+    torch.cuda.synchronize()
+    assert torch.equal(r, want)
+    assert np.array_equal(d.f(), state)
+    assert d.step == steps
 
 
 def test_ensemble_graphs_replaced_without_waiting():

@@ -71,7 +71,7 @@ class Ensemble:
         return {"sites_per_lane": b.value, "max_segments": m.value, "steps_per_chunk": c.value}
 
     def set_tiling(self, sites_per_lane: int = 0, max_segments: int = 0, steps_per_chunk: int = 0) -> "Ensemble":
-        """Sites per lane (4/8; 12 with FP64 and 16 with the rho-only storage throughout),
+        """Sites per lane (4/8; 10 with FP32, 12 with FP64 and 16 with the rho-only storage throughout),
         instance tiles per workgroup window, steps per launch (0 = keep)."""
         call("kslb_ensemble_set_tiling", self._h, sites_per_lane, max_segments, steps_per_chunk)
         self.chunk = steps_per_chunk or getattr(self, "chunk", 64)

@@ -795,6 +795,30 @@ def test_fixed_ends_table3_parity(q, dX):
     assert G < 1e-3
 
 
+@pytest.mark.parametrize("kernel", ["plain", "span"])
+def test_solve_with_fixed_ends(kernel):
+    # kslb_solve on the Table 3 problem (fixed ends run unfused): the result of
+    # init_rho + advance + read_rho bitwise, also written over its input
+    import torch
+    from paper_1711_03540_amd.inputs import table3_ends, table3_profile, table3_sites
+    say("case solve fixed ends %s" % kernel)
+    dX, q = 0.1, 7
+    dT, tau, steps = dX ** 4 / 100, 1.3, 700
+    n = table3_sites(dX)
+    lo, hi = table3_ends()
+    rho0 = torch.tensor(table3_profile(np.arange(n) * dX, 0.0), device="cuda")
+    mk = lambda: Lattice(n, q, "fp64").set_physical(dX, dT, tau).set_kernel(kernel).set_fixed_ends(lo, hi)
+    a, b, c = mk(), mk(), mk()
+    got = a.solve(rho0, steps)
+    want = b.init_rho(rho0).advance(steps).read_rho()
+    r = rho0.clone()
+    c.solve(r, steps, out=r)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want) and torch.equal(r, want)
+    assert np.array_equal(a.f(), b.f()) and a.step == b.step == c.step == steps
+    assert float(got[0]) == pytest.approx(lo, abs=1e-14) and float(got[-1]) == pytest.approx(hi, abs=1e-14)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "split", "rho"])
 def test_fixed_ends_reduced_storage_bitwise(prec):
     # the fixed-end boundary in the reduced storage modes: the plain and

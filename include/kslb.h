@@ -108,8 +108,9 @@ enum { KSLB_GUARD_REFUSE = 0, KSLB_GUARD_RAISE_TAU = 1, KSLB_GUARD_OFF = 2 };
  *              windows of 256 lanes x B sites (B = 12 for FP64, 10 for FP32,
  *              8 for split, 32 for the rho-only state) each keep
  *              W - 2 max|c| s sites after s steps (by default 80 for D1Q7
- *              FP64, 112 for D1Q5 FP64, 64 for FP32 and the rho-only D1Q7
- *              state, 128 for the rho-only D1Q5 state).
+ *              FP64, 112 for D1Q5 FP64, 48 for FP32, 32 for D1Q7 and 40
+ *              for D1Q5 split, 64 for the rho-only D1Q7 state, 128 for the
+ *              rho-only D1Q5 state).
  *   SPAN     : thousands of steps per launch; single-wave workgroups each
  *              hold W = 64 B sites in registers (B = 2 sites per lane for
  *              the population states, max|c| for the rho-only state): their
@@ -353,7 +354,8 @@ kslb_status kslb_ensemble_set_physical(kslb_ensemble* ens, int idx, double dX, d
  *                   (1 = one tile per workgroup);
  *   steps_per_chunk steps per launch, with 2 max|c| steps < the window.
  * Defaults: 8 sites (12 when every instance has FP64 storage, 10 when every
- * instance has FP32 storage), 16 segments, 64 steps.                       */
+ * instance has FP32 storage), 16 segments, 64 steps (48 when every instance
+ * has FP32 storage, 40 when any has split storage).                        */
 kslb_status kslb_ensemble_set_tiling(kslb_ensemble* ens, int sites_per_lane, int max_segments,
                                      int steps_per_chunk);
 

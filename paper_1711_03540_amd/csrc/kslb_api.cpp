@@ -255,19 +255,15 @@ constexpr int kSpanAutoMinSteps = 12;
 // N = 2^24 put the optimum at 80 for D1Q7 FP64 (1063 GLUPS; 1060 at 64,
 // 1063 at 96), 112 for D1Q5 FP64 (1447; 1396 at 64), 64 for the rho-only
 // D1Q7 state (1931; 1925 at 96, 1913 at 128), 128 for rho-only D1Q5 (2371;
-// 2325 at 64), 64 for FP32 (D1Q7 888-913, within 3 % of 48 and 80, whose
-// order changes from device to device; D1Q5 1275, 1214 at 96) and 40 for
-// D1Q7 split; other combinations keep 2 H s <= W / 8.
+// 2325 at 64), 48 for FP32 (D1Q7 975-981, 931 at 64, 912 at 80; D1Q5
+// 1302-1311, 1293 at 64) and for split 32 on D1Q7 (563, 555 at 40, 531 at
+// 64) and 40 on D1Q5 (817, 792 at 64).
 int default_tile_steps(int q, int prec)
 {
     if (prec == kFP64) return q == 7 ? 80 : 112;
     if (prec == kRHO) return q == 7 ? 64 : 128;
-    if (prec == kFP32) return 64;
-    if (q == 7) return 40;
-    const int W = tile_lanes() * tile_sites_per_lane(prec);
-    int s = W / (16 * halo(q));
-    s -= s % 8;
-    return std::max(8, s);
+    if (prec == kFP32) return 48;
+    return q == 7 ? 32 : 40;
 }
 
 kslb_status check_lat(const kslb_lattice* L)
@@ -1586,9 +1582,14 @@ kslb_status kslb_ensemble_create(kslb_ensemble** out, int count, const int64_t* 
     E->prec.assign(precision, precision + count);
     // FP64 throughout: 12 sites per lane by default (3072-site windows: 862
     // against 796 GLUPS for 4096 D1Q7 instances of 512 to 8192 sites); FP32
-    // throughout: 10 (775 against 742 at 64-step chunks, 807 against 770 at 48)
+    // throughout: 10 sites and 48-step chunks (826-830 GLUPS, 783 at 64;
+    // 799 at 8 sites); split storage present: 40-step chunks (485, 456 at 64)
     if (std::all_of(precision, precision + count, [](int p) { return p == kFP64; })) E->B = 12;
-    if (std::all_of(precision, precision + count, [](int p) { return p == kFP32; })) E->B = 10;
+    if (std::all_of(precision, precision + count, [](int p) { return p == kFP32; })) {
+        E->B = 10;
+        E->chunk = 48;
+    }
+    if (std::any_of(precision, precision + count, [](int p) { return p == kSPLIT; })) E->chunk = 40;
     E->device = dev;
     E->buf = (char*)dev_buf;
     E->bytes = buf_bytes;

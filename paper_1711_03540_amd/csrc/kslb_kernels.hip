@@ -109,7 +109,6 @@ __device__ __forceinline__ void eq_all(double rho, const double* e, const double
 }
 
 typedef double d2v __attribute__((ext_vector_type(2)));
-typedef float f4v __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- precision policies
 // A state copy stores population i of site j at element i * p + j, with the
@@ -247,18 +246,17 @@ struct Pol<Q, kFP32> {
         unroll<Q>([&](auto I) { __builtin_nontemporal_store(x.s[I], reinterpret_cast<float*>(st) + I * p + j); });
     }
 
-    // B consecutive sites from j0 (j0 and p multiples of 4)
+    // B consecutive sites from j0 (B and j0 even): 8-byte accesses, two sites
+    // of one population each
     template <int B>
     __device__ static __forceinline__ void load_vec(const char* st, int64_t p, int64_t j0, Site (&x)[B])
     {
         unroll<Q>([&](auto I) {
-            const f4v* src = reinterpret_cast<const f4v*>(reinterpret_cast<const float*>(st) + I * p + j0);
-            unroll<B / 4>([&](auto K) {
-                const f4v v = src[K];
-                x[4 * K].s[I] = v.x;
-                x[4 * K + 1].s[I] = v.y;
-                x[4 * K + 2].s[I] = v.z;
-                x[4 * K + 3].s[I] = v.w;
+            const uint64_t* src = reinterpret_cast<const uint64_t*>(reinterpret_cast<const float*>(st) + I * p + j0);
+            unroll<B / 2>([&](auto K) {
+                const uint64_t v = src[K];
+                x[2 * K].s[I] = __uint_as_float((unsigned)v);
+                x[2 * K + 1].s[I] = __uint_as_float((unsigned)(v >> 32));
             });
         });
     }
@@ -267,14 +265,10 @@ struct Pol<Q, kFP32> {
     __device__ static __forceinline__ void store_vec(char* st, int64_t p, int64_t j0, const Site (&x)[B])
     {
         unroll<Q>([&](auto I) {
-            f4v* dst = reinterpret_cast<f4v*>(reinterpret_cast<float*>(st) + I * p + j0);
-            unroll<B / 4>([&](auto K) {
-                f4v v;
-                v.x = x[4 * K].s[I];
-                v.y = x[4 * K + 1].s[I];
-                v.z = x[4 * K + 2].s[I];
-                v.w = x[4 * K + 3].s[I];
-                dst[K] = v;
+            uint64_t* dst = reinterpret_cast<uint64_t*>(reinterpret_cast<float*>(st) + I * p + j0);
+            unroll<B / 2>([&](auto K) {
+                dst[K] = (uint64_t)__float_as_uint(x[2 * K].s[I]) |
+                         ((uint64_t)__float_as_uint(x[2 * K + 1].s[I]) << 32);
             });
         });
     }
@@ -372,7 +366,8 @@ struct Pol<Q, kSPLIT> {
         unroll<Q>([&](auto I) { __builtin_nontemporal_store(x.n[I], nb + I * p + j); });
     }
 
-    // B consecutive sites from j0 (j0 and p multiples of 4)
+    // B consecutive sites from j0 (B and j0 even): 16-byte density and
+    // 8-byte non-equilibrium accesses
     template <int B>
     __device__ static __forceinline__ void load_vec(const char* st, int64_t p, int64_t j0, Site (&x)[B])
     {
@@ -383,13 +378,11 @@ struct Pol<Q, kSPLIT> {
             x[2 * K + 1].rho = v.y;
         });
         unroll<Q>([&](auto I) {
-            const f4v* src = reinterpret_cast<const f4v*>(nbase(st, p) + I * p + j0);
-            unroll<B / 4>([&](auto K) {
-                const f4v v = src[K];
-                x[4 * K].n[I] = v.x;
-                x[4 * K + 1].n[I] = v.y;
-                x[4 * K + 2].n[I] = v.z;
-                x[4 * K + 3].n[I] = v.w;
+            const uint64_t* src = reinterpret_cast<const uint64_t*>(nbase(st, p) + I * p + j0);
+            unroll<B / 2>([&](auto K) {
+                const uint64_t v = src[K];
+                x[2 * K].n[I] = __uint_as_float((unsigned)v);
+                x[2 * K + 1].n[I] = __uint_as_float((unsigned)(v >> 32));
             });
         });
     }
@@ -405,14 +398,10 @@ struct Pol<Q, kSPLIT> {
             r[K] = v;
         });
         unroll<Q>([&](auto I) {
-            f4v* dst = reinterpret_cast<f4v*>(const_cast<float*>(nbase(st, p)) + I * p + j0);
-            unroll<B / 4>([&](auto K) {
-                f4v v;
-                v.x = x[4 * K].n[I];
-                v.y = x[4 * K + 1].n[I];
-                v.z = x[4 * K + 2].n[I];
-                v.w = x[4 * K + 3].n[I];
-                dst[K] = v;
+            uint64_t* dst = reinterpret_cast<uint64_t*>(const_cast<float*>(nbase(st, p)) + I * p + j0);
+            unroll<B / 2>([&](auto K) {
+                dst[K] = (uint64_t)__float_as_uint(x[2 * K].n[I]) |
+                         ((uint64_t)__float_as_uint(x[2 * K + 1].n[I]) << 32);
             });
         });
     }
@@ -910,11 +899,6 @@ struct Engine {
 
 constexpr int kRingLD = 512;
 
-// 16-byte global loads/stores of a lane's B sites (FP64 only: with the mixed
-// rho/n site record of SPLIT and the 28-byte FP32 record the compiler keeps
-// part of the register block in scratch memory).
-template <int P>
-constexpr bool kVecIO = (P == kFP64 || P == kRHO);
 constexpr int kTileLD = 256;
 
 // Whole periodic lattice of n = B * L sites in one workgroup of L lanes,
@@ -929,17 +913,11 @@ __global__ __launch_bounds__(kRingLD) void k_ring(const char* __restrict__ src, 
     const int lane = threadIdx.x;
     const bool active = lane < L;
     typename E::Site x[B];
-    if (active) {
-        if constexpr (kVecIO<P>) E::PL::template load_vec<B>(src, p, (int64_t)lane * B, x);
-        else unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, p, (int64_t)lane * B + Bi); });
-    }
+    if (active) E::PL::template load_vec<B>(src, p, (int64_t)lane * B, x);
     const int left = lane == 0 ? L - 1 : lane - 1;
     const int right = lane + 1 >= L ? 0 : lane + 1;
     E::run(x, steps, xch, lane, left, right, active, cf);
-    if (active) {
-        if constexpr (kVecIO<P>) E::PL::template store_vec<B>(dst, p, (int64_t)lane * B, x);
-        else unroll<B>([&](auto Bi) { E::PL::store(dst, p, (int64_t)lane * B + Bi, x[Bi]); });
-    }
+    if (active) E::PL::template store_vec<B>(dst, p, (int64_t)lane * B, x);
 }
 
 // One lane's part of a halo-widened window.  The lane holds sites j0 .. j0+B-1
@@ -964,8 +942,11 @@ __device__ __forceinline__ void window_lane(const char* __restrict__ src, char* 
     constexpr int L = kTileLD;
     const int lane = threadIdx.x;
     typename E::Site x[B];
-    // the 16-byte accesses need an even first site (rows are 256-byte aligned
-    // and their pitch is a multiple of 64 sites)
+    // the vector accesses (16 bytes on double rows, 8 on float rows) need an
+    // even first site (rows are 256-byte aligned and their pitch is a
+    // multiple of 64 sites).  With one 4-byte access per site, the write-back
+    // of float rows (lanes 40 bytes apart) reached memory as several times
+    // its bytes.
     const bool inside = j0 >= 0 && j0 + B <= n;
     const bool even = (j0 & 1) == 0;
     if (rho0) {
@@ -979,7 +960,7 @@ __device__ __forceinline__ void window_lane(const char* __restrict__ src, char* 
         } else {
             unroll<B>([&](auto Bi) { x[Bi] = PL::equilibrium(rho0[wrap_site(j0 + Bi, n)], cf); });
         }
-    } else if (kVecIO<P> && inside && even) {
+    } else if (inside && even) {
         E::PL::template load_vec<B>(src, p, j0, x);
     } else if (inside) {
         unroll<B>([&](auto Bi) { x[Bi] = E::PL::load(src, p, j0 + Bi); });
@@ -989,7 +970,7 @@ __device__ __forceinline__ void window_lane(const char* __restrict__ src, char* 
     const int left = lane == 0 ? L - 1 : lane - 1;
     const int right = lane + 1 == L ? 0 : lane + 1;
     E::run(x, s, xch, lane, left, right, true, cf);
-    if (kVecIO<P> && kl0 >= k_lo && kl0 + B <= k_lo + valid && inside && even) {
+    if (kl0 >= k_lo && kl0 + B <= k_lo + valid && inside && even) {
         E::PL::template store_vec<B>(dst, p, j0, x);
     } else {
         unroll<B>([&](auto Bi) {

@@ -502,7 +502,7 @@ def test_ensemble_packing_and_chunking_bitwise(q, prec):
         tilings += [(10, 16, 32), (10, 1, 41), (10, 5, 80)]
     default = Ensemble(sizes, q, prec).tiling()
     assert default == {"sites_per_lane": {"fp64": 12, "fp32": 10}.get(prec, 8), "max_segments": 16,
-                       "steps_per_chunk": 64}
+                       "steps_per_chunk": {"fp32": 48, "split": 40}.get(prec, 64)}
     for B, segs, chunk in tilings:
         ens = Ensemble(sizes, q, prec).set_physical(dX, dT, 1.1).set_tiling(B, segs, chunk)
         assert ens.tiling() == {"sites_per_lane": B, "max_segments": segs, "steps_per_chunk": chunk}
@@ -959,7 +959,7 @@ def test_resolved_kernel_and_launch_shape():
     assert k["kernel"] == "span" and k["steps_per_launch"] % k["exchange_steps"] == 0
     assert k["exchange_steps"] >= 1 and k["workgroups"] >= 2 and k["lanes"] == 64
     n = 100_000
-    for prec, sites, s_default in (("fp64", 12, 80), ("rho", 32, 64), ("fp32", 10, 64)):
+    for prec, sites, s_default in (("fp64", 12, 80), ("rho", 32, 64), ("fp32", 10, 48), ("split", 8, 32)):
         lat = Lattice(n, 7, prec).set_physical(0.3, 2e-4, 1.0)
         k = lat.kernel()
         s = k["steps_per_launch"]

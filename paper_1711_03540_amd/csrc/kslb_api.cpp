@@ -250,7 +250,7 @@ constexpr int64_t kSpanAutoMaxSites = 65536;
 constexpr int kSpanAutoMinSteps = 12;
 
 // Steps per tiled launch, even so that every lane's first site is even (its
-// 16-byte accesses).  Longer launches re-read the state less often but
+// vector accesses).  Longer launches re-read the state less often but
 // recompute a wider halo (2 H s of the window's W sites).  Sweeps of s on
 // N = 2^24 put the optimum at 80 for D1Q7 FP64 (1063 GLUPS; 1060 at 64,
 // 1063 at 96), 112 for D1Q5 FP64 (1447; 1396 at 64), 64 for the rho-only

@@ -628,7 +628,8 @@ def run_serve(rate, requests, budget_gib=4.0, chunk=0, round_steps=0, serve_fp32
     t_issue = sum(valu_per_site_update(q) * v for q, v in su.items()) / (N_SIMD * 16 * CLOCK_GHZ * 1e9)
     out = {"workload": "serve_%d_requests" % len(reqs), "rate_per_s": rate,
            "fp32_requests_storage": serve_fp32, "budget_bytes": srv.arena.size,
-           "offered_glups": float(sum(r.n * r.steps for r in reqs) / reqs[-1].arrival / 1e9)}
+           "offered_glups": float(sum(r.n * r.steps for r in reqs) / reqs[-1].arrival / 1e9),
+           "chunk_and_round_steps": {"q%d_%s" % k: [p.chunk, srv.round_steps] for k, p in srv.pools.items()}}
     out.update(st.summary())
     out["value"] = out["achieved_glups"]
     out["unit"] = "GLUPS"
